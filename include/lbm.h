@@ -1,0 +1,182 @@
+/*
+ * lbm.h -- C ABI of the MI355X constraint-penalization lattice Boltzmann
+ * library (liblbmpen.so), after Millet & Liberge, "Constraint Penalization
+ * Method in the Lattice Boltzmann Method (LBM) for Fluid-Structure
+ * Interaction", arXiv 2511.01629.
+ *
+ * One context holds one fictitious-domain simulation on one GPU: a single
+ * D2Q9 (or D3Q19) lattice covers fluid and solids alike (sec. 2.1); the solids
+ * are the nodes marked by the indicator chi of each rigid particle (eq. 9).
+ * lbm_step advances the coupled system by whole time steps:
+ *
+ *   1. pull streaming with halfway bounce-back walls and periodic axes, then
+ *      the velocity-based BGK collision (sec. 2.2, eq. 10 and 13) with the
+ *      Guo force (eq. 14) and, on solid nodes, the penalization source
+ *      S = w/(2 cs^4) (alpha Pi^neq):(c c - cs^2 I) (eq. 17);
+ *   2. per-particle momentum sums U = (1/M) sum u, I omega = sum r x u
+ *      (sec. 2.4, eq. 22a-b);
+ *   3. Algorithm 1 (sec. 2.4): K-sub-step prediction-correction of the
+ *      centres with the repulsive collision forces of sec. 2.3 (eq. 19-21),
+ *      the collision acceleration A^{n+1}, and the new indicator.
+ *
+ * Conventions shared by every call:
+ *   - Every function returns an int status: LBM_OK (0) or a negative code
+ *     below.  Nothing aborts or throws across the ABI.  lbm_last_error gives
+ *     a message for the last failing call on a context.
+ *   - Pointers named `host_*` or documented as host memory are read or written
+ *     by the CPU; the library never keeps them after the call returns.
+ *   - Lattice units: node (i, j, k) sits at (i, j, k); a wall axis has walls at
+ *     -0.5 and n - 0.5; a periodic axis wraps.
+ *   - Work is queued on the context's HIP stream (lbm_config.stream, or the
+ *     null stream).  lbm_step returns once queued; every lbm_get_* call and
+ *     lbm_sync wait for the stream.
+ *   - One context is used by one host thread at a time.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx; /* opaque, owned by the library */
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,    /* invalid argument; the context is unchanged            */
+    LBM_ENOMEM = -2,    /* device allocation failed, or the workspace is too small */
+    LBM_EDEVICE = -3,   /* a HIP call failed                                      */
+    LBM_ESTATE = -4,    /* call out of order (e.g. no particles set yet)          */
+    LBM_EUNSTABLE = -5, /* a velocity became non-finite or |u| > 0.3              */
+    LBM_EDOMAIN = -6    /* a particle left the box or lost all its nodes          */
+};
+
+enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
+/* population storage: arithmetic is FP64 for LBM_F64 and FP32 otherwise; the
+ * particle sums and Algorithm 1 are FP64 in every mode */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_BF16 = 3 };
+enum { LBM_DISK = 0, LBM_ELLIPSE = 1, LBM_SPHERE = 2 };
+
+typedef struct {
+    int32_t lattice;     /* LBM_D2Q9 or LBM_D3Q19                                   */
+    int32_t storage;     /* LBM_F64 .. LBM_BF16                                      */
+    int32_t n[3];        /* nodes per axis; n[2] is ignored (1) for D2Q9             */
+    int32_t periodic[3]; /* 1: periodic axis, 0: halfway bounce-back walls           */
+    double tau;          /* BGK relaxation time, > 1/2 (sec. 2.2)                     */
+    double alpha;        /* penalization parameter of eq. (17); <= 0 selects 1/tau,
+                            the value used throughout sec. 3; must be <= 1/tau        */
+    double rho_f;        /* fluid density (1 in lattice units)                        */
+    double g[3];         /* gravity acceleration (lattice units)                      */
+    double u0[3], p0;    /* initial uniform velocity and pressure (f = f^eq(p0, u0))  */
+    double eps_p, eps_w; /* collision stiffness, particle-particle and wall (sec. 2.3) */
+    double delta;        /* collision range delta (sec. 2.3)                           */
+    int32_t K;           /* Algorithm 1 sub-steps (>= 1)                               */
+    int32_t collision_form; /* 0: unit direction, C_i = (rho_s,i - rho_f)|g| V_i;
+                               1: the printed form (X_i - X_j), C_i = (rho_s,i - rho_f)|g| */
+    int32_t gravity_form;   /* 0: a = (1 - rho_f/rho_s) g on solids; 1: (rho_s/rho_f - 1) g */
+    double fluid_accel[3];  /* uniform acceleration on fluid nodes (0 in the paper's cases) */
+    int32_t penalize_all;   /* 1: apply the penalization source on every node (testing)   */
+    int32_t device;         /* HIP device ordinal                                          */
+    void *stream;           /* hipStream_t to queue on, or NULL for the null stream         */
+    void *workspace;        /* optional caller-owned device buffer of lbm_workspace_size
+                               bytes (e.g. from torch); NULL: the library allocates         */
+    size_t workspace_bytes; /* size of `workspace`                                          */
+    int32_t max_particles;  /* capacity for lbm_set_particles (sizes the workspace)         */
+} lbm_config;
+
+typedef struct {
+    int32_t shape;     /* LBM_DISK, LBM_ELLIPSE (2D), LBM_SPHERE (3D)                    */
+    double rho_s;      /* solid density, > 0                                             */
+    double a, b;       /* radius (disk/sphere: a); ellipse semi-axes a >= b >= 1          */
+    double x[3];       /* centre X (lattice units)                                       */
+    double theta;      /* 2D orientation of the major axis from +x (radians)              */
+    /* outputs of lbm_get_particles (ignored by lbm_set_particles) */
+    double U[3], omega[3];           /* U^n, omega^n measured on the current state       */
+    double U_prev[3], omega_prev[3]; /* U^{n-1}, omega^{n-1} held for Algorithm 1          */
+    double A[3];                     /* collision acceleration A^n of Algorithm 1          */
+    int32_t n_nodes;                 /* |Omega_i|, nodes owned now                          */
+} lbm_particle;
+
+/* Bytes of device memory a context with this configuration needs (for a
+ * caller-provided workspace).  Host pointers only. */
+int lbm_workspace_size(const lbm_config *cfg, size_t *bytes);
+
+/* Validate cfg, allocate (or carve the workspace), and initialise every node
+ * to f^eq(p0, u0) (eq. 13).  EINVAL: tau <= 1/2, alpha > 1/tau, n <= 0,
+ * unknown lattice/storage, max_particles outside [0, 65534].  *out receives
+ * the context; it is freed by lbm_destroy. */
+int lbm_create(const lbm_config *cfg, lbm_ctx **out);
+
+/* Free the context and everything it allocated (never the caller's workspace). */
+int lbm_destroy(lbm_ctx *ctx);
+
+/* Copy n particles in (host array), rasterise the indicator (eq. 9: closed
+ * set, the lowest index owns a shared node, FP64 tests with no contraction,
+ * minimum image on periodic axes), measure U^0 and omega^0 on the current
+ * populations (eq. 22a-b), set U^{-1} = U^0, omega^{-1} = omega^0, A = 0.
+ * EINVAL: n > max_particles, a bad shape/size, a body crossing a wall, a
+ * radius too large for a periodic axis (a + 2 >= n/2), or a body with no node. */
+int lbm_set_particles(lbm_ctx *ctx, const lbm_particle *host_particles, int32_t n);
+
+/* Queue nsteps >= 0 full time steps (stream-collide-penalize, sums,
+ * Algorithm 1, re-rasterisation).  With no particles set, only the lattice
+ * update runs (pure fluid). */
+int lbm_step(lbm_ctx *ctx, int64_t nsteps);
+
+/* As lbm_step, and write a per-step record of every particle into host_rec:
+ * nsteps x n x 14 doubles, per particle X[3] theta U[3] omega[3] A[3] N of
+ * step n (values before that step's update).  Waits for the stream. */
+int lbm_step_record(lbm_ctx *ctx, int64_t nsteps, double *host_rec);
+
+/* Wait for queued work; report LBM_EUNSTABLE / LBM_EDOMAIN if the device
+ * sentinel tripped since the context was created. */
+int lbm_sync(lbm_ctx *ctx);
+
+/* Macroscopic fields of the current step (eq. 15a-b), host memory, FP64,
+ * node-major: u[N][d] (d = 2 or 3), p[N], owner[N] (-1 = fluid).  Any pointer
+ * may be NULL.  N = n[0] n[1] n[2], x fastest. */
+int lbm_get_fields(lbm_ctx *ctx, double *host_u, double *host_p, int32_t *host_owner);
+
+/* Populations f^n of the current step (after streaming, before collision),
+ * host memory, FP64, direction-major [Q][N]. */
+int lbm_get_populations(lbm_ctx *ctx, double *host_f);
+
+/* Replace the populations by host_f ([Q][N] FP64, rounded to the storage
+ * type).  Particle state is unchanged; call lbm_set_particles afterwards to
+ * re-measure U^0. */
+int lbm_set_populations(lbm_ctx *ctx, const double *host_f);
+
+/* Current particle state into host_particles[0..n): centre, orientation, U^n
+ * and omega^n measured now, U^{n-1}, omega^{n-1}, A^n, node count. */
+int lbm_get_particles(lbm_ctx *ctx, lbm_particle *host_particles, int32_t n);
+
+/* Per-kernel timing with HIP events (measurement aid).  While enabled,
+ * every kernel lbm_step queues is bracketed by events, and lbm_step waits
+ * for the stream before returning.  lbm_profile_read returns, per kernel
+ * class, the summed duration in milliseconds and the launch count since the
+ * last reset (reset = 1 clears them afterwards).  Classes, in order:
+ * 0 stream-collide-penalize, 1 momentum sums, 2 Algorithm 1,
+ * 3 indicator clear, 4 indicator set.  host arrays of LBM_NKERNELS. */
+#define LBM_NKERNELS 5
+int lbm_profile(lbm_ctx *ctx, int32_t enable);
+int lbm_profile_read(lbm_ctx *ctx, double *host_ms, int64_t *host_count, int32_t reset);
+
+/* Plain device-to-device copy of `bytes` bytes with a streaming kernel of the
+ * library (16-byte vector loads/stores), queued on `stream` (hipStream_t or
+ * NULL).  dst and src are device pointers, 16-byte aligned, not overlapping.
+ * Used as the achievable-bandwidth reference of the measurements. */
+int lbm_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+/* Number of completed steps. */
+int lbm_get_step(const lbm_ctx *ctx, int64_t *step);
+
+/* Message for the last failing call on ctx (never NULL). */
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

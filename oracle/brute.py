@@ -227,17 +227,21 @@ def step(state):
 
     Ub = [[(meas[i][1][k] + pt["Uprev"][k]) / 2 for k in range(3)] for i, pt in enumerate(parts)]
     Y = [list(pt["X"]) for pt in parts]
+    # X^{n+1} - X^n - U_bar is the sum of the correction displacements
+    disp = [[0.0, 0.0, 0.0] for _ in parts]
     for _ in range(K):
         Ys = [[Y[i][k] + (Ub[i][k] / K if k < d else 0.0) for k in range(3)] for i in range(len(parts))]
         F0 = [force(i, Y) for i in range(len(parts))]
         F1 = [force(i, Ys) for i in range(len(parts))]
-        Y = [[Ys[i][k] + 1 / (2 * parts[i]["rho_s"] * meas[i][0]) / K ** 2 * (F0[i][k] + F1[i][k]) / 2
-              if k < d else 0.0 for k in range(3)] for i in range(len(parts))]
+        corr = [[1 / (2 * parts[i]["rho_s"] * meas[i][0]) / K ** 2 * (F0[i][k] + F1[i][k]) / 2 if k < d else 0.0
+                 for k in range(3)] for i in range(len(parts))]
+        Y = [[Ys[i][k] + corr[i][k] for k in range(3)] for i in range(len(parts))]
+        disp = [[disp[i][k] + corr[i][k] for k in range(3)] for i in range(len(parts))]
     newparts = []
     for i, pt in enumerate(parts):
         q = dict(pt)
         X = list(Y[i])
-        q["A"] = [2 * (X[k] - pt["X"][k] - Ub[i][k]) if k < d else 0.0 for k in range(3)]
+        q["A"] = [2 * disp[i][k] for k in range(3)]
         for k in range(d):
             if per[k]:
                 if X[k] >= state["n"][k]:

@@ -537,6 +537,7 @@ static void rigid_update(ora_ctx *c)
     real(*Ub)[3] = calloc((size_t)np, sizeof(*Ub));
     real(*F0)[3] = calloc((size_t)np, sizeof(*F0));
     real(*F1)[3] = calloc((size_t)np, sizeof(*F1));
+    real(*D)[3] = calloc((size_t)np, sizeof(*D)); /* summed corrections */
     for (int i = 0; i < np; i++)
         for (int k = 0; k < 3; k++) {
             Y[i][k] = c->p[i].X[k];
@@ -551,14 +552,20 @@ static void rigid_update(ora_ctx *c)
         }
         for (int i = 0; i < np; i++) {
             real M = c->p[i].rho_s * (double)c->p[i].N;
-            for (int k = 0; k < d; k++) /* correction */
-                Y[i][k] = Ys[i][k] + 1.0 / (2.0 * M) * (1.0 / ((double)K * K)) * (F0[i][k] + F1[i][k]) / 2.0;
+            for (int k = 0; k < d; k++) { /* correction */
+                real corr = 1.0 / (2.0 * M) * (1.0 / ((double)K * K)) * (F0[i][k] + F1[i][k]) / 2.0;
+                Y[i][k] = Ys[i][k] + corr;
+                D[i][k] += corr;
+            }
         }
     }
     for (int i = 0; i < np; i++) {
         particle_t *P = &c->p[i];
         for (int k = 0; k < d; k++) {
-            P->A[k] = 2.0 * (Y[i][k] - P->X[k] - Ub[i][k]);
+            /* A^{n+1} = 2 (X^{n+1} - X^n - U_bar): the bracket equals the sum of
+             * the K correction displacements, taken directly so that no two
+             * absolute positions are subtracted */
+            P->A[k] = 2.0 * D[i][k];
             P->X[k] = Y[i][k];
             if (c->periodic[k]) {
                 if (RE(P->X[k]) >= c->n[k]) P->X[k] -= c->n[k];
@@ -576,6 +583,7 @@ static void rigid_update(ora_ctx *c)
     free(Ub);
     free(F0);
     free(F1);
+    free(D);
 }
 
 /* ------------------------------------------------------------- public API */

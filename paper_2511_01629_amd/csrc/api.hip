@@ -1,0 +1,605 @@
+// api.hip -- host side of the C ABI declared in include/lbm.h.
+//
+// The context owns (or carves from the caller's workspace) every device
+// buffer: two population buffers [Q][N] in the storage type, the uint16
+// owner map, the solid-node velocity [d][N] (FP64), a staging area of 4N
+// doubles for transfers, device flags and the particle arrays.  A step queues
+// five kernels on the context stream: the fused stream-collide-penalize
+// update, the per-particle sums, Algorithm 1, the clear of the old scan boxes
+// and the rasterisation of the new ones.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "ctx.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int PART_DOUBLES = 3 * 7 + 4 + 3 + 16 + 3 * 5; // X theta U W Uprev Wprev A, rho a b C, acc, sums, Y Ys Y2 Ub Dc
+constexpr double CS2 = 1.0 / 3.0;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+int storage_bytes(int s) { return s == LBM_F64 ? 8 : s == LBM_F32 ? 4 : 2; }
+
+struct Layout {
+    size_t f0, f1, owner, usol, staging, flags, pd, pf, pi, total;
+};
+
+Layout layout_for(const lbm_config *cfg, int Q, int d, int64_t N)
+{
+    Layout L;
+    size_t off = 0;
+    const size_t fbytes = align_up((size_t)Q * N * storage_bytes(cfg->storage));
+    const int cap = std::max(cfg->max_particles, 1);
+    L.f0 = off;
+    off += fbytes;
+    L.f1 = off;
+    off += fbytes;
+    L.owner = off;
+    off += align_up((size_t)((N + 1) / 2 * 2) * sizeof(uint16_t));
+    L.usol = off;
+    off += align_up((size_t)d * N * sizeof(double));
+    L.staging = off;
+    off += align_up((size_t)4 * N * sizeof(double));
+    L.flags = off;
+    off += ALIGN;
+    L.pd = off;
+    off += align_up((size_t)cap * PART_DOUBLES * sizeof(double));
+    L.pf = off;
+    off += align_up((size_t)cap * 3 * sizeof(float));
+    L.pi = off;
+    off += align_up((size_t)cap * 8 * sizeof(int32_t));
+    L.total = off;
+    return L;
+}
+
+int fail(lbm_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+int hipfail(lbm_ctx *c, hipError_t e, const char *what)
+{
+    return fail(c, LBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(c, expr)                                                                                                \
+    do {                                                                                                               \
+        hipError_t e_ = (expr);                                                                                        \
+        if (e_ != hipSuccess) return hipfail((c), e_, #expr);                                                          \
+    } while (0)
+
+int validate_cfg(const lbm_config *cfg, std::string &why, int &Q, int &d, int64_t &N)
+{
+    if (!cfg) return why = "cfg is NULL", LBM_EINVAL;
+    if (cfg->lattice != LBM_D2Q9 && cfg->lattice != LBM_D3Q19) return why = "unknown lattice", LBM_EINVAL;
+    if (cfg->storage < LBM_F64 || cfg->storage > LBM_BF16) return why = "unknown storage", LBM_EINVAL;
+    Q = cfg->lattice == LBM_D2Q9 ? 9 : 19;
+    d = cfg->lattice == LBM_D2Q9 ? 2 : 3;
+    int n[3] = {cfg->n[0], cfg->n[1], d == 3 ? cfg->n[2] : 1};
+    for (int k = 0; k < 3; ++k)
+        if (n[k] <= 0) return why = "lattice sizes must be positive", LBM_EINVAL;
+    N = (int64_t)n[0] * n[1] * n[2];
+    if ((int64_t)Q * N >= ((int64_t)1 << 31)) return why = "Q*N must stay below 2^31", LBM_EINVAL;
+    if (!(cfg->tau > 0.5)) return why = "tau must exceed 1/2", LBM_EINVAL;
+    if (cfg->alpha > 1.0 / cfg->tau * (1.0 + 1e-12)) return why = "alpha must not exceed 1/tau", LBM_EINVAL;
+    if (cfg->max_particles < 0 || cfg->max_particles > 65534) return why = "max_particles out of range", LBM_EINVAL;
+    if (cfg->K < 1) return why = "K must be >= 1", LBM_EINVAL;
+    if (!(cfg->rho_f > 0)) return why = "rho_f must be positive", LBM_EINVAL;
+    if (cfg->eps_p <= 0 || cfg->eps_w <= 0 || cfg->delta <= 0) return why = "eps_p, eps_w, delta must be positive", LBM_EINVAL;
+    return LBM_OK;
+}
+
+void feq_host(int lattice, double p, const double u[3], double *out)
+{
+    // eq. (13), evaluated once on the host for the uniform initial state
+    static const int c9[9][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
+                                 {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+    const int Q = lattice == LBM_D2Q9 ? 9 : 19;
+    const double w0 = lattice == LBM_D2Q9 ? 4.0 / 9 : 1.0 / 3;
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int q = 0; q < Q; ++q) {
+        int c[3];
+        if (lattice == LBM_D2Q9) {
+            for (int k = 0; k < 3; ++k) c[k] = c9[q][k];
+        } else {
+            for (int k = 0; k < 3; ++k) c[k] = 0;
+            if (q >= 1 && q <= 6) c[(q - 1) / 2] = (q % 2) ? 1 : -1;
+            if (q >= 7) {
+                static const int ax[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+                static const int sg[4][2] = {{1, 1}, {-1, -1}, {1, -1}, {-1, 1}};
+                const int e = q - 7;
+                c[ax[e / 4][0]] = sg[e % 4][0];
+                c[ax[e / 4][1]] = sg[e % 4][1];
+            }
+        }
+        const int s = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+        const double w = lattice == LBM_D2Q9 ? (s == 0 ? 4.0 / 9 : s == 1 ? 1.0 / 9 : 1.0 / 36)
+                                             : (s == 0 ? 1.0 / 3 : s == 1 ? 1.0 / 18 : 1.0 / 36);
+        const double cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+        out[q] = q == 0 ? -(1 - w0) * p / CS2 - w0 * uu / (2 * CS2)
+                        : w * (p / CS2 + cu / CS2 + cu * cu / (2 * CS2 * CS2) - uu / (2 * CS2));
+    }
+}
+
+void carve(lbm_ctx *c, const Layout &L)
+{
+    char *base = (char *)c->ws;
+    c->f[0] = base + L.f0;
+    c->f[1] = base + L.f1;
+    c->owner = (uint16_t *)(base + L.owner);
+    c->usol = (double *)(base + L.usol);
+    c->staging = (double *)(base + L.staging);
+    c->flags = (int32_t *)(base + L.flags);
+    const int cap = c->cap;
+    double *pd = (double *)(base + L.pd);
+    auto take = [&](int per) {
+        double *p = pd;
+        pd += (size_t)cap * per;
+        return p;
+    };
+    c->P.X = take(3);
+    c->P.theta = take(1);
+    c->P.U = take(3);
+    c->P.W = take(3);
+    c->P.Uprev = take(3);
+    c->P.Wprev = take(3);
+    c->P.A = take(3);
+    c->P.rho_s = take(1);
+    c->P.a = take(1);
+    c->P.b = take(1);
+    c->P.Cc = take(1);
+    c->P.acc_d = take(3);
+    c->P.sums = take(16);
+    c->P.Y = take(3);
+    c->P.Ys = take(3);
+    c->P.Y2 = take(3);
+    c->P.Ub = take(3);
+    c->P.Dc = take(3);
+    c->P.acc_f = (float *)(base + L.pf);
+    int32_t *pi = (int32_t *)(base + L.pi);
+    c->P.shape = pi;
+    c->P.N = pi + cap;
+    c->P.lo = pi + 2 * cap;
+    c->P.hi = pi + 5 * cap;
+}
+
+} // namespace
+
+extern "C" {
+
+int lbm_workspace_size(const lbm_config *cfg, size_t *bytes)
+{
+    std::string why;
+    int Q, d;
+    int64_t N;
+    if (!bytes) return LBM_EINVAL;
+    int rc = validate_cfg(cfg, why, Q, d, N);
+    if (rc) return rc;
+    *bytes = layout_for(cfg, Q, d, N).total;
+    return LBM_OK;
+}
+
+int lbm_create(const lbm_config *cfg, lbm_ctx **out)
+{
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    std::string why;
+    int Q, d;
+    int64_t N;
+    int rc = validate_cfg(cfg, why, Q, d, N);
+    if (rc) return rc;
+    lbm_ctx *c = new lbm_ctx();
+    c->cfg = *cfg;
+    c->Q = Q;
+    c->d = d;
+    c->geo.nx = cfg->n[0];
+    c->geo.ny = cfg->n[1];
+    c->geo.nz = d == 3 ? cfg->n[2] : 1;
+    c->cfg.n[2] = c->geo.nz;
+    c->geo.N = N;
+    c->geo.per_x = cfg->periodic[0] != 0;
+    c->geo.per_y = cfg->periodic[1] != 0;
+    c->geo.per_z = d == 3 && cfg->periodic[2] != 0;
+    c->sp.tau = cfg->tau;
+    c->sp.omega = 1.0 / cfg->tau;
+    c->sp.alpha = cfg->alpha > 0 ? cfg->alpha : 1.0 / cfg->tau;
+    c->sp.has_fluid_acc = 0;
+    for (int k = 0; k < 3; ++k) {
+        c->sp.fluid_acc[k] = k < d ? cfg->fluid_accel[k] : 0.0;
+        if (c->sp.fluid_acc[k] != 0.0) c->sp.has_fluid_acc = 1;
+    }
+    c->sp.penalize_all = cfg->penalize_all != 0;
+    c->rp.rho_f = cfg->rho_f;
+    for (int k = 0; k < 3; ++k) c->rp.g[k] = k < d ? cfg->g[k] : 0.0;
+    c->rp.gmag = sqrt(c->rp.g[0] * c->rp.g[0] + c->rp.g[1] * c->rp.g[1] + c->rp.g[2] * c->rp.g[2]);
+    c->rp.eps_p = cfg->eps_p;
+    c->rp.eps_w = cfg->eps_w;
+    c->rp.delta = cfg->delta;
+    c->rp.K = cfg->K;
+    c->rp.cform = cfg->collision_form;
+    c->rp.gform = cfg->gravity_form;
+    c->rp.np = 0;
+    c->rp.d = d;
+    c->device = cfg->device;
+    c->stream = (hipStream_t)cfg->stream;
+    c->cap = std::max(cfg->max_particles, 1);
+    c->np = 0;
+    c->step = 0;
+    c->cur = 0;
+    c->rec_dev = nullptr;
+    c->rec_cap = 0;
+    c->prof = 0;
+    for (int k = 0; k < LBM_NKERNELS; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_cnt[k] = 0;
+    }
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) {
+        delete c;
+        return LBM_EDEVICE;
+    }
+    const Layout L = layout_for(&c->cfg, Q, d, N);
+    if (cfg->workspace) {
+        if (cfg->workspace_bytes < L.total || ((uintptr_t)cfg->workspace % ALIGN) != 0) {
+            delete c;
+            return LBM_ENOMEM;
+        }
+        c->ws = cfg->workspace;
+        c->ws_bytes = cfg->workspace_bytes;
+        c->own_mem = false;
+    } else {
+        e = hipMalloc(&c->ws, L.total);
+        if (e != hipSuccess) {
+            delete c;
+            return LBM_ENOMEM;
+        }
+        c->ws_bytes = L.total;
+        c->own_mem = true;
+    }
+    carve(c, L);
+    double u0[3] = {cfg->u0[0], cfg->u0[1], d == 3 ? cfg->u0[2] : 0.0}, fe[19];
+    feq_host(cfg->lattice, cfg->p0, u0, fe);
+    if ((e = launch_init_uniform(c, c->f[0], fe)) != hipSuccess ||
+        (e = hipMemsetAsync(c->owner, 0xFF, (size_t)((N + 1) / 2 * 2) * sizeof(uint16_t), c->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(c->flags, 0, ALIGN, c->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(c->P.lo, 0, (size_t)c->cap * 6 * sizeof(int32_t), c->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(c->P.hi, 0xFF, (size_t)c->cap * 3 * sizeof(int32_t), c->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
+        if (c->own_mem) (void)hipFree(c->ws);
+        delete c;
+        return LBM_EDEVICE;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx *c)
+{
+    if (!c) return LBM_EINVAL;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    if (c->own_mem) (void)hipFree(c->ws);
+    if (c->rec_dev) (void)hipFree(c->rec_dev);
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+    return LBM_OK;
+}
+
+int lbm_set_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
+{
+    if (!c) return LBM_EINVAL;
+    if (n < 0 || n > c->cfg.max_particles) return fail(c, LBM_EINVAL, "particle count exceeds max_particles");
+    if (n > 0 && !p) return fail(c, LBM_EINVAL, "particles is NULL");
+    const int d = c->d, cap = c->cap;
+    const int nn[3] = {c->geo.nx, c->geo.ny, c->geo.nz};
+    const int per[3] = {c->geo.per_x, c->geo.per_y, c->geo.per_z};
+    for (int i = 0; i < n; ++i) {
+        const lbm_particle &q = p[i];
+        const bool ok_shape = (d == 2 && (q.shape == LBM_DISK || q.shape == LBM_ELLIPSE)) || (d == 3 && q.shape == LBM_SPHERE);
+        if (!ok_shape) return fail(c, LBM_EINVAL, "shape not valid for this lattice");
+        if (!(q.rho_s > 0) || !(q.a >= 1.0)) return fail(c, LBM_EINVAL, "rho_s must be > 0 and a >= 1");
+        if (q.shape == LBM_ELLIPSE && !(q.b >= 1.0 && q.b <= q.a)) return fail(c, LBM_EINVAL, "ellipse needs a >= b >= 1");
+        for (int k = 0; k < d; ++k) {
+            if (!isfinite(q.x[k])) return fail(c, LBM_EINVAL, "non-finite centre");
+            if (per[k]) {
+                if (q.a + 2.0 >= 0.5 * nn[k]) return fail(c, LBM_EINVAL, "radius too large for a periodic axis");
+                if (q.x[k] < 0 || q.x[k] >= nn[k]) return fail(c, LBM_EINVAL, "centre outside a periodic axis");
+            } else if (q.x[k] - q.a < -0.5 || q.x[k] + q.a > nn[k] - 0.5) {
+                return fail(c, LBM_EINVAL, "particle crosses a wall");
+            }
+        }
+    }
+    (void)hipSetDevice(c->device);
+    // clear the previous indicator
+    if (c->np > 0) HIPCHK(c, launch_raster_clear(c));
+    // host images of the particle arrays
+    std::vector<double> X(3 * cap, 0), th(cap, 0), z3(3 * cap, 0), rho(cap, 1), a(cap, 1), b(cap, 1), C(cap, 0);
+    std::vector<int32_t> shape(cap, 0);
+    for (int i = 0; i < n; ++i) {
+        for (int k = 0; k < d; ++k) X[3 * i + k] = p[i].x[k];
+        th[i] = p[i].theta;
+        rho[i] = p[i].rho_s;
+        a[i] = p[i].a;
+        b[i] = p[i].shape == LBM_ELLIPSE ? p[i].b : p[i].a;
+        shape[i] = p[i].shape;
+        const double V = p[i].shape == LBM_DISK      ? M_PI * p[i].a * p[i].a
+                         : p[i].shape == LBM_ELLIPSE ? M_PI * p[i].a * b[i]
+                                                     : 4.0 / 3.0 * M_PI * p[i].a * p[i].a * p[i].a;
+        const double Cl = (p[i].rho_s - c->rp.rho_f) * c->rp.gmag;
+        C[i] = c->rp.cform == 1 ? Cl : Cl * V;
+    }
+    const size_t b3 = sizeof(double) * 3 * cap, b1 = sizeof(double) * cap;
+    HIPCHK(c, hipMemcpyAsync(c->P.X, X.data(), b3, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->P.theta, th.data(), b1, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->P.A, z3.data(), b3, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->P.rho_s, rho.data(), b1, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->P.a, a.data(), b1, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->P.b, b.data(), b1, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->P.Cc, C.data(), b1, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->P.shape, shape.data(), sizeof(int32_t) * cap, hipMemcpyHostToDevice, c->stream));
+    c->np = n;
+    c->host_parts.assign(p, p + n);
+    // indicator, acceleration table, U^0 and omega^0 on the current populations
+    HIPCHK(c, launch_raster_set(c));
+    HIPCHK(c, launch_rigid(c, nullptr, 0));
+    HIPCHK(c, launch_fields(c, c->f[c->cur], c->usol, nullptr, 1));
+    HIPCHK(c, launch_reduce(c));
+    HIPCHK(c, hipMemcpyAsync(c->P.Uprev, c->P.U, b3, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->P.Wprev, c->P.W, b3, hipMemcpyDeviceToDevice, c->stream));
+    std::vector<int32_t> Nn(cap, 0);
+    HIPCHK(c, hipMemcpyAsync(Nn.data(), c->P.N, sizeof(int32_t) * cap, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < n; ++i)
+        if (Nn[i] == 0) return fail(c, LBM_EINVAL, "a particle covers no lattice node");
+    return LBM_OK;
+}
+
+// One step queues the five kernels; with profiling on, each launch is
+// bracketed by a pair of pooled events whose durations are summed per class.
+static int step_impl(lbm_ctx *c, int64_t nsteps, double *rec_dev)
+{
+    std::vector<std::pair<int, size_t>> used; // (kernel class, event pair index)
+    size_t next = 0;
+    auto timed = [&](int kind, hipError_t (*fn)(lbm_ctx *, void *), void *arg) -> hipError_t {
+        if (!c->prof) return fn(c, arg);
+        if (2 * next + 2 > c->ev_pool.size()) {
+            for (int k = 0; k < 64; ++k) {
+                hipEvent_t e;
+                hipError_t err = hipEventCreate(&e);
+                if (err != hipSuccess) return err;
+                c->ev_pool.push_back(e);
+            }
+        }
+        hipError_t err = hipEventRecord(c->ev_pool[2 * next], c->stream);
+        if (err != hipSuccess) return err;
+        err = fn(c, arg);
+        if (err != hipSuccess) return err;
+        err = hipEventRecord(c->ev_pool[2 * next + 1], c->stream);
+        used.push_back({kind, next});
+        ++next;
+        return err;
+    };
+    for (int64_t s = 0; s < nsteps; ++s) {
+        void *bufs[2] = {c->f[c->cur], c->f[c->cur ^ 1]};
+        HIPCHK(c, timed(0, [](lbm_ctx *cc, void *b) { return launch_stream_collide(cc, ((void **)b)[0], ((void **)b)[1]); },
+                        bufs));
+        c->cur ^= 1;
+        HIPCHK(c, timed(1, [](lbm_ctx *cc, void *) { return launch_reduce(cc); }, nullptr));
+        double *rec = rec_dev ? rec_dev + (size_t)s * c->np * 14 : nullptr;
+        HIPCHK(c, timed(2, [](lbm_ctx *cc, void *r) { return launch_rigid(cc, (double *)r, 1); }, rec));
+        HIPCHK(c, timed(3, [](lbm_ctx *cc, void *) { return launch_raster_clear(cc); }, nullptr));
+        HIPCHK(c, timed(4, [](lbm_ctx *cc, void *) { return launch_raster_set(cc); }, nullptr));
+        c->step++;
+        if (c->prof && next >= 512) { // bound the pool: drain what has been recorded
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            for (auto &u : used) {
+                float ms = 0.f;
+                HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[2 * u.second], c->ev_pool[2 * u.second + 1]));
+                c->prof_ms[u.first] += ms;
+                c->prof_cnt[u.first] += 1;
+            }
+            used.clear();
+            next = 0;
+        }
+    }
+    if (c->prof) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (auto &u : used) {
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[2 * u.second], c->ev_pool[2 * u.second + 1]));
+            c->prof_ms[u.first] += ms;
+            c->prof_cnt[u.first] += 1;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int64_t nsteps)
+{
+    if (!c || nsteps < 0) return c ? fail(c, LBM_EINVAL, "nsteps < 0") : LBM_EINVAL;
+    (void)hipSetDevice(c->device);
+    return step_impl(c, nsteps, nullptr);
+}
+
+int lbm_step_record(lbm_ctx *c, int64_t nsteps, double *host_rec)
+{
+    if (!c || nsteps < 0 || (nsteps > 0 && !host_rec)) return c ? fail(c, LBM_EINVAL, "bad arguments") : LBM_EINVAL;
+    (void)hipSetDevice(c->device);
+    const size_t need = (size_t)nsteps * std::max(c->np, 1) * 14 * sizeof(double);
+    if (need > c->rec_cap) {
+        if (c->rec_dev) HIPCHK(c, hipFree(c->rec_dev));
+        c->rec_dev = nullptr;
+        c->rec_cap = 0;
+        HIPCHK(c, hipMalloc(&c->rec_dev, need));
+        c->rec_cap = need;
+    }
+    int rc = step_impl(c, nsteps, c->rec_dev);
+    if (rc) return rc;
+    if (nsteps > 0 && c->np > 0)
+        HIPCHK(c, hipMemcpyAsync(host_rec, c->rec_dev, (size_t)nsteps * c->np * 14 * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return lbm_sync(c);
+}
+
+int lbm_sync(lbm_ctx *c)
+{
+    if (!c) return LBM_EINVAL;
+    (void)hipSetDevice(c->device);
+    int32_t fl[2] = {0, 0};
+    HIPCHK(c, hipMemcpyAsync(fl, c->flags, sizeof(fl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (fl[0]) return fail(c, LBM_EUNSTABLE, "velocity non-finite or above 0.3");
+    if (fl[1]) return fail(c, LBM_EDOMAIN, "a particle left the box or lost all its nodes");
+    return LBM_OK;
+}
+
+int lbm_get_fields(lbm_ctx *c, double *host_u, double *host_p, int32_t *host_owner)
+{
+    if (!c) return LBM_EINVAL;
+    (void)hipSetDevice(c->device);
+    const int64_t N = c->geo.N;
+    if (host_u || host_p) {
+        double *du = c->staging, *dp = c->staging + (size_t)3 * N;
+        HIPCHK(c, launch_fields(c, c->f[c->cur], du, dp, 0));
+        if (host_u) HIPCHK(c, hipMemcpyAsync(host_u, du, sizeof(double) * c->d * N, hipMemcpyDeviceToHost, c->stream));
+        if (host_p) HIPCHK(c, hipMemcpyAsync(host_p, dp, sizeof(double) * N, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if (host_owner) {
+        int32_t *dow = (int32_t *)c->staging;
+        HIPCHK(c, launch_owner_to_int(c, dow));
+        HIPCHK(c, hipMemcpyAsync(host_owner, dow, sizeof(int32_t) * N, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return lbm_sync(c);
+}
+
+int lbm_get_populations(lbm_ctx *c, double *host_f)
+{
+    if (!c || !host_f) return LBM_EINVAL;
+    (void)hipSetDevice(c->device);
+    const int64_t N = c->geo.N;
+    for (int q0 = 0; q0 < c->Q; q0 += 4) {
+        const int nq = std::min(4, c->Q - q0);
+        HIPCHK(c, launch_populations(c, c->f[c->cur], c->staging, q0, nq));
+        HIPCHK(c, hipMemcpyAsync(host_f + (size_t)q0 * N, c->staging, sizeof(double) * nq * N, hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return LBM_OK;
+}
+
+int lbm_set_populations(lbm_ctx *c, const double *host_f)
+{
+    if (!c || !host_f) return LBM_EINVAL;
+    (void)hipSetDevice(c->device);
+    const int64_t N = c->geo.N;
+    // f~ of direction q needs f^n of q and of opp(q): upload both
+    for (int q = 0; q < c->Q; ++q) {
+        int opp;
+        if (c->cfg.lattice == LBM_D2Q9) {
+            static const int o9[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+            opp = o9[q];
+        } else {
+            opp = q == 0 ? 0 : (q % 2 ? q + 1 : q - 1);
+        }
+        HIPCHK(c, hipMemcpyAsync(c->staging, host_f + (size_t)q * N, sizeof(double) * N, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->staging + N, host_f + (size_t)opp * N, sizeof(double) * N, hipMemcpyHostToDevice,
+                                 c->stream));
+        HIPCHK(c, launch_set_populations(c, c->staging, c->f[c->cur], q, 2));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return LBM_OK;
+}
+
+int lbm_get_particles(lbm_ctx *c, lbm_particle *out, int32_t n)
+{
+    if (!c || (n > 0 && !out)) return LBM_EINVAL;
+    if (n > c->np) return fail(c, LBM_EINVAL, "more particles requested than set");
+    (void)hipSetDevice(c->device);
+    if (c->np > 0) {
+        // measure U^n, omega^n on the current populations
+        HIPCHK(c, launch_fields(c, c->f[c->cur], c->usol, nullptr, 1));
+        HIPCHK(c, launch_reduce(c));
+    }
+    const int cap = c->cap;
+    std::vector<double> X(3 * cap), th(cap), U(3 * cap), W(3 * cap), Up(3 * cap), Wp(3 * cap), A(3 * cap);
+    std::vector<int32_t> Nn(cap);
+    const size_t b3 = sizeof(double) * 3 * cap;
+    HIPCHK(c, hipMemcpyAsync(X.data(), c->P.X, b3, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(th.data(), c->P.theta, sizeof(double) * cap, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(U.data(), c->P.U, b3, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(W.data(), c->P.W, b3, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(Up.data(), c->P.Uprev, b3, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(Wp.data(), c->P.Wprev, b3, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(A.data(), c->P.A, b3, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(Nn.data(), c->P.N, sizeof(int32_t) * cap, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < n; ++i) {
+        lbm_particle &q = out[i];
+        q = c->host_parts[i];
+        for (int k = 0; k < 3; ++k) {
+            q.x[k] = X[3 * i + k];
+            q.U[k] = U[3 * i + k];
+            q.omega[k] = W[3 * i + k];
+            q.U_prev[k] = Up[3 * i + k];
+            q.omega_prev[k] = Wp[3 * i + k];
+            q.A[k] = A[3 * i + k];
+        }
+        q.theta = th[i];
+        q.n_nodes = Nn[i];
+    }
+    return lbm_sync(c);
+}
+
+int lbm_profile(lbm_ctx *c, int32_t enable)
+{
+    if (!c) return LBM_EINVAL;
+    c->prof = enable != 0;
+    return LBM_OK;
+}
+
+int lbm_profile_read(lbm_ctx *c, double *ms, int64_t *cnt, int32_t reset)
+{
+    if (!c) return LBM_EINVAL;
+    for (int k = 0; k < LBM_NKERNELS; ++k) {
+        if (ms) ms[k] = c->prof_ms[k];
+        if (cnt) cnt[k] = c->prof_cnt[k];
+        if (reset) {
+            c->prof_ms[k] = 0.0;
+            c->prof_cnt[k] = 0;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_copy(void *dst, const void *src, size_t bytes, void *stream)
+{
+    if ((!dst || !src) && bytes) return LBM_EINVAL;
+    if (((uintptr_t)dst | (uintptr_t)src) % 16) return LBM_EINVAL;
+    return launch_copy(dst, src, bytes, (hipStream_t)stream) == hipSuccess ? LBM_OK : LBM_EDEVICE;
+}
+
+int lbm_get_step(const lbm_ctx *c, int64_t *step)
+{
+    if (!c || !step) return LBM_EINVAL;
+    *step = c->step;
+    return LBM_OK;
+}
+
+const char *lbm_last_error(const lbm_ctx *c)
+{
+    if (!c) return "no context";
+    return c->err.c_str();
+}
+
+} // extern "C"

@@ -1,0 +1,77 @@
+"""The C-ABI library loads and exports every symbol include/lbm.h declares,
+and rejects invalid configurations on the host (no compute call, no GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2511_01629_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(lbm_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_the_binding_exports():
+    assert _declared() == sorted(lbm.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lbm.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def _base():
+    return dict(lattice="D2Q9", n=(64, 32, 1), periodic=(1, 0, 0), tau=0.8, storage="f32")
+
+
+@pytest.mark.parametrize("bad", [
+    dict(tau=0.5), dict(tau=0.3), dict(alpha=2.0), dict(n=(0, 32, 1)), dict(lattice="D3Q19", n=(8, 8, -1)),
+    dict(K=0), dict(eps_p=0.0), dict(delta=-1.0), dict(n=(40000, 40000, 1)),
+])
+def test_invalid_configs_rejected_on_host(bad):
+    lib = lbm.load()
+    cfg = dict(_base(), **bad)
+    c = lbm.make_config(cfg, max_particles=4)
+    size = C.c_size_t()
+    assert lib.lbm_workspace_size(C.byref(c), C.byref(size)) == lbm.LBM_EINVAL
+    ctx = C.c_void_p()
+    assert lib.lbm_create(C.byref(c), C.byref(ctx)) == lbm.LBM_EINVAL
+    assert not ctx.value
+
+
+def test_invalid_storage_and_particle_cap():
+    lib = lbm.load()
+    c = lbm.make_config(_base(), max_particles=70000)
+    ctx = C.c_void_p()
+    assert lib.lbm_create(C.byref(c), C.byref(ctx)) == lbm.LBM_EINVAL
+    c = lbm.make_config(_base(), max_particles=1)
+    c.storage = 7
+    assert lib.lbm_create(C.byref(c), C.byref(ctx)) == lbm.LBM_EINVAL
+
+
+def test_workspace_size_scales_with_storage():
+    lib = lbm.load()
+    sizes = {}
+    for s in ("f64", "f32", "f16"):
+        c = lbm.make_config(_base(), storage=s, max_particles=8)
+        size = C.c_size_t()
+        assert lib.lbm_workspace_size(C.byref(c), C.byref(size)) == 0
+        sizes[s] = size.value
+    N = 64 * 32
+    # two population buffers of Q*N elements differ by the element size
+    assert sizes["f64"] - sizes["f32"] >= 2 * 9 * N * 4 - 4096
+    assert sizes["f32"] - sizes["f16"] >= 2 * 9 * N * 2 - 4096
+
+
+def test_null_arguments():
+    lib = lbm.load()
+    assert lib.lbm_create(None, None) == lbm.LBM_EINVAL
+    assert lib.lbm_destroy(None) == lbm.LBM_EINVAL
+    assert lib.lbm_step(None, 1) == lbm.LBM_EINVAL
+    assert lib.lbm_last_error(None) == b"no context"

@@ -1,0 +1,167 @@
+"""GPU parity: the HIP library through its C ABI against the FP64 oracle on the
+same seeded inputs (FP64 storage: within 1e-12 relative).
+
+Sizes span several 256-node workgroups with a ragged tail; walls, periodic
+axes, corners, contacts and ellipses are all exercised.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import banner, check_owner, pair, rel
+from oracle import oracle as O
+from paper_2511_01629_amd import lbm
+from paper_2511_01629_amd.workloads import place, random_state, workload
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.mark.parametrize("kind,n,periodic", [
+    ("D2Q9", (37, 29, 1), (0, 0, 0)),
+    ("D2Q9", (37, 29, 1), (1, 0, 0)),
+    ("D2Q9", (33, 20, 1), (1, 1, 0)),
+    ("D3Q19", (13, 11, 9), (0, 0, 0)),
+    ("D3Q19", (13, 11, 9), (1, 0, 1)),
+])
+def test_fluid_step_random_state(kind, n, periodic):
+    """Pull streaming with bounce-back/wrap and the BGK collision from a random
+    non-equilibrium state (eq. 10, 13, 15)."""
+    banner(f"fluid random {kind} {n} {periodic}")
+    cfg = dict(lattice=kind, n=n, periodic=periodic, tau=0.7, fluid_accel=(2e-5, -1e-5, 3e-6))
+    Q = 9 if kind == "D2Q9" else 19
+    shp = (n[2] if kind == "D3Q19" else 1, n[1], n[0])
+    f0 = random_state(shp, Q, 2e-3, seed=11)
+    sim, ora = pair(cfg, [], f0=f0)
+    assert rel(sim.populations(), f0) < 1e-16  # set/get round trip through the inverse pull
+    for steps in (1, 4):
+        sim.step(steps)
+        ora.step(steps)
+        e = rel(sim.populations(), ora.f())
+        assert e < TOL, e
+    ug, pg, _ = sim.fields()
+    uo, po, _ = ora.fields()
+    assert rel(ug, uo) < TOL and rel(pg, po) < TOL
+
+
+def test_penalize_all_random_state():
+    banner("penalize_all random")
+    cfg = dict(lattice="D2Q9", n=(31, 27, 1), periodic=(1, 1, 0), tau=0.8, alpha=0.6, penalize_all=1)
+    f0 = random_state((1, 27, 31), 9, 2e-3, seed=5)
+    sim, ora = pair(cfg, [], f0=f0)
+    sim.step(3)
+    ora.step(3)
+    assert rel(sim.populations(), ora.f()) < TOL
+
+
+def _compare_run(cfg, parts, steps, f0=None, storage="f64", tol=TOL, xtol=TOL):
+    sim, ora = pair(cfg, parts, storage=storage, f0=f0)
+    rg = sim.step_record(steps)
+    ro = ora.step(steps, record=True)
+    # per-step records: X theta U omega A N
+    scaleX = max(np.abs(ro[:, :, 0:3]).max(), 1.0)
+    assert np.abs(rg[:, :, 0:3] - ro[:, :, 0:3]).max() / scaleX < xtol
+    assert rel(rg[:, :, 4:10], ro[:, :, 4:10]) < tol * 10
+    eA = np.abs(rg[:, :, 10:13] - ro[:, :, 10:13]).max()
+    assert eA <= max(tol * 10 * np.abs(ro[:, :, 10:13]).max(), 1e-13), eA
+    assert np.array_equal(rg[:, :, 13], ro[:, :, 13])
+    fg, fo = sim.populations(), ora.f()
+    assert rel(fg, fo) < tol
+    Pg, Po = sim.particles(), ora.particles()
+    ug, pg, og = sim.fields()
+    uo, po, oo = ora.fields()
+    assert rel(ug, uo) < tol and rel(pg, po) < tol * 10
+    check_owner(og, oo, parts, Po, cfg.get("periodic", (0, 0, 0)))
+    # omega is a ratio whose numerator sum r x u cancels for near-uniform flow:
+    # its error is measured on the scale |U|/R of an angular velocity
+    Uscale = max(np.abs(Po["U"]).max(), np.abs(Po["U_prev"]).max(), 1e-30)
+    Rmin = min(p["a"] for p in parts)
+    for key in ("U", "U_prev"):
+        assert np.abs(Pg[key] - Po[key]).max() / Uscale < tol * 10, key
+    for key in ("omega", "omega_prev"):
+        assert np.abs(Pg[key] - Po[key]).max() * Rmin / Uscale < tol * 10, key
+    assert np.abs(Pg["theta"] - Po["theta"]).max() < 1e-12
+    return sim, ora, rg, ro
+
+
+def test_particles_random_state_2d():
+    """The whole step with two disks and an ellipse in contact, walls in y,
+    periodic x, from a random state (eq. 9-22, Algorithm 1)."""
+    banner("particles random 2d")
+    cfg = dict(lattice="D2Q9", n=(45, 37, 1), periodic=(1, 0, 0), tau=0.7, g=(0.0, -5e-4, 0.0), eps_p=2.0,
+               eps_w=1.0, delta=1.0)
+    parts = [dict(shape="disk", rho_s=1.5, a=4.0, x=(10.2, 14.7, 0.0)),
+             dict(shape="disk", rho_s=1.2, a=5.0, x=(19.0, 17.1, 0.0)),
+             dict(shape="ellipse", rho_s=1.4, a=6.0, b=3.0, x=(40.5, 6.3, 0.0), theta=0.9)]
+    f0 = random_state((1, 37, 45), 9, 1e-3, seed=3)
+    _, _, rg, _ = _compare_run(cfg, parts, 30, f0=f0)
+    assert np.abs(rg[:, :, 10:12]).max() > 1e-6  # contact forces acted
+
+
+def test_particles_3d():
+    banner("particles 3d")
+    cfg = dict(lattice="D3Q19", n=(17, 15, 19), periodic=(0, 1, 0), tau=0.65, g=(0.0, 0.0, -5e-4))
+    parts = [dict(shape="sphere", rho_s=1.6, a=3.0, x=(7.0, 7.5, 9.0)),
+             dict(shape="sphere", rho_s=1.3, a=3.5, x=(12.2, 8.0, 12.4))]
+    f0 = random_state((19, 15, 17), 19, 1e-3, seed=4)
+    _compare_run(cfg, parts, 12, f0=f0)
+
+
+def test_floating_disk_workload():
+    """The floating-disk workload in full (200x400, 2000 steps, FP64)."""
+    banner("floating disk 200x400 2000 steps")
+    cfg, parts, steps, _ = workload("floating_disk_200x400")
+    sim, ora, rg, ro = _compare_run(cfg, parts, steps)
+    assert np.abs(rg[:, 0, 4:6] - [0.02, 0.0]).max() <= 1e-3 * 0.02
+
+
+def test_small_sedimentation_contacts():
+    """Eight bodies settling in a closed 64x96 box with strong gravity, so that
+    particle-particle and particle-wall forces act (sec. 2.3)."""
+    banner("small sedimentation contacts")
+    kinds = [("disk", 5.0, 5.0)] * 5 + [("ellipse", 6.0, 3.0)] * 3
+    # gaps of 0.3 l.u. < delta: several pairs start inside the collision range
+    parts = place((64, 96), kinds, seed=7, rho_range=(1.2, 1.8), upper_axis=1, gap=0.3, margin=0.3)
+    cfg = dict(lattice="D2Q9", n=(64, 96, 1), periodic=(0, 0, 0), tau=0.6, g=(0.0, -2e-4, 0.0))
+    _, _, rg, _ = _compare_run(cfg, parts, 400, xtol=1e-11)
+    assert (np.abs(rg[:, :, 10:12]).max(axis=(1, 2)) > 0).sum() > 100  # contact forces in most steps
+
+
+def test_determinism_bitwise():
+    banner("determinism")
+    cfg = dict(lattice="D2Q9", n=(80, 64, 1), periodic=(0, 0, 0), tau=0.6, g=(0.0, -1e-4, 0.0))
+    parts = place((80, 64), [("disk", 5.0, 5.0)] * 4, seed=9, rho_range=(1.2, 1.5), upper_axis=1)
+    out = []
+    for _ in range(2):
+        sim = lbm.Simulation(cfg, parts, storage="f32")
+        sim.step(50)
+        out.append((sim.populations(), sim.particles()["X"]))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_unstable_sentinel():
+    banner("sentinel")
+    cfg = dict(lattice="D2Q9", n=(40, 30, 1), periodic=(1, 1, 0), tau=0.8, u0=(0.35, 0.0))
+    sim = lbm.Simulation(cfg, [], storage="f32")
+    sim.step(2)
+    with pytest.raises(lbm.LbmError) as e:
+        sim.sync()
+    assert e.value.code == lbm.LBM_EUNSTABLE
+
+
+def test_particle_validation():
+    banner("validation")
+    cfg = dict(lattice="D2Q9", n=(30, 60, 1), periodic=(1, 0, 0), tau=0.8)
+    sim = lbm.Simulation(cfg, [], storage="f32", max_particles=2)
+    for bad in ([dict(shape="disk", rho_s=1.2, a=5.0, x=(15.0, 3.0, 0.0))],       # crosses the y wall
+                [dict(shape="sphere", rho_s=1.2, a=5.0, x=(15.0, 30.0, 0.0))],    # 3D shape on D2Q9
+                [dict(shape="disk", rho_s=1.2, a=5.0, x=(15.0, 30.0, 0.0))] * 3,  # over capacity
+                [dict(shape="disk", rho_s=1.2, a=14.0, x=(15.0, 30.0, 0.0))],     # a + 2 >= n/2 on the x period
+                [dict(shape="ellipse", rho_s=1.2, a=3.0, b=4.0, x=(15.0, 30.0, 0.0))],  # b > a
+                [dict(shape="disk", rho_s=-1.0, a=5.0, x=(15.0, 30.0, 0.0))]):    # negative density
+        with pytest.raises(lbm.LbmError) as e:
+            sim.set_particles(bad)
+        assert e.value.code == lbm.LBM_EINVAL
+    sim.set_particles([dict(shape="disk", rho_s=1.2, a=5.0, x=(15.0, 30.0, 0.0))])  # a valid one still works
+    sim.step(2)
+    sim.sync()
