@@ -17,7 +17,9 @@ OUT = os.path.join(HERE, "liblbmpen.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+# -ffp-contract=on: multiply-adds are fused only inside one source
+# expression, so every kernel instantiation rounds a node identically.
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result"]
 
 

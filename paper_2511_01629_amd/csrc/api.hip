@@ -4,9 +4,9 @@
 // buffer: two population buffers [Q][N] in the storage type, the uint16
 // owner map, the solid-node velocity [d][N] (FP64), a staging area of 4N
 // doubles for transfers, device flags and the particle arrays.  A step queues
-// five kernels on the context stream: the fused stream-collide-penalize
-// update, the per-particle sums, Algorithm 1, the clear of the old scan boxes
-// and the rasterisation of the new ones.
+// three kernels on the context stream: the fused stream-collide-penalize
+// update, the per-particle sums (which also clear the indicator), and
+// Algorithm 1 with the rasterisation of the new indicator.
 #include <math.h>
 #include <string.h>
 
@@ -20,7 +20,7 @@ using namespace lbm;
 namespace {
 
 constexpr size_t ALIGN = 256;
-constexpr int PART_DOUBLES = 3 * 7 + 4 + 3 + 16 + 3 * 5; // X theta U W Uprev Wprev A, rho a b C, acc, sums, Y Ys Y2 Ub Dc
+constexpr int PART_DOUBLES = 3 * 8 + 5 + 3 + 16 + 3 * 5 + 1; // X Xn theta U W Uprev Wprev A, rho a b C, acc, sums, Ub Y Ys Y2 Dc, dth
 constexpr double CS2 = 1.0 / 3.0;
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
@@ -146,6 +146,7 @@ void carve(lbm_ctx *c, const Layout &L)
         return p;
     };
     c->P.X = take(3);
+    c->P.Xn = take(3);
     c->P.theta = take(1);
     c->P.U = take(3);
     c->P.W = take(3);
@@ -163,6 +164,7 @@ void carve(lbm_ctx *c, const Layout &L)
     c->P.Y2 = take(3);
     c->P.Ub = take(3);
     c->P.Dc = take(3);
+    c->P.dth = take(1);
     c->P.acc_f = (float *)(base + L.pf);
     int32_t *pi = (int32_t *)(base + L.pi);
     c->P.shape = pi;
@@ -348,10 +350,9 @@ int lbm_set_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
     c->np = n;
     c->host_parts.assign(p, p + n);
     // indicator, acceleration table, U^0 and omega^0 on the current populations
-    HIPCHK(c, launch_raster_set(c));
-    HIPCHK(c, launch_rigid(c, nullptr, 0));
+    HIPCHK(c, launch_rigid_raster(c, 0));
     HIPCHK(c, launch_fields(c, c->f[c->cur], c->usol, nullptr, 1));
-    HIPCHK(c, launch_reduce(c));
+    HIPCHK(c, launch_reduce(c, 0, nullptr));
     HIPCHK(c, hipMemcpyAsync(c->P.Uprev, c->P.U, b3, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->P.Wprev, c->P.W, b3, hipMemcpyDeviceToDevice, c->stream));
     std::vector<int32_t> Nn(cap, 0);
@@ -362,7 +363,9 @@ int lbm_set_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
     return LBM_OK;
 }
 
-// One step queues the five kernels; with profiling on, each launch is
+// One step queues the lattice update, the momentum sums (which also clear the
+// indicator) and Algorithm 1 with the new indicator (K = 1; K > 1 adds the
+// sub-step integration before it).  With profiling on, each launch is
 // bracketed by a pair of pooled events whose durations are summed per class.
 static int step_impl(lbm_ctx *c, int64_t nsteps, double *rec_dev)
 {
@@ -392,11 +395,16 @@ static int step_impl(lbm_ctx *c, int64_t nsteps, double *rec_dev)
         HIPCHK(c, timed(0, [](lbm_ctx *cc, void *b) { return launch_stream_collide(cc, ((void **)b)[0], ((void **)b)[1]); },
                         bufs));
         c->cur ^= 1;
-        HIPCHK(c, timed(1, [](lbm_ctx *cc, void *) { return launch_reduce(cc); }, nullptr));
         double *rec = rec_dev ? rec_dev + (size_t)s * c->np * 14 : nullptr;
-        HIPCHK(c, timed(2, [](lbm_ctx *cc, void *r) { return launch_rigid(cc, (double *)r, 1); }, rec));
-        HIPCHK(c, timed(3, [](lbm_ctx *cc, void *) { return launch_raster_clear(cc); }, nullptr));
-        HIPCHK(c, timed(4, [](lbm_ctx *cc, void *) { return launch_raster_set(cc); }, nullptr));
+        HIPCHK(c, timed(1, [](lbm_ctx *cc, void *r) { return launch_reduce(cc, 1, (double *)r); }, rec));
+        if (c->rp.K == 1) {
+            HIPCHK(c, timed(2, [](lbm_ctx *cc, void *) { return launch_rigid_raster(cc, 1); }, nullptr));
+            std::swap(c->P.X, c->P.Xn);
+        } else {
+            HIPCHK(c, timed(2, [](lbm_ctx *cc, void *) { return launch_rigid_substeps(cc); }, nullptr));
+            std::swap(c->P.X, c->P.Xn);
+            HIPCHK(c, timed(3, [](lbm_ctx *cc, void *) { return launch_rigid_raster(cc, 0); }, nullptr));
+        }
         c->step++;
         if (c->prof && next >= 512) { // bound the pool: drain what has been recorded
             HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -529,7 +537,7 @@ int lbm_get_particles(lbm_ctx *c, lbm_particle *out, int32_t n)
     if (c->np > 0) {
         // measure U^n, omega^n on the current populations
         HIPCHK(c, launch_fields(c, c->f[c->cur], c->usol, nullptr, 1));
-        HIPCHK(c, launch_reduce(c));
+        HIPCHK(c, launch_reduce(c, 0, nullptr));
     }
     const int cap = c->cap;
     std::vector<double> X(3 * cap), th(cap), U(3 * cap), W(3 * cap), Up(3 * cap), Wp(3 * cap), A(3 * cap);

@@ -13,12 +13,13 @@ namespace lbm {
 
 // Device arrays of the particle state, structure-of-arrays, FP64.
 struct PartDev {
-    double *X, *theta, *U, *W, *Uprev, *Wprev, *A; // [cap*3] (theta [cap])
+    double *X, *Xn, *theta, *U, *W, *Uprev, *Wprev, *A; // [cap*3] (theta [cap]); Xn: next centres
     double *rho_s, *a, *b, *Cc;                    // [cap]; Cc = collision constant C_i
     double *acc_d;                                 // [cap*3] solid-node acceleration (FP64 mode)
     float *acc_f;                                  // [cap*3] the same in FP32
     double *sums;                                  // [cap*16] momentum sums of the last reduction
-    double *Y, *Ys, *Y2, *Ub, *Dc;                 // [cap*3] Algorithm 1 scratch (Dc: summed corrections)
+    double *Ub, *dth;                              // U_bar = (U^n + U^{n-1})/2 [cap*3], theta increment [cap]
+    double *Y, *Ys, *Y2, *Dc;                      // [cap*3] sub-step scratch (Dc: summed corrections)
     int32_t *shape, *N;                            // [cap]
     int32_t *lo, *hi;                              // [cap*3] scan box (unwrapped node coords)
 };
@@ -87,9 +88,9 @@ hipError_t launch_set_populations(lbm_ctx *c, const double *fn, void *fout, int 
 
 // particles.hip
 hipError_t launch_raster_clear(lbm_ctx *c);
-hipError_t launch_raster_set(lbm_ctx *c);
-hipError_t launch_reduce(lbm_ctx *c);
-hipError_t launch_rigid(lbm_ctx *c, double *rec, int update);
+hipError_t launch_reduce(lbm_ctx *c, int step, double *rec);
+hipError_t launch_rigid_raster(lbm_ctx *c, int update);
+hipError_t launch_rigid_substeps(lbm_ctx *c);
 hipError_t launch_owner_to_int(lbm_ctx *c, int32_t *out);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 

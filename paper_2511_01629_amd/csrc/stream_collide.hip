@@ -104,22 +104,13 @@ __device__ __forceinline__ T feq_q(int q, T p3, T cu, T u15)
     return T(L::w[q]) * (p3 + T(3) * cu + T(4.5) * cu * cu - u15);
 }
 
-template <class L, class S, class T>
-__global__ __launch_bounds__(256) void k_stream_collide(const typename S::raw *__restrict__ fin,
-                                                         typename S::raw *__restrict__ fout,
-                                                         const uint16_t *__restrict__ owner,
-                                                         const T *__restrict__ acc_tab, double *__restrict__ usol,
-                                                         int32_t *__restrict__ flags, Geom g, StepParams sp)
+// Collision of one node, in place: f holds the pulled populations on entry
+// and f~ on return (right side of eq. 10 with F of eq. 14 and, on solid
+// nodes, S of eq. 17).  Writes the velocity of solid nodes for the sums.
+template <class L, class T>
+__device__ __forceinline__ void collide_node(T *f, uint16_t own, const T *__restrict__ acc_tab, const StepParams &sp,
+                                             int32_t *__restrict__ flags, double *__restrict__ usol, int idx, int N)
 {
-    const int N = (int)g.N;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= N) return;
-    int x, y, z;
-    coords<L>(idx, g, x, y, z);
-    T f[L::Q];
-    pull<L, S, T>(fin, idx, x, y, z, g, N, f);
-
-    const uint16_t own = owner[idx];
     const bool solid = own != FLUID;
     T ax = 0, ay = 0, az = 0;
     if (solid) {
@@ -144,13 +135,11 @@ __global__ __launch_bounds__(256) void k_stream_collide(const typename S::raw *_
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) {
             const T cu = T(L::cx[q]) * ux + T(L::cy[q]) * uy + T(L::cz[q]) * uz;
-            const T fe = feq_q<L, T>(q, p3, cu, u15);
-            st<S, T>(fout + q * N + idx, f[q] - om * (f[q] - fe));
+            f[q] = f[q] - om * (f[q] - feq_q<L, T>(q, p3, cu, u15));
         }
         return;
     }
-
-    // solid (or forced) node: full right side of eq. (10)
+    // solid (or forced) node
     T fneq[L::Q];
     T Pxx = 0, Pyy = 0, Pzz = 0, Pxy = 0, Pxz = 0, Pyz = 0;
 #pragma unroll
@@ -182,13 +171,49 @@ __global__ __launch_bounds__(256) void k_stream_collide(const typename S::raw *_
         const T cu = cx * ux + cy * uy + cz * uz;
         const T ca = cx * ax + cy * ay + cz * az;
         const T F = gpre * T(L::w[q]) * (T(3) * (ca - ua) + T(9) * cu * ca);
-        st<S, T>(fout + q * N + idx, f[q] - om * fneq[q] + F + Sq);
+        f[q] = f[q] - om * fneq[q] + F + Sq;
     }
     if (solid) {
         usol[idx] = (double)ux;
         usol[N + idx] = (double)uy;
         if (L::D == 3) usol[2 * N + idx] = (double)uz;
     }
+}
+
+// The lattice update, one node per lane.  Each workgroup covers 256
+// consecutive nodes of one row (fixed y, z), so the row and the wall tests of
+// y and z are uniform and no index division is needed.  Every population is
+// read once (pull) and written once: 2 Q s bytes per node.
+//
+// Measured alternatives that did not pay on MI355X: two adjacent nodes per
+// lane (element-aligned 2-wide loads, or aligned loads with a DPP lane shift
+// for the x-shifted directions), two strided nodes per lane, and an XCD-aware
+// remap of the workgroup order.
+template <class L, class S, class T>
+__global__ __launch_bounds__(256) void k_stream_collide(const typename S::raw *__restrict__ fin,
+                                                         typename S::raw *__restrict__ fout,
+                                                         const uint16_t *__restrict__ owner,
+                                                         const T *__restrict__ acc_tab, double *__restrict__ usol,
+                                                         int32_t *__restrict__ flags, Geom g, StepParams sp, int gx)
+{
+    const int row = blockIdx.x / gx, bx = blockIdx.x - row * gx; // uniform
+    const int x = bx * 256 + (int)threadIdx.x;
+    if (x >= g.nx) return;
+    int y, z;
+    if (L::D == 2) {
+        y = row;
+        z = 0;
+    } else {
+        z = row / g.ny;
+        y = row - z * g.ny;
+    }
+    const int N = (int)g.N;
+    const int idx = row * g.nx + x;
+    T f[L::Q];
+    pull<L, S, T>(fin, idx, x, y, z, g, N, f);
+    collide_node<L, T>(f, owner[idx], acc_tab, sp, flags, usol, idx, N);
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) st<S, T>(fout + q * N + idx, f[q]);
 }
 
 // Macroscopic fields of the state held in fin (pull, then eq. 15a-b).
@@ -331,14 +356,16 @@ static inline unsigned blocks_for(int64_t N) { return (unsigned)((N + 255) / 256
 
 hipError_t launch_stream_collide(lbm_ctx *c, const void *fin, void *fout)
 {
+    const int gx = (c->geo.nx + 255) / 256;
+    const unsigned blocks = (unsigned)gx * (unsigned)(c->geo.ny * c->geo.nz);
     return dispatch(c, [&](auto L, auto S, auto T) {
         using Lt = decltype(L);
         using St = decltype(S);
         using Tt = decltype(T);
         const Tt *acc = std::is_same<Tt, double>::value ? (const Tt *)c->P.acc_d : (const Tt *)c->P.acc_f;
-        hipLaunchKernelGGL((k_stream_collide<Lt, St, Tt>), dim3(blocks_for(c->geo.N)), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL((k_stream_collide<Lt, St, Tt>), dim3(blocks), dim3(256), 0, c->stream,
                            (const typename St::raw *)fin, (typename St::raw *)fout, c->owner, acc, c->usol, c->flags,
-                           c->geo, c->sp);
+                           c->geo, c->sp, gx);
         return hipGetLastError();
     });
 }

@@ -217,14 +217,14 @@ class Simulation:
         self._check(self.lib.lbm_get_step(self.ctx, C.byref(s)))
         return s.value
 
-    KERNELS = ("stream_collide", "reduce", "rigid", "raster_clear", "raster_set")
+    KERNELS = ("stream_collide", "reduce_clear", "rigid_raster", "raster_after_substeps")
 
     def profile(self, enable=True):
         self._check(self.lib.lbm_profile(self.ctx, int(bool(enable))))
 
     def profile_read(self, reset=True):
-        ms = np.zeros(5)
-        cnt = np.zeros(5, dtype=np.int64)
+        ms = np.zeros(len(self.KERNELS))
+        cnt = np.zeros(len(self.KERNELS), dtype=np.int64)
         self._check(self.lib.lbm_profile_read(self.ctx, ms.ctypes.data_as(C.POINTER(C.c_double)),
                                               cnt.ctypes.data_as(C.POINTER(C.c_int64)), int(bool(reset))))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.KERNELS)}

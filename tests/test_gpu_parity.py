@@ -165,3 +165,13 @@ def test_particle_validation():
     sim.set_particles([dict(shape="disk", rho_s=1.2, a=5.0, x=(15.0, 30.0, 0.0))])  # a valid one still works
     sim.step(2)
     sim.sync()
+
+
+def test_substeps_k3():
+    """Algorithm 1 with K = 3 sub-steps (all particles integrated together)."""
+    banner("substeps K=3")
+    kinds = [("disk", 5.0, 5.0)] * 5 + [("ellipse", 6.0, 3.0)] * 3
+    parts = place((64, 96), kinds, seed=7, rho_range=(1.2, 1.8), upper_axis=1, gap=0.3, margin=0.3)
+    cfg = dict(lattice="D2Q9", n=(64, 96, 1), periodic=(0, 0, 0), tau=0.6, g=(0.0, -2e-4, 0.0), K=3)
+    _, _, rg, _ = _compare_run(cfg, parts, 200, xtol=1e-11)
+    assert (np.abs(rg[:, :, 10:12]).max(axis=(1, 2)) > 0).sum() > 20
