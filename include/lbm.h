@@ -153,6 +153,30 @@ int lbm_set_populations(lbm_ctx *ctx, const double *host_f);
  * and omega^n measured now, U^{n-1}, omega^{n-1}, A^n, node count. */
 int lbm_get_particles(lbm_ctx *ctx, lbm_particle *host_particles, int32_t n);
 
+/* ---- differentiated runs (extension beyond the paper) ----
+ * Gradients of a loss of the final particle centres with respect to the
+ * solid densities rho_s,i, tau (alpha follows it when alpha <= 0 was given)
+ * and |g| (the direction of g fixed), by a hand-written adjoint of the step.
+ * The derivative is that of the step map with the indicator sequence frozen
+ * (a binary indicator makes the loss piecewise smooth).
+ *
+ * lbm_forward_checkpointed: run nsteps >= 1 steps starting right after
+ * lbm_set_particles (else ESTATE; K must be 1, else EINVAL), snapshotting the state every `every`
+ * steps and keeping every step's particle record (device memory allocated
+ * by the library: about (nsteps/every + 1) population buffers plus small
+ * records).  Waits for the stream.
+ *
+ * lbm_backward: host dL_dX (n x 3 doubles, the loss gradient with respect
+ * to the final centres) in; host g_rho_s (n), g_tau, g_gmag out (any may be
+ * NULL).  Recomputes each segment from its snapshot (`every` extra
+ * population buffers) and sweeps the adjoint backwards.  The state at the
+ * end of the differentiated run is restored afterwards.  ESTATE without a
+ * preceding lbm_forward_checkpointed; may be called repeatedly with other
+ * seeds.  The snapshot memory is released by lbm_set_particles or
+ * lbm_destroy. */
+int lbm_forward_checkpointed(lbm_ctx *ctx, int64_t nsteps, int32_t every);
+int lbm_backward(lbm_ctx *ctx, const double *dL_dX, double *g_rho_s, double *g_tau, double *g_gmag);
+
 /* Per-kernel timing with HIP events (measurement aid).  While enabled,
  * every kernel lbm_step queues is bracketed by events, and lbm_step waits
  * for the stream before returning.  lbm_profile_read returns, per kernel

@@ -1,0 +1,498 @@
+// adjoint.hip -- hand-written adjoint of one time step (gfx950).
+//
+// The step map is differentiated with the indicator sequence frozen (a
+// binary indicator makes the loss piecewise smooth in the parameters; the
+// derivative is that of the smooth pieces).  With the indicator frozen,
+// omega^n only advances theta, and theta only moves the indicator, so the
+// angular sums carry no derivative: the adjoint of the momentum sums is the
+// broadcast u_bar(x) = U_bar_i / N_i onto the nodes of particle i.
+//
+// One backward step n, given the adjoints of the step's outputs
+// (lambda = dL/df~^n, X_bar^{n+1}, A_bar^{n+1}, U_bar of the U^n kept for the
+// next step), runs three kernels:
+//   k_adj_rigid     Algorithm 1 transposed, one workgroup per particle: the
+//                   pair and wall force Jacobians at X^n and at the
+//                   prediction, gathered over all particles across lanes;
+//                   gives X_bar^n, the adjoint of U^n (for the broadcast) and
+//                   of U^{n-1}, and the density and |g| partials of the
+//                   collision constant and of 1/(2M).
+//   k_adj_lattice   per node: the Jacobian-transpose of the collision
+//                   (eq. 10, 13, 14, 15, 17) re-evaluated from the stored
+//                   pre-step populations, plus the broadcast u_bar; then the
+//                   transpose of the pull, which is a push (streaming is a
+//                   permutation).  Writes a_bar on solid nodes and a
+//                   per-workgroup partial of dL/dtau.
+//   k_adj_particles per particle: A_bar^n = sum of a_bar over its nodes, and
+//                   the density and |g| partials through a = b g + A.
+#include "dispatch.h"
+#include "node.h"
+
+namespace lbm {
+
+// ----------------------------------------------------------- lattice adjoint
+template <class L, class S, class T>
+__global__ __launch_bounds__(256) void k_adj_lattice(const typename S::raw *__restrict__ fprev,
+                                                      const uint16_t *__restrict__ owner, const T *__restrict__ acc_tab,
+                                                      const T *__restrict__ uext, const T *__restrict__ lam_in,
+                                                      T *__restrict__ lam_out, double *__restrict__ asol,
+                                                      double *__restrict__ tau_part, Geom g, StepParams sp, int gx)
+{
+    const int row = blockIdx.x / gx, bx = blockIdx.x - row * gx;
+    const int x = bx * 256 + (int)threadIdx.x;
+    const bool valid = x < g.nx;
+    double tb = 0.0;
+    if (valid) {
+        int y, z;
+        if (L::D == 2) {
+            y = row;
+            z = 0;
+        } else {
+            z = row / g.ny;
+            y = row - z * g.ny;
+        }
+        const int N = (int)g.N;
+        const int idx = row * g.nx + x;
+        T f[L::Q];
+        pull<L, S, T>(fprev, idx, x, y, z, g, N, f);
+        const uint16_t own = owner[idx];
+        const bool solid = own != FLUID;
+        T a[3] = {0, 0, 0};
+        if (solid) {
+            for (int k = 0; k < 3; ++k) a[k] = acc_tab[3 * own + k];
+        } else if (sp.has_fluid_acc) {
+            for (int k = 0; k < 3; ++k) a[k] = (T)sp.fluid_acc[k];
+        }
+        T u[3], p;
+        moments<L, T>(f, a[0], a[1], a[2], u[0], u[1], u[2], p);
+        const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        const T om = (T)sp.omega, p3 = T(3) * p, u15 = T(1.5) * uu;
+        const bool pen = solid || sp.penalize_all;
+        const bool frc = solid || sp.has_fluid_acc;
+        T fneq[L::Q], lam[L::Q], fbar[L::Q];
+        T Pxx = 0, Pyy = 0, Pzz = 0, Pxy = 0, Pxz = 0, Pyz = 0;
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            const T cu = T(L::cx[q]) * u[0] + T(L::cy[q]) * u[1] + T(L::cz[q]) * u[2];
+            fneq[q] = f[q] - feq_q<L, T>(q, p3, cu, u15);
+            lam[q] = lam_in[q * N + idx];
+            if (pen) {
+                const T cx = T(L::cx[q]), cy = T(L::cy[q]), cz = T(L::cz[q]);
+                Pxx += fneq[q] * cx * cx;
+                Pyy += fneq[q] * cy * cy;
+                Pzz += fneq[q] * cz * cz;
+                Pxy += fneq[q] * cx * cy;
+                Pxz += fneq[q] * cx * cz;
+                Pyz += fneq[q] * cy * cz;
+            }
+        }
+        // f~ = f - om fneq + F + S:  f_bar = lam, fneq_bar = -om lam, F_bar = S_bar = lam
+        T fnb[L::Q];
+        T omb = 0;
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            fbar[q] = lam[q];
+            fnb[q] = -om * lam[q];
+            omb -= lam[q] * fneq[q];
+        }
+        T sigb = 0;
+        if (pen) {
+            // S_q = sigma 4.5 w_q (Pi : c c - tr Pi / 3): Pi_bar and sigma_bar
+            const T sigma = (T)sp.alpha;
+            const T tr3 = (Pxx + Pyy + Pzz) * T(1.0 / 3.0);
+            T sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0, str = 0;
+#pragma unroll
+            for (int q = 0; q < L::Q; ++q) {
+                const T cx = T(L::cx[q]), cy = T(L::cy[q]), cz = T(L::cz[q]);
+                const T wl = T(4.5 * L::w[q]) * lam[q];
+                sxx += wl * cx * cx;
+                syy += wl * cy * cy;
+                szz += wl * cz * cz;
+                sxy += wl * cx * cy;
+                sxz += wl * cx * cz;
+                syz += wl * cy * cz;
+                str += wl;
+                const T PiCC = cx * cx * Pxx + cy * cy * Pyy + cz * cz * Pzz +
+                               T(2) * (cx * cy * Pxy + cx * cz * Pxz + cy * cz * Pyz);
+                sigb += wl * (PiCC - tr3);
+            }
+            // trace term acts on the lattice dimensions only (Pzz = 0 in 2D)
+            const T t3 = str * T(1.0 / 3.0);
+            const T bxx = sigma * (sxx - t3), byy = sigma * (syy - t3), bzz = (L::D == 3) ? sigma * (szz - t3) : T(0);
+            const T bxy = sigma * sxy, bxz = sigma * sxz, byz = sigma * syz;
+#pragma unroll
+            for (int q = 0; q < L::Q; ++q) {
+                const T cx = T(L::cx[q]), cy = T(L::cy[q]), cz = T(L::cz[q]);
+                fnb[q] += bxx * cx * cx + byy * cy * cy + bzz * cz * cz +
+                          T(2) * (bxy * cx * cy + bxz * cx * cz + byz * cy * cz);
+            }
+        }
+        T ub[3] = {0, 0, 0}, ab[3] = {0, 0, 0};
+        T gamb = 0;
+        if (frc) {
+            // F_q = gamma w_q [3 (c - u).a + 9 (c.u)(c.a)],  gamma = 1 - om/2
+            const T gpre = T(1) - T(0.5) * om;
+            const T ua = u[0] * a[0] + u[1] * a[1] + u[2] * a[2];
+#pragma unroll
+            for (int q = 0; q < L::Q; ++q) {
+                const T c[3] = {T(L::cx[q]), T(L::cy[q]), T(L::cz[q])};
+                const T ca = c[0] * a[0] + c[1] * a[1] + c[2] * a[2];
+                const T cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+                const T gl = gpre * T(L::w[q]) * lam[q];
+                for (int k = 0; k < 3; ++k) {
+                    ub[k] += gl * (T(-3) * a[k] + T(9) * ca * c[k]);
+                    ab[k] += gl * (T(3) * (c[k] - u[k]) + T(9) * cu * c[k]);
+                }
+                gamb += T(L::w[q]) * lam[q] * (T(3) * (ca - ua) + T(9) * cu * ca);
+            }
+        }
+        // fneq = f - feq(p, u)
+        T pb = 0;
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            fbar[q] += fnb[q];
+            const T eb = -fnb[q]; // feq_bar
+            const T c[3] = {T(L::cx[q]), T(L::cy[q]), T(L::cz[q])};
+            if (q == 0) {
+                pb += eb * T(-3.0 * (1.0 - L::w[0]));
+                for (int k = 0; k < 3; ++k) ub[k] += eb * T(-3.0 * L::w[0]) * u[k];
+            } else {
+                const T cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+                pb += eb * T(3.0 * L::w[q]);
+                for (int k = 0; k < 3; ++k) ub[k] += eb * T(L::w[q]) * (T(3) * c[k] + T(9) * cu * c[k] - T(3) * u[k]);
+            }
+        }
+        // p = (s/3 - w0 |u|^2 / 2) / (1 - w0)
+        const T sb = pb * T(1.0 / (3.0 * (1.0 - L::w[0])));
+        for (int k = 0; k < 3; ++k) ub[k] += pb * T(-L::w[0] / (1.0 - L::w[0])) * u[k];
+        if (solid)
+            for (int k = 0; k < L::D; ++k) ub[k] += uext[3 * own + k];
+        if (L::D == 2) ub[2] = 0;
+        // u = j + a/2
+        for (int k = 0; k < 3; ++k) ab[k] += T(0.5) * ub[k];
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            fbar[q] += T(L::cx[q]) * ub[0] + T(L::cy[q]) * ub[1] + T(L::cz[q]) * ub[2] + (q > 0 ? sb : T(0));
+            // transpose of the pull: f_q(x) came from pull_offset(q, x)
+            lam_out[pull_offset<L>(q, idx, x, y, z, g, N)] = fbar[q];
+        }
+        if (solid) {
+            asol[idx] = (double)ab[0];
+            asol[N + idx] = (double)ab[1];
+            if (L::D == 3) asol[2 * N + idx] = (double)ab[2];
+        }
+        // dL/dtau through om = 1/tau, gamma = 1 - 1/(2 tau), and alpha = 1/tau
+        const double om2 = sp.omega * sp.omega;
+        tb = (double)omb * (-om2) + (double)gamb * (0.5 * om2);
+        if (pen && sp.alpha_tracks_tau) tb += (double)sigb * (-om2);
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = tb;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tau_part[blockIdx.x] += red[0];
+}
+
+// --------------------------------------------------------------- rigid adjoint
+struct AdjArrays {
+    const double *rec;   // step-n record [np][REC_STRIDE]
+    const double *Xbar;  // X_bar^{n+1}  [np*3]
+    const double *Abar;  // A_bar^{n+1}
+    const double *Upbar; // adjoint of U^n as the next step's U^{n-1}
+    double *Xbar_out;    // X_bar^n
+    double *Upbar_out;   // adjoint of U^{n-1}
+    double *uext_d;      // U_bar^n / N per particle (broadcast), [np*3]
+    float *uext_f;
+    double *acc_d; // a_i of step n
+    float *acc_f;
+    double *rho_g, *g_g; // accumulated partials per particle
+};
+
+__device__ __forceinline__ double particle_volume(int shape, double a, double b)
+{
+    if (shape == LBM_DISK) return M_PI * a * a;
+    if (shape == LBM_ELLIPSE) return M_PI * a * b;
+    return 4.0 / 3.0 * M_PI * a * a * a;
+}
+
+// J v for the pair-force Jacobian J = dT/dd of T(d) = (C/eps_p) s^2 d/|d|
+// (form 0) or (C/eps_p) s^2 d (form 1), s = (cut - |d|)/delta; J is symmetric.
+__device__ __forceinline__ void pair_jac_apply(double C, const double *d, double dist, double cut,
+                                               const RigidParams &rp, const double *v, double *out)
+{
+    const double k = C / rp.eps_p, s = (cut - dist) / rp.delta;
+    double dh[3] = {d[0] / dist, d[1] / dist, d[2] / dist};
+    double a1, a2;
+    if (rp.cform == 1) {
+        a2 = s * s;
+        a1 = -2.0 * s * dist / rp.delta;
+    } else {
+        a2 = s * s / dist;
+        a1 = -2.0 * s / rp.delta - s * s / dist;
+    }
+    const double dv = dh[0] * v[0] + dh[1] * v[1] + dh[2] * v[2];
+    for (int m = 0; m < 3; ++m) out[m] += k * (a1 * dv * dh[m] + a2 * v[m]);
+}
+
+__global__ __launch_bounds__(256) void k_adj_rigid(AdjArrays A, PartDev P, RigidParams rp, Geom g)
+{
+    const int j = blockIdx.x, d = rp.d, np = rp.np;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int per[3] = {g.per_x, g.per_y, g.per_z};
+    auto pos = [&](int i, int which, double *Y) {
+        const double *r = A.rec + REC_STRIDE * i;
+        for (int k = 0; k < 3; ++k) {
+            Y[k] = r[k];
+            if (which == 1 && k < d) Y[k] += 0.5 * (r[4 + k] + r[14 + k]); // prediction X + U_bar
+        }
+    };
+    auto fbar = [&](int i, double *F) {
+        const double *r = A.rec + REC_STRIDE * i;
+        const double Ni = r[13];
+        const double c = Ni > 0 ? 1.0 / (2.0 * P.rho_s[i] * Ni) : 0.0;
+        for (int k = 0; k < 3; ++k) F[k] = k < d ? 0.5 * c * (A.Xbar[3 * i + k] + 2.0 * A.Abar[3 * i + k]) : 0.0;
+    };
+    double Fj[3];
+    fbar(j, Fj);
+    const double Rj = P.a[j], Cj = P.Cc[j];
+    // per lane: acc[w][k] = sum_i (J_ji F_j - J_ij F_i) at positions w (0: X^n, 1: prediction),
+    // unit[w][k] = force on j per unit collision constant
+    double acc[2][3] = {{0, 0, 0}, {0, 0, 0}}, unit[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        if (i == j) continue;
+        double Fi[3];
+        fbar(i, Fi);
+        const double Ri = P.a[i], Ci = P.Cc[i], cut = Ri + Rj + rp.delta;
+        for (int w = 0; w < 2; ++w) {
+            double Yj[3], Yi[3], dv[3] = {0, 0, 0};
+            pos(j, w, Yj);
+            pos(i, w, Yi);
+            for (int k = 0; k < d; ++k) {
+                dv[k] = Yj[k] - Yi[k];
+                if (per[k]) {
+                    const double h = 0.5 * n[k];
+                    if (dv[k] > h) dv[k] -= n[k];
+                    else if (dv[k] < -h) dv[k] += n[k];
+                }
+            }
+            const double dist = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+            if (!(dist <= cut) || dist == 0.0) continue;
+            pair_jac_apply(Cj, dv, dist, cut, rp, Fj, acc[w]);
+            double neg[3] = {0, 0, 0};
+            pair_jac_apply(Ci, dv, dist, cut, rp, Fi, neg);
+            for (int k = 0; k < 3; ++k) acc[w][k] -= neg[k];
+            const double s = (cut - dist) / rp.delta;
+            const double sc = (rp.cform == 1 ? s * s : s * s / dist) / rp.eps_p;
+            for (int k = 0; k < 3; ++k) unit[w][k] += sc * dv[k];
+        }
+    }
+    __shared__ double red[12][256];
+    for (int w = 0; w < 2; ++w)
+        for (int k = 0; k < 3; ++k) {
+            red[w * 3 + k][threadIdx.x] = acc[w][k];
+            red[6 + w * 3 + k][threadIdx.x] = unit[w][k];
+        }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int m = 0; m < 12; ++m) red[m][threadIdx.x] += red[m][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    for (int w = 0; w < 2; ++w)
+        for (int k = 0; k < 3; ++k) {
+            acc[w][k] = red[w * 3 + k][0];
+            unit[w][k] = red[6 + w * 3 + k][0];
+        }
+    // walls through the mirror particle
+    for (int w = 0; w < 2; ++w) {
+        double Yj[3];
+        pos(j, w, Yj);
+        for (int k = 0; k < d; ++k) {
+            if (per[k]) continue;
+            const double walls[2] = {-0.5, n[k] - 0.5};
+            for (int s = 0; s < 2; ++s) {
+                const double dv = 2.0 * (Yj[k] - walls[s]);
+                const double dist = fabs(dv);
+                if (dist > 2.0 * Rj + rp.delta) continue;
+                const double qq = (2.0 * Rj + rp.delta - dist) / rp.delta;
+                const double kw = Cj / rp.eps_w;
+                double dT, tu;
+                if (rp.cform == 1) {
+                    dT = kw * (2.0 * qq * qq - 4.0 * qq * dist / rp.delta);
+                    tu = qq * qq * dv / rp.eps_w;
+                } else {
+                    dT = -4.0 * kw * qq / rp.delta;
+                    tu = qq * qq * (dv >= 0 ? 1.0 : -1.0) / rp.eps_w;
+                }
+                acc[w][k] += dT * Fj[k];
+                unit[w][k] += tu;
+            }
+        }
+    }
+    const double *rj = A.rec + REC_STRIDE * j;
+    const double Nj = rj[13], rho = P.rho_s[j];
+    const double cj = Nj > 0 ? 1.0 / (2.0 * rho * Nj) : 0.0;
+    double corrb_dot_F = 0.0, Cbar = 0.0;
+    double Xsb[3], Ubb[3];
+    for (int k = 0; k < 3; ++k) {
+        const double corrb = k < d ? A.Xbar[3 * j + k] + 2.0 * A.Abar[3 * j + k] : 0.0;
+        corrb_dot_F += corrb * 0.5 * Cj * (unit[0][k] + unit[1][k]);
+        Cbar += Fj[k] * (unit[0][k] + unit[1][k]);
+        Xsb[k] = k < d ? A.Xbar[3 * j + k] + acc[1][k] : 0.0;
+        A.Xbar_out[3 * j + k] = k < d ? Xsb[k] + acc[0][k] : 0.0;
+        Ubb[k] = Xsb[k];
+        A.Upbar_out[3 * j + k] = 0.5 * Ubb[k];
+        const double Unb = 0.5 * Ubb[k] + A.Upbar[3 * j + k];
+        const double ue = Nj > 0 ? Unb / Nj : 0.0;
+        A.uext_d[3 * j + k] = ue;
+        A.uext_f[3 * j + k] = (float)ue;
+    }
+    // c = 1/(2 rho N): dc/drho = -c/rho;  C = (rho - rho_f)|g| V (form 0) or (rho - rho_f)|g| (form 1)
+    const double V = rp.cform == 1 ? 1.0 : particle_volume(P.shape[j], P.a[j], P.b[j]);
+    A.rho_g[j] += corrb_dot_F * (-cj / rho) + Cbar * rp.gmag * V;
+    A.g_g[j] += Cbar * (rho - rp.rho_f) * V;
+    // acceleration of the particle's nodes during step n: b g + A^n
+    const double bj = rp.gform == 0 ? 1.0 - rp.rho_f / rho : rho / rp.rho_f - 1.0;
+    for (int k = 0; k < 3; ++k) {
+        const double acc_k = k < d ? bj * rp.g[k] + rj[10 + k] : 0.0;
+        A.acc_d[3 * j + k] = acc_k;
+        A.acc_f[3 * j + k] = (float)acc_k;
+    }
+}
+
+// ------------------------------------------------------------ particle adjoint
+// A_bar^n_i = sum of a_bar over the nodes of particle i (step n indicator);
+// a = b_i g + A_i gives the density and |g| partials.
+template <int D>
+__global__ __launch_bounds__(256) void k_adj_particles(const uint16_t *__restrict__ owner,
+                                                        const double *__restrict__ asol, const double *__restrict__ rec,
+                                                        PartDev P, RigidParams rp, Geom g, double *__restrict__ Abar_out,
+                                                        double *__restrict__ rho_g, double *__restrict__ g_g)
+{
+    const int i = blockIdx.x;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int per[3] = {g.per_x, g.per_y, g.per_z};
+    const double *r = rec + REC_STRIDE * i;
+    int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
+    const double R = P.a[i];
+    for (int k = 0; k < D; ++k) {
+        int l = (int)floor(r[k] - R) - 2, h = (int)ceil(r[k] + R) + 2;
+        if (!per[k]) {
+            l = l < 0 ? 0 : l;
+            h = h > n[k] - 1 ? n[k] - 1 : h;
+        }
+        lo[k] = l;
+        ext[k] = h - l + 1 > 0 ? h - l + 1 : 0;
+    }
+    const long cells = (long)ext[0] * ext[1] * ext[2];
+    const int N = (int)g.N;
+    double s[3] = {0, 0, 0};
+    for (long c = threadIdx.x; c < cells; c += blockDim.x) {
+        const int lx = (int)(c % ext[0]), ly = (int)((c / ext[0]) % ext[1]), lz = (int)(c / ((long)ext[0] * ext[1]));
+        const int x = wrap(lo[0] + lx, g.nx), y = wrap(lo[1] + ly, g.ny), z = wrap(lo[2] + lz, g.nz);
+        const int node = x + g.nx * (y + g.ny * z);
+        if (owner[node] != (uint16_t)i) continue;
+        for (int k = 0; k < D; ++k) s[k] += asol[(size_t)k * N + node];
+    }
+    __shared__ double red[3][256];
+    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double rho = P.rho_s[i];
+    const double bi = rp.gform == 0 ? 1.0 - rp.rho_f / rho : rho / rp.rho_f - 1.0;
+    const double dbdrho = rp.gform == 0 ? rp.rho_f / (rho * rho) : 1.0 / rp.rho_f;
+    double ag = 0.0, aghat = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        Abar_out[3 * i + k] = red[k][0];
+        ag += red[k][0] * rp.g[k];
+        aghat += rp.gmag > 0 ? red[k][0] * rp.g[k] / rp.gmag : 0.0;
+    }
+    rho_g[i] += ag * dbdrho;
+    g_g[i] += bi * aghat;
+}
+
+// U^{-1} = U^0 was measured with a = b g on every node of the particle:
+// dU^{-1}/da = 1/2 gives the density and |g| partials of the initial state.
+__global__ void k_adj_initial(PartDev P, RigidParams rp, const double *__restrict__ Upbar, double *__restrict__ rho_g,
+                              double *__restrict__ g_g)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rp.np) return;
+    const double rho = P.rho_s[i];
+    const double bi = rp.gform == 0 ? 1.0 - rp.rho_f / rho : rho / rp.rho_f - 1.0;
+    const double dbdrho = rp.gform == 0 ? rp.rho_f / (rho * rho) : 1.0 / rp.rho_f;
+    double ag = 0.0, aghat = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double ab = 0.5 * Upbar[3 * i + k];
+        ag += ab * rp.g[k];
+        aghat += rp.gmag > 0 ? ab * rp.g[k] / rp.gmag : 0.0;
+    }
+    rho_g[i] += ag * dbdrho;
+    g_g[i] += bi * aghat;
+}
+
+// ----------------------------------------------------------------- launchers
+hipError_t launch_adj_lattice(lbm_ctx *c, const void *fprev, const uint16_t *owner, const double *uext_d,
+                              const float *uext_f, const double *acc_d, const float *acc_f, const void *lam_in,
+                              void *lam_out, double *asol, double *tau_part)
+{
+    const int gx = (c->geo.nx + 255) / 256;
+    const unsigned blocks = (unsigned)gx * (unsigned)(c->geo.ny * c->geo.nz);
+    return dispatch(c, [&](auto L, auto S, auto T) {
+        using Lt = decltype(L);
+        using St = decltype(S);
+        using Tt = decltype(T);
+        const bool dbl = std::is_same<Tt, double>::value;
+        const Tt *acc = dbl ? (const Tt *)acc_d : (const Tt *)acc_f;
+        const Tt *uext = dbl ? (const Tt *)uext_d : (const Tt *)uext_f;
+        hipLaunchKernelGGL((k_adj_lattice<Lt, St, Tt>), dim3(blocks), dim3(256), 0, c->stream,
+                           (const typename St::raw *)fprev, owner, acc, uext, (const Tt *)lam_in, (Tt *)lam_out, asol,
+                           tau_part, c->geo, c->sp, gx);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_adj_rigid(lbm_ctx *c, const AdjArraysHost &h)
+{
+    if (c->np == 0) return hipSuccess;
+    AdjArrays A{h.rec, h.Xbar, h.Abar, h.Upbar, h.Xbar_out, h.Upbar_out, h.uext_d, h.uext_f, h.acc_d, h.acc_f,
+                h.rho_g, h.g_g};
+    RigidParams rp = c->rp;
+    rp.np = c->np;
+    hipLaunchKernelGGL(k_adj_rigid, dim3(c->np), dim3(256), 0, c->stream, A, c->P, rp, c->geo);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_particles(lbm_ctx *c, const uint16_t *owner, const double *asol, const double *rec,
+                                double *Abar_out, double *rho_g, double *g_g)
+{
+    if (c->np == 0) return hipSuccess;
+    RigidParams rp = c->rp;
+    rp.np = c->np;
+    if (c->d == 2)
+        hipLaunchKernelGGL(k_adj_particles<2>, dim3(c->np), dim3(256), 0, c->stream, owner, asol, rec, c->P, rp, c->geo,
+                           Abar_out, rho_g, g_g);
+    else
+        hipLaunchKernelGGL(k_adj_particles<3>, dim3(c->np), dim3(256), 0, c->stream, owner, asol, rec, c->P, rp, c->geo,
+                           Abar_out, rho_g, g_g);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_initial(lbm_ctx *c, const double *Upbar, double *rho_g, double *g_g)
+{
+    if (c->np == 0) return hipSuccess;
+    RigidParams rp = c->rp;
+    rp.np = c->np;
+    hipLaunchKernelGGL(k_adj_initial, dim3((c->np + 255) / 256), dim3(256), 0, c->stream, c->P, rp, Upbar, rho_g, g_g);
+    return hipGetLastError();
+}
+
+} // namespace lbm

@@ -175,6 +175,74 @@ void carve(lbm_ctx *c, const Layout &L)
 
 } // namespace
 
+// One step queues the lattice update, the momentum sums (which also clear the
+// indicator) and Algorithm 1 with the new indicator (K = 1; K > 1 adds the
+// sub-step integration before it).  With profiling on, each launch is
+// bracketed by a pair of pooled events whose durations are summed per class.
+int lbm::step_impl(lbm_ctx *c, int64_t nsteps, double *rec_dev)
+{
+    std::vector<std::pair<int, size_t>> used; // (kernel class, event pair index)
+    size_t next = 0;
+    auto timed = [&](int kind, hipError_t (*fn)(lbm_ctx *, void *), void *arg) -> hipError_t {
+        if (!c->prof) return fn(c, arg);
+        if (2 * next + 2 > c->ev_pool.size()) {
+            for (int k = 0; k < 64; ++k) {
+                hipEvent_t e;
+                hipError_t err = hipEventCreate(&e);
+                if (err != hipSuccess) return err;
+                c->ev_pool.push_back(e);
+            }
+        }
+        hipError_t err = hipEventRecord(c->ev_pool[2 * next], c->stream);
+        if (err != hipSuccess) return err;
+        err = fn(c, arg);
+        if (err != hipSuccess) return err;
+        err = hipEventRecord(c->ev_pool[2 * next + 1], c->stream);
+        used.push_back({kind, next});
+        ++next;
+        return err;
+    };
+    for (int64_t s = 0; s < nsteps; ++s) {
+        void *bufs[2] = {c->f[c->cur], c->f[c->cur ^ 1]};
+        HIPCHK(c, timed(0, [](lbm_ctx *cc, void *b) { return launch_stream_collide(cc, ((void **)b)[0], ((void **)b)[1]); },
+                        bufs));
+        c->cur ^= 1;
+        double *rec = rec_dev ? rec_dev + (size_t)s * c->np * REC_STRIDE : nullptr;
+        HIPCHK(c, timed(1, [](lbm_ctx *cc, void *r) { return launch_reduce(cc, 1, (double *)r); }, rec));
+        if (c->rp.K == 1) {
+            HIPCHK(c, timed(2, [](lbm_ctx *cc, void *) { return launch_rigid_raster(cc, 1); }, nullptr));
+            std::swap(c->P.X, c->P.Xn);
+        } else {
+            HIPCHK(c, timed(2, [](lbm_ctx *cc, void *) { return launch_rigid_substeps(cc); }, nullptr));
+            std::swap(c->P.X, c->P.Xn);
+            HIPCHK(c, timed(3, [](lbm_ctx *cc, void *) { return launch_rigid_raster(cc, 0); }, nullptr));
+        }
+        c->step++;
+        c->fresh = 0;
+        if (c->prof && next >= 512) { // bound the pool: drain what has been recorded
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            for (auto &u : used) {
+                float ms = 0.f;
+                HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[2 * u.second], c->ev_pool[2 * u.second + 1]));
+                c->prof_ms[u.first] += ms;
+                c->prof_cnt[u.first] += 1;
+            }
+            used.clear();
+            next = 0;
+        }
+    }
+    if (c->prof) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (auto &u : used) {
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[2 * u.second], c->ev_pool[2 * u.second + 1]));
+            c->prof_ms[u.first] += ms;
+            c->prof_cnt[u.first] += 1;
+        }
+    }
+    return LBM_OK;
+}
+
 extern "C" {
 
 int lbm_workspace_size(const lbm_config *cfg, size_t *bytes)
@@ -219,6 +287,9 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
         if (c->sp.fluid_acc[k] != 0.0) c->sp.has_fluid_acc = 1;
     }
     c->sp.penalize_all = cfg->penalize_all != 0;
+    c->sp.alpha_tracks_tau = !(cfg->alpha > 0);
+    c->grad = nullptr;
+    c->fresh = 0;
     c->rp.rho_f = cfg->rho_f;
     for (int k = 0; k < 3; ++k) c->rp.g[k] = k < d ? cfg->g[k] : 0.0;
     c->rp.gmag = sqrt(c->rp.g[0] * c->rp.g[0] + c->rp.g[1] * c->rp.g[1] + c->rp.g[2] * c->rp.g[2]);
@@ -290,6 +361,7 @@ int lbm_destroy(lbm_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     if (c->own_mem) (void)hipFree(c->ws);
     if (c->rec_dev) (void)hipFree(c->rec_dev);
+    free_grad(c);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
     return LBM_OK;
@@ -360,73 +432,8 @@ int lbm_set_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int i = 0; i < n; ++i)
         if (Nn[i] == 0) return fail(c, LBM_EINVAL, "a particle covers no lattice node");
-    return LBM_OK;
-}
-
-// One step queues the lattice update, the momentum sums (which also clear the
-// indicator) and Algorithm 1 with the new indicator (K = 1; K > 1 adds the
-// sub-step integration before it).  With profiling on, each launch is
-// bracketed by a pair of pooled events whose durations are summed per class.
-static int step_impl(lbm_ctx *c, int64_t nsteps, double *rec_dev)
-{
-    std::vector<std::pair<int, size_t>> used; // (kernel class, event pair index)
-    size_t next = 0;
-    auto timed = [&](int kind, hipError_t (*fn)(lbm_ctx *, void *), void *arg) -> hipError_t {
-        if (!c->prof) return fn(c, arg);
-        if (2 * next + 2 > c->ev_pool.size()) {
-            for (int k = 0; k < 64; ++k) {
-                hipEvent_t e;
-                hipError_t err = hipEventCreate(&e);
-                if (err != hipSuccess) return err;
-                c->ev_pool.push_back(e);
-            }
-        }
-        hipError_t err = hipEventRecord(c->ev_pool[2 * next], c->stream);
-        if (err != hipSuccess) return err;
-        err = fn(c, arg);
-        if (err != hipSuccess) return err;
-        err = hipEventRecord(c->ev_pool[2 * next + 1], c->stream);
-        used.push_back({kind, next});
-        ++next;
-        return err;
-    };
-    for (int64_t s = 0; s < nsteps; ++s) {
-        void *bufs[2] = {c->f[c->cur], c->f[c->cur ^ 1]};
-        HIPCHK(c, timed(0, [](lbm_ctx *cc, void *b) { return launch_stream_collide(cc, ((void **)b)[0], ((void **)b)[1]); },
-                        bufs));
-        c->cur ^= 1;
-        double *rec = rec_dev ? rec_dev + (size_t)s * c->np * 14 : nullptr;
-        HIPCHK(c, timed(1, [](lbm_ctx *cc, void *r) { return launch_reduce(cc, 1, (double *)r); }, rec));
-        if (c->rp.K == 1) {
-            HIPCHK(c, timed(2, [](lbm_ctx *cc, void *) { return launch_rigid_raster(cc, 1); }, nullptr));
-            std::swap(c->P.X, c->P.Xn);
-        } else {
-            HIPCHK(c, timed(2, [](lbm_ctx *cc, void *) { return launch_rigid_substeps(cc); }, nullptr));
-            std::swap(c->P.X, c->P.Xn);
-            HIPCHK(c, timed(3, [](lbm_ctx *cc, void *) { return launch_rigid_raster(cc, 0); }, nullptr));
-        }
-        c->step++;
-        if (c->prof && next >= 512) { // bound the pool: drain what has been recorded
-            HIPCHK(c, hipStreamSynchronize(c->stream));
-            for (auto &u : used) {
-                float ms = 0.f;
-                HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[2 * u.second], c->ev_pool[2 * u.second + 1]));
-                c->prof_ms[u.first] += ms;
-                c->prof_cnt[u.first] += 1;
-            }
-            used.clear();
-            next = 0;
-        }
-    }
-    if (c->prof) {
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        for (auto &u : used) {
-            float ms = 0.f;
-            HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[2 * u.second], c->ev_pool[2 * u.second + 1]));
-            c->prof_ms[u.first] += ms;
-            c->prof_cnt[u.first] += 1;
-        }
-    }
+    c->fresh = 1;
+    free_grad(c);
     return LBM_OK;
 }
 
@@ -441,7 +448,7 @@ int lbm_step_record(lbm_ctx *c, int64_t nsteps, double *host_rec)
 {
     if (!c || nsteps < 0 || (nsteps > 0 && !host_rec)) return c ? fail(c, LBM_EINVAL, "bad arguments") : LBM_EINVAL;
     (void)hipSetDevice(c->device);
-    const size_t need = (size_t)nsteps * std::max(c->np, 1) * 14 * sizeof(double);
+    const size_t need = (size_t)nsteps * std::max(c->np, 1) * REC_STRIDE * sizeof(double);
     if (need > c->rec_cap) {
         if (c->rec_dev) HIPCHK(c, hipFree(c->rec_dev));
         c->rec_dev = nullptr;
@@ -451,9 +458,14 @@ int lbm_step_record(lbm_ctx *c, int64_t nsteps, double *host_rec)
     }
     int rc = step_impl(c, nsteps, c->rec_dev);
     if (rc) return rc;
-    if (nsteps > 0 && c->np > 0)
-        HIPCHK(c, hipMemcpyAsync(host_rec, c->rec_dev, (size_t)nsteps * c->np * 14 * sizeof(double),
-                                 hipMemcpyDeviceToHost, c->stream));
+    if (nsteps > 0 && c->np > 0) {
+        std::vector<double> full((size_t)nsteps * c->np * REC_STRIDE);
+        HIPCHK(c, hipMemcpyAsync(full.data(), c->rec_dev, full.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (size_t r = 0; r < (size_t)nsteps * c->np; ++r)
+            for (int k = 0; k < 14; ++k) host_rec[r * 14 + k] = full[r * REC_STRIDE + k];
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return lbm_sync(c);
 }

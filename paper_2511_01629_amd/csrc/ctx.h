@@ -9,7 +9,14 @@
 
 #include "../../include/lbm.h"
 
+// Checkpoint storage of a differentiated run (grad.hip).
+struct GradState;
+
 namespace lbm {
+
+// Per-step, per-particle record written by the momentum-sum kernel:
+// X[3] theta U^n[3] omega^n[3] A^n[3] N U^{n-1}[3] (pad to 20 doubles).
+constexpr int REC_STRIDE = 20;
 
 // Device arrays of the particle state, structure-of-arrays, FP64.
 struct PartDev {
@@ -36,7 +43,21 @@ struct StepParams {
     double fluid_acc[3];
     int has_fluid_acc;
     int penalize_all;
+    int alpha_tracks_tau; // alpha = 1/tau (the default) rather than a fixed value
 };
+
+// Device pointers of one backward step of Algorithm 1 (see adjoint.hip).
+struct AdjArraysHost {
+    const double *rec, *Xbar, *Abar, *Upbar;
+    double *Xbar_out, *Upbar_out, *uext_d;
+    float *uext_f;
+    double *acc_d;
+    float *acc_f;
+    double *rho_g, *g_g;
+};
+
+// Periodic index wrap for an index at most one period out of range.
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 struct RigidParams {
     double rho_f, gmag, g[3];
@@ -69,6 +90,9 @@ struct lbm_ctx {
     double *rec_dev;
     size_t rec_cap;
     std::vector<lbm_particle> host_parts; // inputs of the last lbm_set_particles
+    // differentiated run (lbm_forward_checkpointed / lbm_backward)
+    GradState *grad;
+    int fresh; // no step since the last lbm_set_particles
     // per-kernel event timing (lbm_profile)
     int prof;
     std::vector<hipEvent_t> ev_pool;
@@ -93,5 +117,18 @@ hipError_t launch_rigid_raster(lbm_ctx *c, int update);
 hipError_t launch_rigid_substeps(lbm_ctx *c);
 hipError_t launch_owner_to_int(lbm_ctx *c, int32_t *out);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+// adjoint.hip
+hipError_t launch_adj_lattice(lbm_ctx *c, const void *fprev, const uint16_t *owner, const double *uext_d,
+                              const float *uext_f, const double *acc_d, const float *acc_f, const void *lam_in,
+                              void *lam_out, double *asol, double *tau_part);
+hipError_t launch_adj_rigid(lbm_ctx *c, const AdjArraysHost &h);
+hipError_t launch_adj_particles(lbm_ctx *c, const uint16_t *owner, const double *asol, const double *rec,
+                                double *Abar_out, double *rho_g, double *g_g);
+hipError_t launch_adj_initial(lbm_ctx *c, const double *Upbar, double *rho_g, double *g_g);
+
+// api.hip (shared with grad.hip)
+int step_impl(lbm_ctx *c, int64_t nsteps, double *rec_dev);
+void free_grad(lbm_ctx *c);
 
 } // namespace lbm

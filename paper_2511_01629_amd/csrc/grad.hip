@@ -1,0 +1,229 @@
+// grad.hip -- differentiated runs: forward with checkpoints, then the
+// hand-written adjoint swept backwards segment by segment.
+//
+// Forward (lbm_forward_checkpointed): every `every` steps the whole state is
+// snapshotted (post-collision populations, indicator, particle arrays), and
+// every step's particle record is kept on the device.
+// Backward (lbm_backward): for each segment from the last, restore its
+// snapshot and recompute its steps, storing each step's input populations and
+// indicator; then run the adjoint steps of the segment in reverse.  All
+// kernels are deterministic, so the recomputed states are bitwise those of the
+// forward run.  At the end the final forward state is restored.
+#include <algorithm>
+#include <vector>
+
+#include "ctx.h"
+
+using namespace lbm;
+
+struct GradState {
+    int64_t T = 0;
+    int every = 0, nsnap = 0;
+    size_t fbytes = 0, obytes = 0, pbytes = 0;
+    char *snap = nullptr;  // nsnap x (fbytes + obytes + pbytes)
+    std::vector<PartDev> snapP;
+    std::vector<int> snapCur;
+    std::vector<int64_t> snapStep;
+    double *rec = nullptr; // T x np x REC_STRIDE
+};
+
+namespace {
+
+#define HIPCHK(c, expr)                                                                                                \
+    do {                                                                                                               \
+        hipError_t e_ = (expr);                                                                                        \
+        if (e_ != hipSuccess) {                                                                                        \
+            (c)->err = std::string(#expr) + ": " + hipGetErrorString(e_);                                              \
+            return LBM_EDEVICE;                                                                                        \
+        }                                                                                                              \
+    } while (0)
+
+size_t storage_bytes(int s) { return s == LBM_F64 ? 8 : s == LBM_F32 ? 4 : 2; }
+
+// The particle arrays occupy one contiguous region of the workspace, from
+// P.X's block start (the first double array) to the end of the int block.
+char *part_base(lbm_ctx *c) { return (char *)std::min(c->P.X, c->P.Xn); }
+size_t part_bytes(lbm_ctx *c) { return (size_t)((char *)(c->P.hi + 3 * c->cap) - part_base(c)); }
+
+int snapshot(lbm_ctx *c, GradState *G, int k)
+{
+    char *dst = G->snap + (size_t)k * (G->fbytes + G->obytes + G->pbytes);
+    HIPCHK(c, hipMemcpyAsync(dst, c->f[c->cur], G->fbytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dst + G->fbytes, c->owner, G->obytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dst + G->fbytes + G->obytes, part_base(c), G->pbytes, hipMemcpyDeviceToDevice, c->stream));
+    G->snapP[k] = c->P;
+    G->snapCur[k] = c->cur;
+    G->snapStep[k] = c->step;
+    return LBM_OK;
+}
+
+int restore(lbm_ctx *c, GradState *G, int k)
+{
+    const char *src = G->snap + (size_t)k * (G->fbytes + G->obytes + G->pbytes);
+    c->P = G->snapP[k];
+    c->cur = G->snapCur[k];
+    c->step = G->snapStep[k];
+    HIPCHK(c, hipMemcpyAsync(c->f[c->cur], src, G->fbytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->owner, src + G->fbytes, G->obytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(part_base(c), src + G->fbytes + G->obytes, G->pbytes, hipMemcpyDeviceToDevice, c->stream));
+    return LBM_OK;
+}
+
+template <class Tp> int dev_alloc(lbm_ctx *c, Tp **p, size_t n, std::vector<void *> &owned)
+{
+    HIPCHK(c, hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(Tp)));
+    owned.push_back(*p);
+    HIPCHK(c, hipMemsetAsync(*p, 0, std::max<size_t>(n, 1) * sizeof(Tp), c->stream));
+    return LBM_OK;
+}
+
+} // namespace
+
+void lbm::free_grad(lbm_ctx *c)
+{
+    if (!c->grad) return;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->grad->snap) (void)hipFree(c->grad->snap);
+    if (c->grad->rec) (void)hipFree(c->grad->rec);
+    delete c->grad;
+    c->grad = nullptr;
+}
+
+extern "C" {
+
+int lbm_forward_checkpointed(lbm_ctx *c, int64_t nsteps, int32_t every)
+{
+    if (!c) return LBM_EINVAL;
+    if (nsteps < 1 || every < 1) return c->err = "nsteps and every must be >= 1", LBM_EINVAL;
+    if (!c->fresh) return c->err = "a differentiated run must start right after lbm_set_particles", LBM_ESTATE;
+    if (c->np == 0) return c->err = "no particles", LBM_ESTATE;
+    if (c->rp.K != 1) return c->err = "the adjoint of Algorithm 1 is implemented for K = 1", LBM_EINVAL;
+    (void)hipSetDevice(c->device);
+    free_grad(c);
+    GradState *G = new GradState();
+    c->grad = G;
+    G->T = nsteps;
+    G->every = every;
+    G->nsnap = (int)((nsteps + every - 1) / every) + 1; // segment starts + final state
+    G->fbytes = (size_t)c->Q * c->geo.N * storage_bytes(c->cfg.storage);
+    G->obytes = (size_t)((c->geo.N + 1) / 2 * 2) * sizeof(uint16_t);
+    G->pbytes = part_bytes(c);
+    G->snapP.resize(G->nsnap);
+    G->snapCur.resize(G->nsnap);
+    G->snapStep.resize(G->nsnap);
+    HIPCHK(c, hipMalloc((void **)&G->snap, (size_t)G->nsnap * (G->fbytes + G->obytes + G->pbytes)));
+    HIPCHK(c, hipMalloc((void **)&G->rec, (size_t)nsteps * c->np * REC_STRIDE * sizeof(double)));
+    for (int64_t s = 0; s < nsteps; ++s) {
+        if (s % every == 0) {
+            int rc = snapshot(c, G, (int)(s / every));
+            if (rc) return rc;
+        }
+        int rc = step_impl(c, 1, G->rec + (size_t)s * c->np * REC_STRIDE);
+        if (rc) return rc;
+    }
+    int rc = snapshot(c, G, G->nsnap - 1);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return lbm_sync(c);
+}
+
+int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau, double *g_gmag)
+{
+    if (!c || !dL_dX) return LBM_EINVAL;
+    GradState *G = c->grad;
+    if (!G) return c->err = "no differentiated forward run to go back through", LBM_ESTATE;
+    (void)hipSetDevice(c->device);
+    const int np = c->np, Q = c->Q;
+    const int64_t N = c->geo.N;
+    const size_t lam_elt = c->cfg.storage == LBM_F64 ? 8 : 4;
+    const int gx = (c->geo.nx + 255) / 256;
+    const size_t nblocks = (size_t)gx * c->geo.ny * c->geo.nz;
+    std::vector<void *> owned;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(c->stream);
+        for (void *p : owned) (void)hipFree(p);
+    };
+    char *seg = nullptr, *lam = nullptr;
+    double *asol = nullptr, *taup = nullptr, *Xbar = nullptr, *Abar = nullptr, *Upbar = nullptr, *rho_g = nullptr,
+           *g_g = nullptr, *uext_d = nullptr, *acc_d = nullptr;
+    float *uext_f = nullptr, *acc_f = nullptr;
+    const size_t segb = G->fbytes + G->obytes;
+    int rc = LBM_OK;
+    if ((rc = dev_alloc(c, &seg, (size_t)G->every * segb, owned)) || (rc = dev_alloc(c, &lam, 2 * Q * N * lam_elt, owned)) ||
+        (rc = dev_alloc(c, &asol, (size_t)c->d * N, owned)) || (rc = dev_alloc(c, &taup, nblocks, owned)) ||
+        (rc = dev_alloc(c, &Xbar, 6 * (size_t)np, owned)) || (rc = dev_alloc(c, &Abar, 3 * (size_t)np, owned)) ||
+        (rc = dev_alloc(c, &Upbar, 6 * (size_t)np, owned)) || (rc = dev_alloc(c, &rho_g, np, owned)) ||
+        (rc = dev_alloc(c, &g_g, np, owned)) || (rc = dev_alloc(c, &uext_d, 3 * (size_t)np, owned)) ||
+        (rc = dev_alloc(c, &acc_d, 3 * (size_t)np, owned)) || (rc = dev_alloc(c, &uext_f, 3 * (size_t)np, owned)) ||
+        (rc = dev_alloc(c, &acc_f, 3 * (size_t)np, owned))) {
+        cleanup();
+        return rc;
+    }
+    // seed: X_bar^T = dL/dX_final; everything else zero
+    std::vector<double> seed(3 * (size_t)np, 0.0);
+    for (int i = 0; i < np; ++i)
+        for (int k = 0; k < c->d; ++k) seed[3 * i + k] = dL_dX[3 * i + k];
+    if (hipMemcpyAsync(Xbar, seed.data(), seed.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+        cleanup();
+        return c->err = "seed copy failed", LBM_EDEVICE;
+    }
+    int cx = 0, cu = 0, cl = 0; // which half of the ping-pong adjoint buffers is current
+    const int nseg = G->nsnap - 1;
+    for (int sg = nseg - 1; sg >= 0 && rc == LBM_OK; --sg) {
+        const int64_t s0 = (int64_t)sg * G->every, s1 = std::min<int64_t>(s0 + G->every, G->T);
+        if ((rc = restore(c, G, sg))) break;
+        for (int64_t n = s0; n < s1 && rc == LBM_OK; ++n) {
+            char *slot = seg + (size_t)(n - s0) * segb;
+            if (hipMemcpyAsync(slot, c->f[c->cur], G->fbytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+                hipMemcpyAsync(slot + G->fbytes, c->owner, G->obytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+                rc = LBM_EDEVICE;
+                break;
+            }
+            rc = step_impl(c, 1, nullptr);
+        }
+        for (int64_t n = s1 - 1; n >= s0 && rc == LBM_OK; --n) {
+            const char *slot = seg + (size_t)(n - s0) * segb;
+            const uint16_t *own_n = (const uint16_t *)(slot + G->fbytes);
+            const double *rec_n = G->rec + (size_t)n * np * REC_STRIDE;
+            AdjArraysHost h{rec_n, Xbar + 3 * np * cx, Abar, Upbar + 3 * np * cu, Xbar + 3 * np * (cx ^ 1),
+                            Upbar + 3 * np * (cu ^ 1), uext_d, uext_f, acc_d, acc_f, rho_g, g_g};
+            if (launch_adj_rigid(c, h) != hipSuccess) rc = LBM_EDEVICE;
+            cx ^= 1;
+            cu ^= 1;
+            char *lin = lam + (size_t)cl * Q * N * lam_elt, *lout = lam + (size_t)(cl ^ 1) * Q * N * lam_elt;
+            if (rc == LBM_OK && launch_adj_lattice(c, slot, own_n, uext_d, uext_f, acc_d, acc_f, lin, lout, asol, taup) !=
+                                    hipSuccess)
+                rc = LBM_EDEVICE;
+            cl ^= 1;
+            if (rc == LBM_OK && launch_adj_particles(c, own_n, asol, rec_n, Abar, rho_g, g_g) != hipSuccess)
+                rc = LBM_EDEVICE;
+        }
+    }
+    if (rc == LBM_OK && launch_adj_initial(c, Upbar + 3 * np * cu, rho_g, g_g) != hipSuccess) rc = LBM_EDEVICE;
+    std::vector<double> hr(np), hg(np), ht(nblocks);
+    if (rc == LBM_OK) {
+        if (hipMemcpyAsync(hr.data(), rho_g, np * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipMemcpyAsync(hg.data(), g_g, np * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipMemcpyAsync(ht.data(), taup, nblocks * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            rc = LBM_EDEVICE;
+    }
+    if (rc == LBM_OK) {
+        double gt = 0.0, gg = 0.0;
+        for (size_t b = 0; b < nblocks; ++b) gt += ht[b];
+        for (int i = 0; i < np; ++i) gg += hg[i];
+        if (g_rho_s)
+            for (int i = 0; i < np; ++i) g_rho_s[i] = hr[i];
+        if (g_tau) *g_tau = gt;
+        if (g_gmag) *g_gmag = gg;
+    }
+    int rr = restore(c, G, G->nsnap - 1);
+    cleanup();
+    if (rc != LBM_OK) {
+        if (c->err.empty()) c->err = "adjoint kernel launch failed";
+        return rc;
+    }
+    return rr;
+}
+
+} // extern "C"

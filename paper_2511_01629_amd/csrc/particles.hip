@@ -42,7 +42,6 @@ __device__ __forceinline__ bool inside_shape(int shape, double a, double b, doub
     return dadd(dmul(dmul(b, b), dmul(xi, xi)), dmul(dmul(a, a), dmul(eta, eta))) <= dmul(dmul(a, a), dmul(b, b));
 }
 
-__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 // 16-bit atomic minimum through a 32-bit compare-and-swap on the aligned word.
 __device__ __forceinline__ void atomic_min_u16(uint16_t *addr, uint16_t val)
@@ -102,7 +101,7 @@ __global__ __launch_bounds__(256) void k_raster_clear(uint16_t *__restrict__ own
 // this clears the whole indicator for the next rasterisation -- and the
 // quantities Algorithm 1 needs are prepared: U_bar = (U^n + U^{n-1})/2,
 // dtheta = (omega^n + omega^{n-1})/2, then U^{n-1} <- U^n, omega^{n-1} <- omega^n.
-// rec (optional) receives X theta U omega A N of the step.
+// rec (optional) receives the step's record (layout REC_STRIDE in ctx.h).
 template <int D, bool STEP>
 __global__ __launch_bounds__(256) void k_reduce(uint16_t *__restrict__ owner, const double *__restrict__ usol,
                                                  PartDev P, Geom g, double *__restrict__ rec)
@@ -192,12 +191,13 @@ __global__ __launch_bounds__(256) void k_reduce(uint16_t *__restrict__ owner, co
     }
     if (STEP) {
         if (rec) {
-            double *r = rec + 14 * i;
+            double *r = rec + REC_STRIDE * i;
             for (int k = 0; k < 3; ++k) {
                 r[k] = P.X[3 * i + k];
                 r[4 + k] = U[k];
                 r[7 + k] = W[k];
                 r[10 + k] = P.A[3 * i + k];
+                r[14 + k] = P.Uprev[3 * i + k];
             }
             r[3] = P.theta[i];
             r[13] = (double)cnt;

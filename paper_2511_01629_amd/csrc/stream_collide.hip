@@ -12,173 +12,10 @@
 // The owner map (uint16, FLUID = 0xFFFF) selects the solid branch; a
 // wavefront with no solid node never executes it.  Solid nodes also write
 // their velocity (FP64) for the per-particle momentum sums.
-#include "ctx.h"
-#include "lattice.h"
+#include "dispatch.h"
+#include "node.h"
 
 namespace lbm {
-
-template <class L>
-__device__ __forceinline__ void coords(int idx, const Geom &g, int &x, int &y, int &z)
-{
-    if (L::D == 2) {
-        y = idx / g.nx;
-        x = idx - y * g.nx;
-        z = 0;
-    } else {
-        int row = idx / g.nx;
-        x = idx - row * g.nx;
-        z = row / g.ny;
-        y = row - z * g.ny;
-    }
-}
-
-// Source offset of population q pulled into node (x,y,z): the neighbour
-// x - c_q (wrapped on periodic axes) or, behind a wall, the opposite
-// population of the node itself.
-template <class L>
-__device__ __forceinline__ int pull_offset(int q, int idx, int x, int y, int z, const Geom &g, int N)
-{
-    int sx = x - L::cx[q], sy = y - L::cy[q], sz = z - L::cz[q];
-    bool wall = false;
-    if (L::cx[q] != 0) {
-        if (sx < 0) {
-            if (g.per_x) sx += g.nx; else wall = true;
-        } else if (sx >= g.nx) {
-            if (g.per_x) sx -= g.nx; else wall = true;
-        }
-    }
-    if (L::cy[q] != 0) {
-        if (sy < 0) {
-            if (g.per_y) sy += g.ny; else wall = true;
-        } else if (sy >= g.ny) {
-            if (g.per_y) sy -= g.ny; else wall = true;
-        }
-    }
-    if (L::D == 3 && L::cz[q] != 0) {
-        if (sz < 0) {
-            if (g.per_z) sz += g.nz; else wall = true;
-        } else if (sz >= g.nz) {
-            if (g.per_z) sz -= g.nz; else wall = true;
-        }
-    }
-    return wall ? L::opp[q] * N + idx : q * N + (sx + g.nx * (sy + g.ny * sz));
-}
-
-template <class L, class S, class T>
-__device__ __forceinline__ void pull(const typename S::raw *__restrict__ fin, int idx, int x, int y, int z,
-                                     const Geom &g, int N, T *f)
-{
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) f[q] = ld<S, T>(fin + pull_offset<L>(q, idx, x, y, z, g, N));
-}
-
-// u = sum f c + a/2 and p = (cs^2 sum_{q>0} f - w0 |u|^2 / 2)/(1 - w0)  (eq. 15a-b)
-template <class L, class T>
-__device__ __forceinline__ void moments(const T *f, T ax, T ay, T az, T &ux, T &uy, T &uz, T &p)
-{
-    T jx = 0, jy = 0, jz = 0, s = 0;
-#pragma unroll
-    for (int q = 1; q < L::Q; ++q) {
-        if (L::cx[q] > 0) jx += f[q];
-        if (L::cx[q] < 0) jx -= f[q];
-        if (L::cy[q] > 0) jy += f[q];
-        if (L::cy[q] < 0) jy -= f[q];
-        if (L::cz[q] > 0) jz += f[q];
-        if (L::cz[q] < 0) jz -= f[q];
-        s += f[q];
-    }
-    ux = jx + T(0.5) * ax;
-    uy = jy + T(0.5) * ay;
-    uz = (L::D == 3) ? jz + T(0.5) * az : T(0);
-    const T uu = ux * ux + uy * uy + uz * uz;
-    constexpr double w0 = L::w[0];
-    p = (T(1.0 / 3.0) * s - T(0.5 * w0) * uu) * T(1.0 / (1.0 - w0));
-}
-
-// f^eq_q of eq. (13) with cs^2 = 1/3: q = 0: -(1-w0) 3p - w0 1.5|u|^2;
-// q > 0: w_q (3p + 3 c.u + 4.5 (c.u)^2 - 1.5|u|^2)
-template <class L, class T>
-__device__ __forceinline__ T feq_q(int q, T p3, T cu, T u15)
-{
-    if (q == 0) return T(-(1.0 - L::w[0])) * p3 - T(L::w[0]) * u15;
-    return T(L::w[q]) * (p3 + T(3) * cu + T(4.5) * cu * cu - u15);
-}
-
-// Collision of one node, in place: f holds the pulled populations on entry
-// and f~ on return (right side of eq. 10 with F of eq. 14 and, on solid
-// nodes, S of eq. 17).  Writes the velocity of solid nodes for the sums.
-template <class L, class T>
-__device__ __forceinline__ void collide_node(T *f, uint16_t own, const T *__restrict__ acc_tab, const StepParams &sp,
-                                             int32_t *__restrict__ flags, double *__restrict__ usol, int idx, int N)
-{
-    const bool solid = own != FLUID;
-    T ax = 0, ay = 0, az = 0;
-    if (solid) {
-        ax = acc_tab[3 * own + 0];
-        ay = acc_tab[3 * own + 1];
-        az = acc_tab[3 * own + 2];
-    } else if (sp.has_fluid_acc) {
-        ax = (T)sp.fluid_acc[0];
-        ay = (T)sp.fluid_acc[1];
-        az = (T)sp.fluid_acc[2];
-    }
-    T ux, uy, uz, p;
-    moments<L, T>(f, ax, ay, az, ux, uy, uz, p);
-    const T uu = ux * ux + uy * uy + uz * uz;
-    if (!(uu < T(0.09))) flags[0] = 1; // |u| > 0.3 or not finite
-    const T om = (T)sp.omega;
-    const T p3 = T(3) * p, u15 = T(1.5) * uu;
-
-    const bool pen = solid || sp.penalize_all;
-    const bool frc = solid || sp.has_fluid_acc;
-    if (!pen && !frc) {
-#pragma unroll
-        for (int q = 0; q < L::Q; ++q) {
-            const T cu = T(L::cx[q]) * ux + T(L::cy[q]) * uy + T(L::cz[q]) * uz;
-            f[q] = f[q] - om * (f[q] - feq_q<L, T>(q, p3, cu, u15));
-        }
-        return;
-    }
-    // solid (or forced) node
-    T fneq[L::Q];
-    T Pxx = 0, Pyy = 0, Pzz = 0, Pxy = 0, Pxz = 0, Pyz = 0;
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) {
-        const T cu = T(L::cx[q]) * ux + T(L::cy[q]) * uy + T(L::cz[q]) * uz;
-        fneq[q] = f[q] - feq_q<L, T>(q, p3, cu, u15);
-        if (L::cx[q] != 0) Pxx += fneq[q];
-        if (L::cy[q] != 0) Pyy += fneq[q];
-        if (L::cz[q] != 0) Pzz += fneq[q];
-        if (L::cx[q] * L::cy[q] > 0) Pxy += fneq[q];
-        if (L::cx[q] * L::cy[q] < 0) Pxy -= fneq[q];
-        if (L::cx[q] * L::cz[q] > 0) Pxz += fneq[q];
-        if (L::cx[q] * L::cz[q] < 0) Pxz -= fneq[q];
-        if (L::cy[q] * L::cz[q] > 0) Pyz += fneq[q];
-        if (L::cy[q] * L::cz[q] < 0) Pyz -= fneq[q];
-    }
-    const T al = pen ? (T)sp.alpha : T(0);
-    const T trace3 = (Pxx + Pyy + Pzz) * T(1.0 / 3.0);
-    const T gpre = T(1) - T(0.5) * om;
-    const T ua = ux * ax + uy * ay + uz * az;
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) {
-        const T cx = T(L::cx[q]), cy = T(L::cy[q]), cz = T(L::cz[q]);
-        // S_q = alpha w_q / (2 cs^4) Pi^neq : (c c - cs^2 I)   (eq. 17)
-        const T PiCC = cx * cx * Pxx + cy * cy * Pyy + cz * cz * Pzz +
-                       T(2) * (cx * cy * Pxy + cx * cz * Pxz + cy * cz * Pyz);
-        const T Sq = al * T(4.5 * L::w[q]) * (PiCC - trace3);
-        // F_q = (1 - 1/(2 tau)) w_q [3 (c - u).a + 9 (c.u)(c.a)]   (eq. 14)
-        const T cu = cx * ux + cy * uy + cz * uz;
-        const T ca = cx * ax + cy * ay + cz * az;
-        const T F = gpre * T(L::w[q]) * (T(3) * (ca - ua) + T(9) * cu * ca);
-        f[q] = f[q] - om * fneq[q] + F + Sq;
-    }
-    if (solid) {
-        usol[idx] = (double)ux;
-        usol[N + idx] = (double)uy;
-        if (L::D == 3) usol[2 * N + idx] = (double)uz;
-    }
-}
 
 // The lattice update, one node per lane.  Each workgroup covers 256
 // consecutive nodes of one row (fixed y, z), so the row and the wall tests of
@@ -328,27 +165,6 @@ __global__ __launch_bounds__(256) void k_init_uniform(typename S::raw *__restric
             if ((t < 0 || t >= n[k]) && !per[k]) out = true;
         }
         st<S, T>(fout + (size_t)q * N + idx, (T)(out ? fe.v[L::opp[q]] : fe.v[q]));
-    }
-}
-
-// ------------------------------------------------------------------ dispatch
-
-template <class F>
-static hipError_t dispatch(lbm_ctx *c, F &&fn)
-{
-    if (c->cfg.lattice == LBM_D2Q9) {
-        switch (c->cfg.storage) {
-        case LBM_F64: return fn(D2Q9{}, StF64{}, double{});
-        case LBM_F32: return fn(D2Q9{}, StF32{}, float{});
-        case LBM_F16: return fn(D2Q9{}, StF16{}, float{});
-        default: return fn(D2Q9{}, StBF16{}, float{});
-        }
-    }
-    switch (c->cfg.storage) {
-    case LBM_F64: return fn(D3Q19{}, StF64{}, double{});
-    case LBM_F32: return fn(D3Q19{}, StF32{}, float{});
-    case LBM_F16: return fn(D3Q19{}, StF16{}, float{});
-    default: return fn(D3Q19{}, StBF16{}, float{});
     }
 }
 

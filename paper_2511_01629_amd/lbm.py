@@ -24,7 +24,8 @@ CODES = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "EUNSTABLE
 
 EXPORTS = ["lbm_workspace_size", "lbm_create", "lbm_destroy", "lbm_set_particles", "lbm_step", "lbm_step_record",
            "lbm_sync", "lbm_get_fields", "lbm_get_populations", "lbm_set_populations", "lbm_get_particles",
-           "lbm_get_step", "lbm_last_error", "lbm_profile", "lbm_profile_read", "lbm_copy"]
+           "lbm_get_step", "lbm_last_error", "lbm_profile", "lbm_profile_read", "lbm_copy",
+           "lbm_forward_checkpointed", "lbm_backward"]
 
 
 class LbmUnavailable(RuntimeError):
@@ -87,6 +88,8 @@ def load():
     lib.lbm_profile.argtypes = [P, I32]
     lib.lbm_profile_read.argtypes = [P, dp, C.POINTER(C.c_int64), I32]
     lib.lbm_copy.argtypes = [P, P, C.c_size_t, P]
+    lib.lbm_forward_checkpointed.argtypes = [P, I64, I32]
+    lib.lbm_backward.argtypes = [P, dp, dp, dp, dp]
     _LIB = lib
     return lib
 
@@ -216,6 +219,20 @@ class Simulation:
         s = C.c_int64()
         self._check(self.lib.lbm_get_step(self.ctx, C.byref(s)))
         return s.value
+
+    def forward_checkpointed(self, nsteps, every):
+        self._check(self.lib.lbm_forward_checkpointed(self.ctx, int(nsteps), int(every)))
+
+    def backward(self, dL_dX):
+        """Gradients (d rho_s [n], d tau, d |g|) of a loss whose gradient with
+        respect to the final centres is dL_dX (n x 3)."""
+        seed = np.ascontiguousarray(np.asarray(dL_dX, dtype=np.float64).reshape(self.np, 3))
+        g_rho = np.zeros(max(self.np, 1))
+        g_tau = C.c_double()
+        g_g = C.c_double()
+        self._check(self.lib.lbm_backward(self.ctx, seed.ctypes.data_as(C.POINTER(C.c_double)),
+                                          g_rho.ctypes.data_as(C.POINTER(C.c_double)), C.byref(g_tau), C.byref(g_g)))
+        return g_rho[: self.np], g_tau.value, g_g.value
 
     KERNELS = ("stream_collide", "reduce_clear", "rigid_raster", "raster_after_substeps")
 

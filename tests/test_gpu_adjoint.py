@@ -1,0 +1,126 @@
+"""The hand-written adjoint against the oracle's complex-step derivative.
+
+Both differentiate the step map with the indicator sequence frozen; the
+complex-step oracle is exact to rounding, so in FP64 storage the adjoint
+gradient must agree to near rounding.  Loss: a weighted sum of the final
+centres (weights seeded), parameters: each rho_s, tau and |g|.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import banner
+from oracle import oracle as O
+from paper_2511_01629_amd import lbm
+from paper_2511_01629_amd.workloads import place
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_gradient(cfg, parts, steps, w):
+    """Complex-step derivative of L = sum(w * X_final) for each parameter."""
+    npart = len(parts)
+    out = []
+    for k in range(npart + 2):
+        seed = dict(d_rho_s=[0.0] * npart, d_tau=0.0, d_gmag=0.0, h=1e-30)
+        if k < npart:
+            seed["d_rho_s"][k] = 1.0
+        elif k == npart:
+            seed["d_tau"] = 1.0
+        else:
+            seed["d_gmag"] = 1.0
+        o = O.Oracle(cfg, parts, complex_step=seed)
+        o.step(steps)
+        Xi = o.particles(imag=True)["X"]
+        out.append(float((w * Xi).sum() / seed["h"]))
+    return np.array(out)
+
+
+def gpu_gradient(cfg, parts, steps, every, w, storage="f64"):
+    sim = lbm.Simulation(cfg, parts, storage=storage)
+    sim.forward_checkpointed(steps, every)
+    X_end = sim.particles()["X"].copy()
+    f_end = sim.populations()
+    g_rho, g_tau, g_g = sim.backward(w)
+    # the final state is restored after the sweep
+    assert np.array_equal(sim.populations(), f_end) and np.array_equal(sim.particles()["X"], X_end)
+    again = sim.backward(w)
+    assert np.array_equal(again[0], g_rho) and again[1] == g_tau and again[2] == g_g  # deterministic
+    return np.concatenate([g_rho, [g_tau, g_g]])
+
+
+def _check(ga, go, tol):
+    scale = np.abs(go).max()
+    err = np.abs(ga - go) / np.maximum(np.abs(go), 1e-3 * scale)
+    print(f"[measured] max rel err {err.max():.3e}", flush=True)
+    for a, o in zip(ga, go):
+        print(f"   adjoint {a: .10e}  oracle {o: .10e}", flush=True)
+    assert err.max() < tol, err
+
+
+def test_adjoint_2d_contacts_f64():
+    banner("adjoint 2d contacts f64")
+    kinds = [("disk", 5.0, 5.0)] * 3 + [("ellipse", 6.0, 3.0)]
+    parts = place((48, 64), kinds, seed=31, rho_range=(1.3, 1.8), upper_axis=1, gap=0.3, margin=0.3)
+    cfg = dict(lattice="D2Q9", n=(48, 64, 1), periodic=(0, 0, 0), tau=0.65, g=(0.0, -3e-4, 0.0))
+    w = np.random.default_rng(5).normal(size=(len(parts), 3))
+    w[:, 2] = 0.0
+    steps = 60
+    go = oracle_gradient(cfg, parts, steps, w)
+    ga = gpu_gradient(cfg, parts, steps, 16, w)
+    _check(ga, go, 1e-8)
+
+
+def test_adjoint_2d_periodic_mean_height_f64():
+    """The mean-height loss of the differentiated workload on a small box, x periodic."""
+    banner("adjoint 2d periodic f64")
+    parts = place((40, 72), [("disk", 6.0, 6.0)] * 3, seed=32, rho_range=(1.2, 1.6), upper_axis=1, gap=0.5,
+                  margin=0.3)
+    cfg = dict(lattice="D2Q9", n=(40, 72, 1), periodic=(1, 0, 0), tau=0.7, g=(0.0, -2e-4, 0.0))
+    w = np.zeros((len(parts), 3))
+    w[:, 1] = 1.0 / len(parts)
+    go = oracle_gradient(cfg, parts, 50, w)
+    ga = gpu_gradient(cfg, parts, 50, 50, w)
+    _check(ga, go, 1e-8)
+
+
+def test_adjoint_3d_f64():
+    banner("adjoint 3d f64")
+    parts = place((20, 18, 26), [("sphere", 3.5, 3.5)] * 3, seed=33, rho_range=(1.3, 1.7), upper_axis=2, gap=0.4,
+                  margin=0.3)
+    cfg = dict(lattice="D3Q19", n=(20, 18, 26), periodic=(0, 1, 0), tau=0.7, g=(0.0, 0.0, -3e-4))
+    w = np.random.default_rng(6).normal(size=(len(parts), 3))
+    go = oracle_gradient(cfg, parts, 30, w)
+    ga = gpu_gradient(cfg, parts, 30, 7, w)
+    _check(ga, go, 1e-8)
+
+
+def test_adjoint_2d_f32_storage():
+    """FP32 storage and arithmetic (FP64 particle adjoint): the gradient of the
+    same loss within the stated relative bound."""
+    banner("adjoint 2d f32")
+    parts = place((40, 72), [("disk", 6.0, 6.0)] * 3, seed=32, rho_range=(1.2, 1.6), upper_axis=1, gap=0.5,
+                  margin=0.3)
+    cfg = dict(lattice="D2Q9", n=(40, 72, 1), periodic=(1, 0, 0), tau=0.7, g=(0.0, -2e-4, 0.0))
+    w = np.zeros((len(parts), 3))
+    w[:, 1] = 1.0 / len(parts)
+    go = oracle_gradient(cfg, parts, 50, w)
+    ga = gpu_gradient(cfg, parts, 50, 10, w, storage="f32")
+    _check(ga, go, 1e-3)
+
+
+def test_adjoint_rejects_bad_use():
+    banner("adjoint errors")
+    parts = [dict(shape="disk", rho_s=1.5, a=5.0, x=(20.0, 30.0, 0.0))]
+    cfg = dict(lattice="D2Q9", n=(40, 60, 1), tau=0.7, g=(0.0, -1e-4, 0.0))
+    sim = lbm.Simulation(cfg, parts, storage="f32")
+    with pytest.raises(lbm.LbmError) as e:
+        sim.backward(np.zeros((1, 3)))
+    assert e.value.code == lbm.LBM_ESTATE
+    sim.step(1)
+    with pytest.raises(lbm.LbmError) as e:
+        sim.forward_checkpointed(5, 2)
+    assert e.value.code == lbm.LBM_ESTATE
+    sim2 = lbm.Simulation(dict(cfg, K=2), parts, storage="f32")
+    with pytest.raises(lbm.LbmError) as e:
+        sim2.forward_checkpointed(5, 2)
+    assert e.value.code == lbm.LBM_EINVAL
