@@ -100,6 +100,44 @@ def run_mode(name, storage, steps, warmup, profile=True):
     return out
 
 
+def run_adjoint(name, storage, every):
+    """Forward with checkpoints + hand-written adjoint on the differentiated
+    workload; fwd+adj MLUPS counts each node-step once."""
+    import torch
+
+    import numpy as np
+
+    from paper_2511_01629_amd import lbm
+    from paper_2511_01629_amd.workloads import workload
+
+    cfg, parts, steps, _ = workload(name)
+    sim = lbm.Simulation(cfg, parts, storage=storage, device=0)
+    N = sim.N
+    seed = np.zeros((len(parts), 3))
+    seed[:, 1] = 1.0 / len(parts)
+    st = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record(st)
+    sim.forward_checkpointed(steps, every)
+    e1.record(st)
+    g_rho, g_tau, g_g = sim.backward(seed)
+    e2.record(st)
+    torch.cuda.synchronize()
+    t_f, t_b = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    mlups = N * steps / ((t_f + t_b) * 1e-3) / 1e6
+    # algorithmic bytes per node-step: forward 2 Q s, adjoint 2 Q 4 + d 4 (lambda in/out, u);
+    # the recomputation of each segment is a checkpointing cost and is not credited
+    alg = 2 * 9 * STORAGE_BYTES[storage] + 2 * 9 * 4 + 2 * 4
+    return dict(workload=name, storage=storage, steps=steps, checkpoint_every=every, ms_forward=t_f,
+                ms_backward=t_b, mlups=mlups, alg_bytes_per_node_step=alg,
+                frac=mlups * 1e6 * alg / (HBM_PEAK_GBS * 1e9), grad_tau=g_tau, grad_gmag=g_g,
+                grad_rho_s_first=float(g_rho[0]))
+
+
 def copy_ceiling(nbytes=2 << 30, reps=20):
     import torch
 
@@ -181,6 +219,12 @@ def main():
             modes[f"{name}/{storage}"] = {k: r[k] for k in ("mlups", "ms_per_step", "kernel_gbs", "kernel_frac",
                                                              "kernel_avg_us", "breakdown_us")}
             log(f"  {r['mlups']:.0f} MLUPS, fused kernel {r['kernel_gbs']:.0f} GB/s")
+    if not args.no_modes:
+        log("forward + adjoint adjoint_512x1024 f32 (5000 steps, checkpoint every 100)")
+        adj = run_adjoint("adjoint_512x1024", "f32", 100)
+        modes["adjoint_512x1024/f32/fwd+adj"] = adj
+        log(f"  {adj['mlups']:.0f} MLUPS fwd+adj ({adj['ms_forward']:.0f} ms forward, {adj['ms_backward']:.0f} ms "
+            f"backward), {adj['frac']:.3f} of roofline")
     log("copy ceiling")
     ceiling = copy_ceiling()
     log(f"  {ceiling:.0f} GB/s")

@@ -124,3 +124,30 @@ def test_adjoint_rejects_bad_use():
     with pytest.raises(lbm.LbmError) as e:
         sim2.forward_checkpointed(5, 2)
     assert e.value.code == lbm.LBM_EINVAL
+
+
+def test_autograd_wrapper_matches_oracle():
+    """torch.autograd over the checkpointed run: loss.backward() gives the
+    complex-step oracle gradient of the mean final height."""
+    banner("autograd wrapper")
+    import torch
+
+    from paper_2511_01629_amd.autograd import Run, mean_height_loss
+
+    parts = place((40, 72), [("disk", 6.0, 6.0)] * 3, seed=32, rho_range=(1.2, 1.6), upper_axis=1, gap=0.5,
+                  margin=0.3)
+    cfg = dict(lattice="D2Q9", n=(40, 72, 1), periodic=(1, 0, 0), tau=0.7, g=(0.0, -2e-4, 0.0))
+    run = Run(cfg=cfg, particles=parts, steps=50, every=8, storage="f64")
+    rho = torch.tensor([p["rho_s"] for p in parts], dtype=torch.float64, requires_grad=True)
+    tau = torch.tensor(0.7, dtype=torch.float64, requires_grad=True)
+    gmag = torch.tensor(2e-4, dtype=torch.float64, requires_grad=True)
+    loss = mean_height_loss(rho, tau, gmag, run)
+    loss.backward()
+    w = np.zeros((3, 3))
+    w[:, 1] = 1.0 / 3
+    go = oracle_gradient(cfg, parts, 50, w)
+    ga = np.concatenate([rho.grad.numpy(), [tau.grad.item(), gmag.grad.item()]])
+    _check(ga, go, 1e-8)
+    o = O.Oracle(cfg, parts)
+    o.step(50)
+    assert abs(loss.item() - o.particles()["X"][:, 1].mean()) < 1e-10
