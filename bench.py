@@ -220,11 +220,12 @@ def main():
                                                              "kernel_avg_us", "breakdown_us")}
             log(f"  {r['mlups']:.0f} MLUPS, fused kernel {r['kernel_gbs']:.0f} GB/s")
     if not args.no_modes:
-        log("forward + adjoint adjoint_512x1024 f32 (5000 steps, checkpoint every 100)")
-        adj = run_adjoint("adjoint_512x1024", "f32", 100)
-        modes["adjoint_512x1024/f32/fwd+adj"] = adj
-        log(f"  {adj['mlups']:.0f} MLUPS fwd+adj ({adj['ms_forward']:.0f} ms forward, {adj['ms_backward']:.0f} ms "
-            f"backward), {adj['frac']:.3f} of roofline")
+        log("forward + adjoint adjoint_512x1024 f32 (5000 steps; checkpoint every 100, and every step kept)")
+        for every in (100, 1):
+            adj = run_adjoint("adjoint_512x1024", "f32", every)
+            modes[f"adjoint_512x1024/f32/fwd+adj/every{every}"] = adj
+            log(f"  every {every}: {adj['mlups']:.0f} MLUPS fwd+adj ({adj['ms_forward']:.0f} ms forward, "
+                f"{adj['ms_backward']:.0f} ms backward), {adj['frac']:.3f} of roofline")
     log("copy ceiling")
     ceiling = copy_ceiling()
     log(f"  {ceiling:.0f} GB/s")

@@ -132,8 +132,8 @@ void feq_host(int lattice, double p, const double u[3], double *out)
 void carve(lbm_ctx *c, const Layout &L)
 {
     char *base = (char *)c->ws;
-    c->f[0] = base + L.f0;
-    c->f[1] = base + L.f1;
+    c->f[0] = c->fws[0] = base + L.f0;
+    c->f[1] = c->fws[1] = base + L.f1;
     c->owner = (uint16_t *)(base + L.owner);
     c->usol = (double *)(base + L.usol);
     c->staging = (double *)(base + L.staging);

@@ -78,8 +78,10 @@ struct lbm_ctx {
     bool own_mem;
     void *ws;
     size_t ws_bytes;
-    void *f[2]; // post-collision populations f~ (ping-pong), [Q][N] raw storage
-    int cur;    // f[cur] holds f~ of the last completed step
+    void *f[2];   // post-collision populations f~ (ping-pong), [Q][N] raw storage
+    int cur;      // f[cur] holds f~ of the last completed step
+    void *fws[2]; // the workspace's two population buffers (f[] points elsewhere only
+                  // inside a differentiated run)
     uint16_t *owner;
     double *usol;    // [d][N] velocity on solid nodes (written by the fused kernel)
     double *staging; // [4][N] doubles for field/population transfers

@@ -1,14 +1,21 @@
 // grad.hip -- differentiated runs: forward with checkpoints, then the
 // hand-written adjoint swept backwards segment by segment.
 //
-// Forward (lbm_forward_checkpointed): every `every` steps the whole state is
-// snapshotted (post-collision populations, indicator, particle arrays), and
-// every step's particle record is kept on the device.
-// Backward (lbm_backward): for each segment from the last, restore its
-// snapshot and recompute its steps, storing each step's input populations and
-// indicator; then run the adjoint steps of the segment in reverse.  All
-// kernels are deterministic, so the recomputed states are bitwise those of the
-// forward run.  At the end the final forward state is restored.
+// Every adjoint step n needs the populations that entered step n and the
+// indicator of step n ("frame" n), plus the step's particle record.
+//
+// every > 1: the forward run snapshots the whole state (populations,
+// indicator, particle arrays) every `every` steps.  The backward pass restores
+// a segment's snapshot into the first of every + 1 population frames and
+// recomputes the segment with the lattice kernel reading frame n and writing
+// frame n + 1 directly (no copies), keeping each step's indicator; then it runs
+// the segment's adjoint steps in reverse.  All kernels are deterministic, so
+// the recomputed frames are bitwise those of the forward run.
+//
+// every == 1: the forward run itself writes every frame (T + 1 population
+// buffers and T indicators -- e.g. 100 GB for 5000 steps of a 512x1024 FP32
+// lattice, which 288 GB of HBM holds), and the backward pass recomputes
+// nothing.
 #include <algorithm>
 #include <vector>
 
@@ -21,6 +28,7 @@ struct GradState {
     int every = 0, nsnap = 0;
     size_t fbytes = 0, obytes = 0, pbytes = 0;
     char *snap = nullptr;  // nsnap x (fbytes + obytes + pbytes)
+    char *hist = nullptr;  // every == 1: (T + 1) population frames, then T indicators
     std::vector<PartDev> snapP;
     std::vector<int> snapCur;
     std::vector<int64_t> snapStep;
@@ -57,13 +65,14 @@ int snapshot(lbm_ctx *c, GradState *G, int k)
     return LBM_OK;
 }
 
-int restore(lbm_ctx *c, GradState *G, int k)
+// Restore snapshot k; its populations go to fdst (NULL: the live buffer).
+int restore(lbm_ctx *c, GradState *G, int k, void *fdst = nullptr)
 {
     const char *src = G->snap + (size_t)k * (G->fbytes + G->obytes + G->pbytes);
     c->P = G->snapP[k];
     c->cur = G->snapCur[k];
     c->step = G->snapStep[k];
-    HIPCHK(c, hipMemcpyAsync(c->f[c->cur], src, G->fbytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(fdst ? fdst : c->f[c->cur], src, G->fbytes, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->owner, src + G->fbytes, G->obytes, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(part_base(c), src + G->fbytes + G->obytes, G->pbytes, hipMemcpyDeviceToDevice, c->stream));
     return LBM_OK;
@@ -84,6 +93,7 @@ void lbm::free_grad(lbm_ctx *c)
     if (!c->grad) return;
     (void)hipStreamSynchronize(c->stream);
     if (c->grad->snap) (void)hipFree(c->grad->snap);
+    if (c->grad->hist) (void)hipFree(c->grad->hist);
     if (c->grad->rec) (void)hipFree(c->grad->rec);
     delete c->grad;
     c->grad = nullptr;
@@ -108,11 +118,35 @@ int lbm_forward_checkpointed(lbm_ctx *c, int64_t nsteps, int32_t every)
     G->fbytes = (size_t)c->Q * c->geo.N * storage_bytes(c->cfg.storage);
     G->obytes = (size_t)((c->geo.N + 1) / 2 * 2) * sizeof(uint16_t);
     G->pbytes = part_bytes(c);
+    HIPCHK(c, hipMalloc((void **)&G->rec, (size_t)nsteps * c->np * REC_STRIDE * sizeof(double)));
+    if (every == 1) {
+        // keep every frame: the lattice kernel of step n reads frame n and writes frame n+1
+        HIPCHK(c, hipMalloc((void **)&G->hist, (size_t)(nsteps + 1) * G->fbytes + (size_t)nsteps * G->obytes));
+        char *fr = G->hist, *ow = G->hist + (size_t)(nsteps + 1) * G->fbytes;
+        HIPCHK(c, hipMemcpyAsync(fr, c->f[c->cur], G->fbytes, hipMemcpyDeviceToDevice, c->stream));
+        for (int64_t s = 0; s < nsteps; ++s) {
+            c->f[c->cur] = fr + (size_t)s * G->fbytes;
+            c->f[c->cur ^ 1] = fr + (size_t)(s + 1) * G->fbytes;
+            HIPCHK(c, hipMemcpyAsync(ow + (size_t)s * G->obytes, c->owner, G->obytes, hipMemcpyDeviceToDevice,
+                                     c->stream));
+            int rc = step_impl(c, 1, G->rec + (size_t)s * c->np * REC_STRIDE);
+            if (rc) {
+                c->f[0] = c->fws[0];
+                c->f[1] = c->fws[1];
+                return rc;
+            }
+        }
+        const void *last = c->f[c->cur];
+        c->f[0] = c->fws[0];
+        c->f[1] = c->fws[1];
+        HIPCHK(c, hipMemcpyAsync(c->f[c->cur], last, G->fbytes, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return lbm_sync(c);
+    }
     G->snapP.resize(G->nsnap);
     G->snapCur.resize(G->nsnap);
     G->snapStep.resize(G->nsnap);
     HIPCHK(c, hipMalloc((void **)&G->snap, (size_t)G->nsnap * (G->fbytes + G->obytes + G->pbytes)));
-    HIPCHK(c, hipMalloc((void **)&G->rec, (size_t)nsteps * c->np * REC_STRIDE * sizeof(double)));
     for (int64_t s = 0; s < nsteps; ++s) {
         if (s % every == 0) {
             int rc = snapshot(c, G, (int)(s / every));
@@ -147,9 +181,11 @@ int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau
     double *asol = nullptr, *taup = nullptr, *Xbar = nullptr, *Abar = nullptr, *Upbar = nullptr, *rho_g = nullptr,
            *g_g = nullptr, *uext_d = nullptr, *acc_d = nullptr;
     float *uext_f = nullptr, *acc_f = nullptr;
-    const size_t segb = G->fbytes + G->obytes;
+    const bool all = G->hist != nullptr;
+    // segment frames: every + 1 population buffers, then every indicators
+    const size_t segsize = all ? 1 : (size_t)(G->every + 1) * G->fbytes + (size_t)G->every * G->obytes;
     int rc = LBM_OK;
-    if ((rc = dev_alloc(c, &seg, (size_t)G->every * segb, owned)) || (rc = dev_alloc(c, &lam, 2 * Q * N * lam_elt, owned)) ||
+    if ((rc = dev_alloc(c, &seg, segsize, owned)) || (rc = dev_alloc(c, &lam, 2 * Q * N * lam_elt, owned)) ||
         (rc = dev_alloc(c, &asol, (size_t)c->d * N, owned)) || (rc = dev_alloc(c, &taup, nblocks, owned)) ||
         (rc = dev_alloc(c, &Xbar, 6 * (size_t)np, owned)) || (rc = dev_alloc(c, &Abar, 3 * (size_t)np, owned)) ||
         (rc = dev_alloc(c, &Upbar, 6 * (size_t)np, owned)) || (rc = dev_alloc(c, &rho_g, np, owned)) ||
@@ -168,22 +204,34 @@ int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau
         return c->err = "seed copy failed", LBM_EDEVICE;
     }
     int cx = 0, cu = 0, cl = 0; // which half of the ping-pong adjoint buffers is current
-    const int nseg = G->nsnap - 1;
+    const int64_t span = all ? G->T : G->every;
+    const int nseg = all ? 1 : G->nsnap - 1;
     for (int sg = nseg - 1; sg >= 0 && rc == LBM_OK; --sg) {
-        const int64_t s0 = (int64_t)sg * G->every, s1 = std::min<int64_t>(s0 + G->every, G->T);
-        if ((rc = restore(c, G, sg))) break;
-        for (int64_t n = s0; n < s1 && rc == LBM_OK; ++n) {
-            char *slot = seg + (size_t)(n - s0) * segb;
-            if (hipMemcpyAsync(slot, c->f[c->cur], G->fbytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
-                hipMemcpyAsync(slot + G->fbytes, c->owner, G->obytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
-                rc = LBM_EDEVICE;
-                break;
+        const int64_t s0 = (int64_t)sg * span, s1 = std::min<int64_t>(s0 + span, G->T);
+        char *fr, *ow; // frame n - s0 of populations / indicators
+        if (all) {
+            fr = G->hist;
+            ow = G->hist + (size_t)(G->T + 1) * G->fbytes;
+        } else {
+            fr = seg;
+            ow = seg + (size_t)(G->every + 1) * G->fbytes;
+            if ((rc = restore(c, G, sg, fr))) break;
+            for (int64_t n = s0; n < s1 && rc == LBM_OK; ++n) {
+                c->f[c->cur] = fr + (size_t)(n - s0) * G->fbytes;
+                c->f[c->cur ^ 1] = fr + (size_t)(n - s0 + 1) * G->fbytes;
+                if (hipMemcpyAsync(ow + (size_t)(n - s0) * G->obytes, c->owner, G->obytes, hipMemcpyDeviceToDevice,
+                                   c->stream) != hipSuccess) {
+                    rc = LBM_EDEVICE;
+                    break;
+                }
+                rc = step_impl(c, 1, nullptr);
             }
-            rc = step_impl(c, 1, nullptr);
+            c->f[0] = c->fws[0];
+            c->f[1] = c->fws[1];
         }
         for (int64_t n = s1 - 1; n >= s0 && rc == LBM_OK; --n) {
-            const char *slot = seg + (size_t)(n - s0) * segb;
-            const uint16_t *own_n = (const uint16_t *)(slot + G->fbytes);
+            const char *fprev = fr + (size_t)(n - s0) * G->fbytes;
+            const uint16_t *own_n = (const uint16_t *)(ow + (size_t)(n - s0) * G->obytes);
             const double *rec_n = G->rec + (size_t)n * np * REC_STRIDE;
             AdjArraysHost h{rec_n, Xbar + 3 * np * cx, Abar, Upbar + 3 * np * cu, Xbar + 3 * np * (cx ^ 1),
                             Upbar + 3 * np * (cu ^ 1), uext_d, uext_f, acc_d, acc_f, rho_g, g_g};
@@ -191,8 +239,8 @@ int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau
             cx ^= 1;
             cu ^= 1;
             char *lin = lam + (size_t)cl * Q * N * lam_elt, *lout = lam + (size_t)(cl ^ 1) * Q * N * lam_elt;
-            if (rc == LBM_OK && launch_adj_lattice(c, slot, own_n, uext_d, uext_f, acc_d, acc_f, lin, lout, asol, taup) !=
-                                    hipSuccess)
+            if (rc == LBM_OK &&
+                launch_adj_lattice(c, fprev, own_n, uext_d, uext_f, acc_d, acc_f, lin, lout, asol, taup) != hipSuccess)
                 rc = LBM_EDEVICE;
             cl ^= 1;
             if (rc == LBM_OK && launch_adj_particles(c, own_n, asol, rec_n, Abar, rho_g, g_g) != hipSuccess)
@@ -217,7 +265,9 @@ int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau
         if (g_tau) *g_tau = gt;
         if (g_gmag) *g_gmag = gg;
     }
-    int rr = restore(c, G, G->nsnap - 1);
+    c->f[0] = c->fws[0];
+    c->f[1] = c->fws[1];
+    int rr = all ? LBM_OK : restore(c, G, G->nsnap - 1);
     cleanup();
     if (rc != LBM_OK) {
         if (c->err.empty()) c->err = "adjoint kernel launch failed";

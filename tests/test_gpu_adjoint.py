@@ -70,16 +70,18 @@ def test_adjoint_2d_contacts_f64():
     _check(ga, go, 1e-8)
 
 
-def test_adjoint_2d_periodic_mean_height_f64():
-    """The mean-height loss of the differentiated workload on a small box, x periodic."""
-    banner("adjoint 2d periodic f64")
+@pytest.mark.parametrize("every", [50, 7, 1])
+def test_adjoint_2d_periodic_mean_height_f64(every):
+    """The mean-height loss of the differentiated workload on a small box, x
+    periodic; one segment, uneven segments, and every frame kept (every = 1)."""
+    banner(f"adjoint 2d periodic f64 every={every}")
     parts = place((40, 72), [("disk", 6.0, 6.0)] * 3, seed=32, rho_range=(1.2, 1.6), upper_axis=1, gap=0.5,
                   margin=0.3)
     cfg = dict(lattice="D2Q9", n=(40, 72, 1), periodic=(1, 0, 0), tau=0.7, g=(0.0, -2e-4, 0.0))
     w = np.zeros((len(parts), 3))
     w[:, 1] = 1.0 / len(parts)
     go = oracle_gradient(cfg, parts, 50, w)
-    ga = gpu_gradient(cfg, parts, 50, 50, w)
+    ga = gpu_gradient(cfg, parts, 50, every, w)
     _check(ga, go, 1e-8)
 
 
