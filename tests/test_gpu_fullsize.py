@@ -1,0 +1,74 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times (the library picks the same kernels; only the step count is short).
+
+The oracle runs the same steps; the indicator is compared on every node, the
+particle state in full, the populations on a seeded sample of nodes plus every
+solid node.  FP64 storage: within 1e-12 relative; FP32 storage: within the
+bound of a few steps of FP32 rounding.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import banner, check_owner, pair, rel
+from paper_2511_01629_amd.workloads import workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _compare(name, storage, steps, tol, nsample=200_000, u_atol=0.0, f_atol=0.0):
+    cfg, parts, _, _ = workload(name)
+    banner(f"full size {name} {storage} {steps} steps")
+    sim, ora = pair(cfg, parts, storage=storage)
+    rg = sim.step_record(steps)
+    ro = ora.step(steps, record=True)
+    # particle records of every step
+    assert np.array_equal(rg[:, :, 13], ro[:, :, 13])  # node counts
+    assert np.abs(rg[:, :, 0:3] - ro[:, :, 0:3]).max() <= tol * np.abs(ro[:, :, 0:3]).max()
+    Usc = np.abs(ro[:, :, 4:7]).max()
+    if Usc > 0:
+        assert np.abs(rg[:, :, 4:7] - ro[:, :, 4:7]).max() <= max(10 * tol * Usc, u_atol)
+    # indicator on every node (boundary ties allowed)
+    _, _, og = sim.fields()
+    uo, po, oo = ora.fields()
+    Po = ora.particles()
+    check_owner(og, oo, parts, Po, cfg.get("periodic", (0, 0, 0)))
+    # populations on a sample of nodes and on all solid nodes
+    fg, fo = sim.populations(), ora.f()
+    flat_g = fg.reshape(-1, fg.shape[-1])
+    flat_o = fo.reshape(-1, fo.shape[-1])
+    rng = np.random.default_rng(2024)
+    idx = np.unique(np.concatenate([rng.integers(0, flat_o.shape[0], nsample), np.flatnonzero(oo.reshape(-1) >= 0)]))
+    e = rel(flat_g[idx], flat_o[idx])
+    ea = float(np.abs(flat_g[idx] - flat_o[idx]).max())
+    print(f"[measured] {name} {storage}: population max rel err {e:.3e}, abs {ea:.3e} on {idx.size} nodes",
+          flush=True)
+    assert e < tol or ea <= f_atol
+    return sim, ora
+
+
+def test_fullsize_sedimentation_f64():
+    _compare("sedimentation_2048x4096", "f64", 3, 1e-12)
+
+
+def test_fullsize_sedimentation_f32():
+    _compare("sedimentation_2048x4096", "f32", 3, 2e-6)
+
+
+def test_fullsize_sedimentation_f16():
+    """FP16 storage right after the start: the bodies move at ~1e-6 and the
+    populations they set in motion (~1e-7) sit among FP16 subnormals (spacing
+    6e-8), so populations and velocities are compared with absolute bounds of a
+    few FP16 quanta."""
+    _compare("sedimentation_2048x4096", "f16", 2, 2e-3, u_atol=4e-7, f_atol=2.4e-7)
+
+
+def test_fullsize_spheres_f32():
+    _compare("spheres_256x256x512", "f32", 2, 2e-6, nsample=100_000)
+
+
+def test_fullsize_adjoint_workload_f64():
+    _compare("adjoint_512x1024", "f64", 100, 1e-12)
+
+
+def test_fullsize_disk_settling_f64():
+    _compare("disk_settling_400x1600", "f64", 100, 1e-12)
