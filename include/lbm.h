@@ -22,7 +22,8 @@
  * Conventions shared by every call:
  *   - Every function returns an int status: LBM_OK (0) or a negative code
  *     below.  Nothing aborts or throws across the ABI.  lbm_last_error gives
- *     a message for the last failing call on a context.
+ *     a message for the last failing call on a context (NULL: of the last
+ *     failed lbm_create or lbm_workspace_size on the calling thread).
  *   - Pointers named `host_*` or documented as host memory are read or written
  *     by the CPU; the library never keeps them after the call returns.
  *   - Lattice units: node (i, j, k) sits at (i, j, k); a wall axis has walls at
@@ -184,8 +185,8 @@ int lbm_backward(lbm_ctx *ctx, const double *dL_dX, double *g_rho_s, double *g_t
  * last reset (reset = 1 clears them afterwards).  Classes, in order:
  * 0 stream-collide-penalize, 1 momentum sums (with the indicator clear),
  * 2 Algorithm 1 with the new indicator (K = 1) or the sub-step integration
- * (K > 1), 3 the indicator after sub-steps (K > 1 only).
- * host arrays of LBM_NKERNELS. */
+ * (K > 1), 3 the indicator after sub-steps (K > 1 only).  host_ms and
+ * host_count are host arrays of LBM_NKERNELS. */
 #define LBM_NKERNELS 4
 int lbm_profile(lbm_ctx *ctx, int32_t enable);
 int lbm_profile_read(lbm_ctx *ctx, double *host_ms, int64_t *host_count, int32_t reset);
@@ -199,7 +200,8 @@ int lbm_copy(void *dst, const void *src, size_t bytes, void *stream);
 /* Number of completed steps. */
 int lbm_get_step(const lbm_ctx *ctx, int64_t *step);
 
-/* Message for the last failing call on ctx (never NULL). */
+/* Message for the last failing call on ctx (never NULL).  With ctx = NULL:
+ * the last lbm_workspace_size or lbm_create failure on the calling thread. */
 const char *lbm_last_error(const lbm_ctx *ctx);
 
 #ifdef __cplusplus

@@ -26,6 +26,7 @@
 //                   the density and |g| partials through a = b g + A.
 #include "dispatch.h"
 #include "node.h"
+#include "reduce.h"
 
 namespace lbm {
 
@@ -185,14 +186,10 @@ __global__ __launch_bounds__(256) void k_adj_lattice(const typename S::raw *__re
         tb = (double)omb * (-om2) + (double)gamb * (0.5 * om2);
         if (pen && sp.alpha_tracks_tau) tb += (double)sigb * (-om2);
     }
-    __shared__ double red[256];
-    red[threadIdx.x] = tb;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) tau_part[blockIdx.x] += red[0];
+    __shared__ double part[256 / WAVE][1];
+    double s[1] = {tb};
+    block_sum<1, 256>(s, part);
+    if (threadIdx.x == 0) tau_part[blockIdx.x] += s[0];
 }
 
 // --------------------------------------------------------------- rigid adjoint
@@ -236,85 +233,87 @@ __device__ __forceinline__ void pair_jac_apply(double C, const double *d, double
     for (int m = 0; m < 3; ++m) out[m] += k * (a1 * dv * dh[m] + a2 * v[m]);
 }
 
-__global__ __launch_bounds__(256) void k_adj_rigid(AdjArrays A, PartDev P, RigidParams rp, Geom g)
+// What the transposed Algorithm 1 needs of one particle in step n: its centre
+// X^n (Y[0]) and prediction X^n + U_bar^n (Y[1]), the adjoint of its
+// correction F_bar = c (X_bar + 2 A_bar)/2 with c = 1/(2 rho N), its radius
+// and collision constant.
+struct AdjBody {
+    double Y[2][3];
+    double F[3];
+    double R, C;
+};
+
+__device__ __forceinline__ void adj_positions(const double *r, int d, AdjBody &b)
 {
-    const int j = blockIdx.x, d = rp.d, np = rp.np;
+    for (int k = 0; k < 3; ++k) {
+        b.Y[0][k] = r[k];
+        b.Y[1][k] = r[k] + (k < d ? 0.5 * (r[4 + k] + r[14 + k]) : 0.0);
+    }
+}
+
+__device__ __forceinline__ void adj_force_bar(const double *Xb, const double *Ab, double Ni, double rho, int d, double *F)
+{
+    const double c = Ni > 0 ? 1.0 / (2.0 * rho * Ni) : 0.0;
+    for (int k = 0; k < 3; ++k) F[k] = k < d ? 0.5 * c * (Xb[k] + 2.0 * Ab[k]) : 0.0;
+}
+
+// Partner i's share of particle j's adjoint: acc[w] += J_ji F_j - J_ij F_i at
+// positions w (0: X^n, 1: prediction), unit[w] += the pair force on j per
+// unit collision constant.
+__device__ __forceinline__ void adj_pair(const AdjBody &bj, const AdjBody &bi, const RigidParams &rp, const Geom &g,
+                                         double acc[2][3], double unit[2][3])
+{
     const int n[3] = {g.nx, g.ny, g.nz};
     const int per[3] = {g.per_x, g.per_y, g.per_z};
-    auto pos = [&](int i, int which, double *Y) {
-        const double *r = A.rec + REC_STRIDE * i;
-        for (int k = 0; k < 3; ++k) {
-            Y[k] = r[k];
-            if (which == 1 && k < d) Y[k] += 0.5 * (r[4 + k] + r[14 + k]); // prediction X + U_bar
-        }
-    };
-    auto fbar = [&](int i, double *F) {
-        const double *r = A.rec + REC_STRIDE * i;
-        const double Ni = r[13];
-        const double c = Ni > 0 ? 1.0 / (2.0 * P.rho_s[i] * Ni) : 0.0;
-        for (int k = 0; k < 3; ++k) F[k] = k < d ? 0.5 * c * (A.Xbar[3 * i + k] + 2.0 * A.Abar[3 * i + k]) : 0.0;
-    };
-    double Fj[3];
-    fbar(j, Fj);
-    const double Rj = P.a[j], Cj = P.Cc[j];
-    // per lane: acc[w][k] = sum_i (J_ji F_j - J_ij F_i) at positions w (0: X^n, 1: prediction),
-    // unit[w][k] = force on j per unit collision constant
-    double acc[2][3] = {{0, 0, 0}, {0, 0, 0}}, unit[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    for (int i = threadIdx.x; i < np; i += blockDim.x) {
-        if (i == j) continue;
-        double Fi[3];
-        fbar(i, Fi);
-        const double Ri = P.a[i], Ci = P.Cc[i], cut = Ri + Rj + rp.delta;
-        for (int w = 0; w < 2; ++w) {
-            double Yj[3], Yi[3], dv[3] = {0, 0, 0};
-            pos(j, w, Yj);
-            pos(i, w, Yi);
-            for (int k = 0; k < d; ++k) {
-                dv[k] = Yj[k] - Yi[k];
-                if (per[k]) {
-                    const double h = 0.5 * n[k];
-                    if (dv[k] > h) dv[k] -= n[k];
-                    else if (dv[k] < -h) dv[k] += n[k];
-                }
-            }
-            const double dist = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-            if (!(dist <= cut) || dist == 0.0) continue;
-            pair_jac_apply(Cj, dv, dist, cut, rp, Fj, acc[w]);
-            double neg[3] = {0, 0, 0};
-            pair_jac_apply(Ci, dv, dist, cut, rp, Fi, neg);
-            for (int k = 0; k < 3; ++k) acc[w][k] -= neg[k];
-            const double s = (cut - dist) / rp.delta;
-            const double sc = (rp.cform == 1 ? s * s : s * s / dist) / rp.eps_p;
-            for (int k = 0; k < 3; ++k) unit[w][k] += sc * dv[k];
-        }
-    }
-    __shared__ double red[12][256];
-    for (int w = 0; w < 2; ++w)
-        for (int k = 0; k < 3; ++k) {
-            red[w * 3 + k][threadIdx.x] = acc[w][k];
-            red[6 + w * 3 + k][threadIdx.x] = unit[w][k];
-        }
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int m = 0; m < 12; ++m) red[m][threadIdx.x] += red[m][threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x != 0) return;
-    for (int w = 0; w < 2; ++w)
-        for (int k = 0; k < 3; ++k) {
-            acc[w][k] = red[w * 3 + k][0];
-            unit[w][k] = red[6 + w * 3 + k][0];
-        }
-    // walls through the mirror particle
+    const double cut = bi.R + bj.R + rp.delta;
+#pragma unroll
     for (int w = 0; w < 2; ++w) {
-        double Yj[3];
-        pos(j, w, Yj);
-        for (int k = 0; k < d; ++k) {
-            if (per[k]) continue;
+        double dv[3] = {0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (k >= rp.d) continue;
+            dv[k] = bj.Y[w][k] - bi.Y[w][k];
+            if (per[k]) {
+                const double h = 0.5 * n[k];
+                if (dv[k] > h) dv[k] -= n[k];
+                else if (dv[k] < -h) dv[k] += n[k];
+            }
+        }
+        const double dist = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+        if (!(dist <= cut) || dist == 0.0) continue;
+        pair_jac_apply(bj.C, dv, dist, cut, rp, bj.F, acc[w]);
+        double neg[3] = {0, 0, 0};
+        pair_jac_apply(bi.C, dv, dist, cut, rp, bi.F, neg);
+        for (int k = 0; k < 3; ++k) acc[w][k] -= neg[k];
+        const double s = (cut - dist) / rp.delta;
+        const double sc = (rp.cform == 1 ? s * s : s * s / dist) / rp.eps_p;
+        for (int k = 0; k < 3; ++k) unit[w][k] += sc * dv[k];
+    }
+}
+
+// Closing of the transposed Algorithm 1 for particle j once the partner sums
+// acc and unit are complete: the wall Jacobians (mirror particle), then
+// X_bar^n, the adjoint of U^{n-1}, the broadcast U_bar^n / N, the acceleration
+// of the step's nodes; drho and dg receive the density and |g| partials of
+// the collision constant and of 1/(2M).  Xbj, Abj, Upbj: X_bar^{n+1}, A_bar^{n+1}
+// and the adjoint of U^n of particle j; Nj, Aj: N and A^n of its record.
+__device__ void adj_rigid_close(int j, const AdjArrays &A, const RigidParams &rp, const Geom &g, const AdjBody &bj,
+                                double Nj, const double *Aj, double rho, double V, const double *Xbj, const double *Abj,
+                                const double *Upbj, double acc[2][3], double unit[2][3], double &drho, double &dg)
+{
+    const int d = rp.d;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int per[3] = {g.per_x, g.per_y, g.per_z};
+    const double Rj = bj.R, Cj = bj.C;
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (k >= d || per[k]) continue;
             const double walls[2] = {-0.5, n[k] - 0.5};
+#pragma unroll
             for (int s = 0; s < 2; ++s) {
-                const double dv = 2.0 * (Yj[k] - walls[s]);
+                const double dv = 2.0 * (bj.Y[w][k] - walls[s]);
                 const double dist = fabs(dv);
                 if (dist > 2.0 * Rj + rp.delta) continue;
                 const double qq = (2.0 * Rj + rp.delta - dist) / rp.delta;
@@ -327,116 +326,194 @@ __global__ __launch_bounds__(256) void k_adj_rigid(AdjArrays A, PartDev P, Rigid
                     dT = -4.0 * kw * qq / rp.delta;
                     tu = qq * qq * (dv >= 0 ? 1.0 : -1.0) / rp.eps_w;
                 }
-                acc[w][k] += dT * Fj[k];
+                acc[w][k] += dT * bj.F[k];
                 unit[w][k] += tu;
             }
         }
     }
-    const double *rj = A.rec + REC_STRIDE * j;
-    const double Nj = rj[13], rho = P.rho_s[j];
     const double cj = Nj > 0 ? 1.0 / (2.0 * rho * Nj) : 0.0;
     double corrb_dot_F = 0.0, Cbar = 0.0;
-    double Xsb[3], Ubb[3];
     for (int k = 0; k < 3; ++k) {
-        const double corrb = k < d ? A.Xbar[3 * j + k] + 2.0 * A.Abar[3 * j + k] : 0.0;
+        const double corrb = k < d ? Xbj[k] + 2.0 * Abj[k] : 0.0;
         corrb_dot_F += corrb * 0.5 * Cj * (unit[0][k] + unit[1][k]);
-        Cbar += Fj[k] * (unit[0][k] + unit[1][k]);
-        Xsb[k] = k < d ? A.Xbar[3 * j + k] + acc[1][k] : 0.0;
-        A.Xbar_out[3 * j + k] = k < d ? Xsb[k] + acc[0][k] : 0.0;
-        Ubb[k] = Xsb[k];
-        A.Upbar_out[3 * j + k] = 0.5 * Ubb[k];
-        const double Unb = 0.5 * Ubb[k] + A.Upbar[3 * j + k];
+        Cbar += bj.F[k] * (unit[0][k] + unit[1][k]);
+        const double Xsb = k < d ? Xbj[k] + acc[1][k] : 0.0;
+        A.Xbar_out[3 * j + k] = k < d ? Xsb + acc[0][k] : 0.0;
+        A.Upbar_out[3 * j + k] = 0.5 * Xsb;
+        const double Unb = 0.5 * Xsb + Upbj[k];
         const double ue = Nj > 0 ? Unb / Nj : 0.0;
         A.uext_d[3 * j + k] = ue;
         A.uext_f[3 * j + k] = (float)ue;
     }
     // c = 1/(2 rho N): dc/drho = -c/rho;  C = (rho - rho_f)|g| V (form 0) or (rho - rho_f)|g| (form 1)
-    const double V = rp.cform == 1 ? 1.0 : particle_volume(P.shape[j], P.a[j], P.b[j]);
-    A.rho_g[j] += corrb_dot_F * (-cj / rho) + Cbar * rp.gmag * V;
-    A.g_g[j] += Cbar * (rho - rp.rho_f) * V;
+    const double Vc = rp.cform == 1 ? 1.0 : V;
+    drho = corrb_dot_F * (-cj / rho) + Cbar * rp.gmag * Vc;
+    dg = Cbar * (rho - rp.rho_f) * Vc;
     // acceleration of the particle's nodes during step n: b g + A^n
-    const double bj = rp.gform == 0 ? 1.0 - rp.rho_f / rho : rho / rp.rho_f - 1.0;
+    const double bj_ = rp.gform == 0 ? 1.0 - rp.rho_f / rho : rho / rp.rho_f - 1.0;
     for (int k = 0; k < 3; ++k) {
-        const double acc_k = k < d ? bj * rp.g[k] + rj[10 + k] : 0.0;
+        const double acc_k = k < d ? bj_ * rp.g[k] + Aj[k] : 0.0;
         A.acc_d[3 * j + k] = acc_k;
         A.acc_f[3 * j + k] = (float)acc_k;
     }
 }
 
+__device__ __forceinline__ AdjBody load_body(const AdjArrays &A, const PartDev &P, int i, int d)
+{
+    AdjBody b;
+    const double *r = A.rec + REC_STRIDE * i;
+    adj_positions(r, d, b);
+    adj_force_bar(A.Xbar + 3 * i, A.Abar + 3 * i, r[13], P.rho_s[i], d, b.F);
+    b.R = P.a[i];
+    b.C = P.Cc[i];
+    return b;
+}
+
+// Many bodies: one workgroup per particle j, partners across lanes.
+__global__ __launch_bounds__(256) void k_adj_rigid(AdjArrays A, PartDev P, RigidParams rp, Geom g)
+{
+    const int j = blockIdx.x, d = rp.d, np = rp.np;
+    __shared__ double part[256 / WAVE][12];
+    const AdjBody bj = load_body(A, P, j, d);
+    // what the closing needs, loaded up front so its latency overlaps the sums
+    const double *rj = A.rec + REC_STRIDE * j;
+    double Xbj[3], Abj[3], Upbj[3], Aj[3];
+    for (int k = 0; k < 3; ++k) {
+        Xbj[k] = A.Xbar[3 * j + k];
+        Abj[k] = A.Abar[3 * j + k];
+        Upbj[k] = A.Upbar[3 * j + k];
+        Aj[k] = rj[10 + k];
+    }
+    const double Nj = rj[13], rho = P.rho_s[j], V = particle_volume(P.shape[j], P.a[j], P.b[j]);
+    const double rg0 = A.rho_g[j], gg0 = A.g_g[j];
+    double acc[2][3] = {{0, 0, 0}, {0, 0, 0}}, unit[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    for (int i = threadIdx.x; i < np; i += 256) {
+        if (i == j) continue;
+        adj_pair(bj, load_body(A, P, i, d), rp, g, acc, unit);
+    }
+    double s[12];
+    for (int w = 0; w < 2; ++w)
+        for (int k = 0; k < 3; ++k) {
+            s[w * 3 + k] = acc[w][k];
+            s[6 + w * 3 + k] = unit[w][k];
+        }
+    block_sum<12, 256>(s, part);
+    if (threadIdx.x != 0) return;
+    for (int w = 0; w < 2; ++w)
+        for (int k = 0; k < 3; ++k) {
+            acc[w][k] = s[w * 3 + k];
+            unit[w][k] = s[6 + w * 3 + k];
+        }
+    double drho, dg;
+    adj_rigid_close(j, A, rp, g, bj, Nj, Aj, rho, V, Xbj, Abj, Upbj, acc, unit, drho, dg);
+    A.rho_g[j] = rg0 + drho;
+    A.g_g[j] = gg0 + dg;
+}
+
 // ------------------------------------------------------------ particle adjoint
 // A_bar^n_i = sum of a_bar over the nodes of particle i (step n indicator);
 // a = b_i g + A_i gives the density and |g| partials.
+
+// This lane's partial sums of a_bar over the owned cells lane, lane + nl, ...
+// of box b, the loads of U cells in flight together.
+template <int D, int U>
+__device__ __forceinline__ void cell_abar(const uint16_t *__restrict__ owner, const double *__restrict__ asol,
+                                          const Geom &g, int i, const Box &b, int lane, int nl, double *s)
+{
+    const int N = (int)g.N;
+    CellWalk w(b.ext[0] > 0 ? b.ext[0] : 1, b.ext[1] > 0 ? b.ext[1] : 1, lane, nl);
+    for (int base = lane; base < b.cells; base += U * nl) {
+        uint16_t o[U];
+        double v[U][D];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int xu, yu, zu;
+            const int node = base + u * nl < b.cells ? walk_node(b, w, g, xu, yu, zu) : 0;
+            w.next();
+            o[u] = owner[node];
+#pragma unroll
+            for (int k = 0; k < D; ++k) v[u][k] = asol[(size_t)k * N + node];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (base + u * nl >= b.cells || o[u] != (uint16_t)i) continue;
+#pragma unroll
+            for (int k = 0; k < D; ++k) s[k] += v[u][k];
+        }
+    }
+}
+
+// Closing for particle i from the totals t: A_bar^n into Abar_out, and the
+// density and |g| partials through a = b_i g + A_i.
+__device__ __forceinline__ void adj_particle_close(const double *t, double rho, const RigidParams &rp, double *Abar_out,
+                                                   double &drho, double &dg)
+{
+    const double bi = rp.gform == 0 ? 1.0 - rp.rho_f / rho : rho / rp.rho_f - 1.0;
+    const double dbdrho = rp.gform == 0 ? rp.rho_f / (rho * rho) : 1.0 / rp.rho_f;
+    double ag = 0.0, aghat = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        Abar_out[k] = t[k];
+        ag += t[k] * rp.g[k];
+        aghat += rp.gmag > 0 ? t[k] * rp.g[k] / rp.gmag : 0.0;
+    }
+    drho = ag * dbdrho;
+    dg = bi * aghat;
+}
+
+// Box of particle i in step n: around the recorded centre r.
+__device__ __forceinline__ Box adj_box(const double *r, double R, const Geom &g, int d)
+{
+    int lo[3], hi[3];
+    centre_box(r, R, g, d, lo, hi);
+    return make_box(lo, hi);
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_adj_particles(const uint16_t *__restrict__ owner,
                                                         const double *__restrict__ asol, const double *__restrict__ rec,
                                                         PartDev P, RigidParams rp, Geom g, double *__restrict__ Abar_out,
                                                         double *__restrict__ rho_g, double *__restrict__ g_g)
 {
+    __shared__ double part[256 / WAVE][3];
     const int i = blockIdx.x;
-    const int n[3] = {g.nx, g.ny, g.nz};
-    const int per[3] = {g.per_x, g.per_y, g.per_z};
-    const double *r = rec + REC_STRIDE * i;
-    int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
-    const double R = P.a[i];
-    for (int k = 0; k < D; ++k) {
-        int l = (int)floor(r[k] - R) - 2, h = (int)ceil(r[k] + R) + 2;
-        if (!per[k]) {
-            l = l < 0 ? 0 : l;
-            h = h > n[k] - 1 ? n[k] - 1 : h;
-        }
-        lo[k] = l;
-        ext[k] = h - l + 1 > 0 ? h - l + 1 : 0;
-    }
-    const long cells = (long)ext[0] * ext[1] * ext[2];
-    const int N = (int)g.N;
+    const Box b = adj_box(rec + REC_STRIDE * i, P.a[i], g, D);
+    const double rho = P.rho_s[i], rg0 = rho_g[i], gg0 = g_g[i];
     double s[3] = {0, 0, 0};
-    for (long c = threadIdx.x; c < cells; c += blockDim.x) {
-        const int lx = (int)(c % ext[0]), ly = (int)((c / ext[0]) % ext[1]), lz = (int)(c / ((long)ext[0] * ext[1]));
-        const int x = wrap(lo[0] + lx, g.nx), y = wrap(lo[1] + ly, g.ny), z = wrap(lo[2] + lz, g.nz);
-        const int node = x + g.nx * (y + g.ny * z);
-        if (owner[node] != (uint16_t)i) continue;
-        for (int k = 0; k < D; ++k) s[k] += asol[(size_t)k * N + node];
-    }
-    __shared__ double red[3][256];
-    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-        __syncthreads();
-    }
+    cell_abar<D, UNR>(owner, asol, g, i, b, threadIdx.x, 256, s);
+    block_sum<3, 256>(s, part);
     if (threadIdx.x != 0) return;
-    const double rho = P.rho_s[i];
-    const double bi = rp.gform == 0 ? 1.0 - rp.rho_f / rho : rho / rp.rho_f - 1.0;
-    const double dbdrho = rp.gform == 0 ? rp.rho_f / (rho * rho) : 1.0 / rp.rho_f;
-    double ag = 0.0, aghat = 0.0;
-    for (int k = 0; k < 3; ++k) {
-        Abar_out[3 * i + k] = red[k][0];
-        ag += red[k][0] * rp.g[k];
-        aghat += rp.gmag > 0 ? red[k][0] * rp.g[k] / rp.gmag : 0.0;
-    }
-    rho_g[i] += ag * dbdrho;
-    g_g[i] += bi * aghat;
+    double drho, dg;
+    adj_particle_close(s, rho, rp, Abar_out + 3 * i, drho, dg);
+    rho_g[i] = rg0 + drho;
+    g_g[i] = gg0 + dg;
 }
 
 // U^{-1} = U^0 was measured with a = b g on every node of the particle:
 // dU^{-1}/da = 1/2 gives the density and |g| partials of the initial state.
+__device__ __forceinline__ void adj_initial_terms(double rho, const double *Upb, const RigidParams &rp, double &drho,
+                                                  double &dg)
+{
+    const double bi = rp.gform == 0 ? 1.0 - rp.rho_f / rho : rho / rp.rho_f - 1.0;
+    const double dbdrho = rp.gform == 0 ? rp.rho_f / (rho * rho) : 1.0 / rp.rho_f;
+    double ag = 0.0, aghat = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double ab = 0.5 * Upb[k];
+        ag += ab * rp.g[k];
+        aghat += rp.gmag > 0 ? ab * rp.g[k] / rp.gmag : 0.0;
+    }
+    drho = ag * dbdrho;
+    dg = bi * aghat;
+}
+
 __global__ void k_adj_initial(PartDev P, RigidParams rp, const double *__restrict__ Upbar, double *__restrict__ rho_g,
                               double *__restrict__ g_g)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= rp.np) return;
-    const double rho = P.rho_s[i];
-    const double bi = rp.gform == 0 ? 1.0 - rp.rho_f / rho : rho / rp.rho_f - 1.0;
-    const double dbdrho = rp.gform == 0 ? rp.rho_f / (rho * rho) : 1.0 / rp.rho_f;
-    double ag = 0.0, aghat = 0.0;
-    for (int k = 0; k < 3; ++k) {
-        const double ab = 0.5 * Upbar[3 * i + k];
-        ag += ab * rp.g[k];
-        aghat += rp.gmag > 0 ? ab * rp.g[k] / rp.gmag : 0.0;
-    }
-    rho_g[i] += ag * dbdrho;
-    g_g[i] += bi * aghat;
+    double drho, dg;
+    adj_initial_terms(P.rho_s[i], Upbar + 3 * i, rp, drho, dg);
+    rho_g[i] += drho;
+    g_g[i] += dg;
 }
 
 // ----------------------------------------------------------------- launchers
@@ -460,14 +537,18 @@ hipError_t launch_adj_lattice(lbm_ctx *c, const void *fprev, const uint16_t *own
     });
 }
 
+static AdjArrays adj_arrays(const AdjArraysHost &h)
+{
+    return AdjArrays{h.rec,    h.Xbar,   h.Abar,  h.Upbar,  h.Xbar_out, h.Upbar_out,
+                     h.uext_d, h.uext_f, h.acc_d, h.acc_f, h.rho_g,    h.g_g};
+}
+
 hipError_t launch_adj_rigid(lbm_ctx *c, const AdjArraysHost &h)
 {
     if (c->np == 0) return hipSuccess;
-    AdjArrays A{h.rec, h.Xbar, h.Abar, h.Upbar, h.Xbar_out, h.Upbar_out, h.uext_d, h.uext_f, h.acc_d, h.acc_f,
-                h.rho_g, h.g_g};
     RigidParams rp = c->rp;
     rp.np = c->np;
-    hipLaunchKernelGGL(k_adj_rigid, dim3(c->np), dim3(256), 0, c->stream, A, c->P, rp, c->geo);
+    hipLaunchKernelGGL(k_adj_rigid, dim3(c->np), dim3(256), 0, c->stream, adj_arrays(h), c->P, rp, c->geo);
     return hipGetLastError();
 }
 

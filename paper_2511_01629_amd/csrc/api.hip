@@ -20,6 +20,9 @@ using namespace lbm;
 namespace {
 
 constexpr size_t ALIGN = 256;
+
+// message of the last lbm_workspace_size / lbm_create failure on this thread
+thread_local std::string g_create_err = "no error";
 constexpr int PART_DOUBLES = 3 * 8 + 5 + 3 + 16 + 3 * 5 + 1; // X Xn theta U W Uprev Wprev A, rho a b C, acc, sums, Ub Y Ys Y2 Dc, dth
 constexpr double CS2 = 1.0 / 3.0;
 
@@ -208,11 +211,12 @@ int lbm::step_impl(lbm_ctx *c, int64_t nsteps, double *rec_dev)
                         bufs));
         c->cur ^= 1;
         double *rec = rec_dev ? rec_dev + (size_t)s * c->np * REC_STRIDE : nullptr;
-        HIPCHK(c, timed(1, [](lbm_ctx *cc, void *r) { return launch_reduce(cc, 1, (double *)r); }, rec));
         if (c->rp.K == 1) {
+            HIPCHK(c, timed(1, [](lbm_ctx *cc, void *r) { return launch_reduce(cc, 1, (double *)r); }, rec));
             HIPCHK(c, timed(2, [](lbm_ctx *cc, void *) { return launch_rigid_raster(cc, 1); }, nullptr));
             std::swap(c->P.X, c->P.Xn);
         } else {
+            HIPCHK(c, timed(1, [](lbm_ctx *cc, void *r) { return launch_reduce(cc, 1, (double *)r); }, rec));
             HIPCHK(c, timed(2, [](lbm_ctx *cc, void *) { return launch_rigid_substeps(cc); }, nullptr));
             std::swap(c->P.X, c->P.Xn);
             HIPCHK(c, timed(3, [](lbm_ctx *cc, void *) { return launch_rigid_raster(cc, 0); }, nullptr));
@@ -252,7 +256,7 @@ int lbm_workspace_size(const lbm_config *cfg, size_t *bytes)
     int64_t N;
     if (!bytes) return LBM_EINVAL;
     int rc = validate_cfg(cfg, why, Q, d, N);
-    if (rc) return rc;
+    if (rc) return g_create_err = why, rc;
     *bytes = layout_for(cfg, Q, d, N).total;
     return LBM_OK;
 }
@@ -265,7 +269,7 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
     int Q, d;
     int64_t N;
     int rc = validate_cfg(cfg, why, Q, d, N);
-    if (rc) return rc;
+    if (rc) return g_create_err = why, rc;
     lbm_ctx *c = new lbm_ctx();
     c->cfg = *cfg;
     c->Q = Q;
@@ -309,6 +313,7 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
     c->cur = 0;
     c->rec_dev = nullptr;
     c->rec_cap = 0;
+    c->owner_next = nullptr;
     c->prof = 0;
     for (int k = 0; k < LBM_NKERNELS; ++k) {
         c->prof_ms[k] = 0.0;
@@ -317,12 +322,14 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) {
         delete c;
+        g_create_err = std::string("hipSetDevice: ") + hipGetErrorString(e);
         return LBM_EDEVICE;
     }
     const Layout L = layout_for(&c->cfg, Q, d, N);
     if (cfg->workspace) {
         if (cfg->workspace_bytes < L.total || ((uintptr_t)cfg->workspace % ALIGN) != 0) {
             delete c;
+            g_create_err = "workspace too small or not 256-byte aligned";
             return LBM_ENOMEM;
         }
         c->ws = cfg->workspace;
@@ -332,6 +339,7 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
         e = hipMalloc(&c->ws, L.total);
         if (e != hipSuccess) {
             delete c;
+            g_create_err = std::string("hipMalloc: ") + hipGetErrorString(e);
             return LBM_ENOMEM;
         }
         c->ws_bytes = L.total;
@@ -348,6 +356,7 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
         (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
         if (c->own_mem) (void)hipFree(c->ws);
         delete c;
+        g_create_err = std::string("initialisation: ") + hipGetErrorString(e);
         return LBM_EDEVICE;
     }
     *out = c;
@@ -618,7 +627,7 @@ int lbm_get_step(const lbm_ctx *c, int64_t *step)
 
 const char *lbm_last_error(const lbm_ctx *c)
 {
-    if (!c) return "no context";
+    if (!c) return g_create_err.c_str();
     return c->err.c_str();
 }
 

@@ -82,7 +82,9 @@ struct lbm_ctx {
     int cur;      // f[cur] holds f~ of the last completed step
     void *fws[2]; // the workspace's two population buffers (f[] points elsewhere only
                   // inside a differentiated run)
-    uint16_t *owner;
+    uint16_t *owner;      // indicator the next step reads
+    uint16_t *owner_next; // NULL: steps update `owner` in place; else the (all FLUID)
+                          // buffer the next step's indicator goes to (differentiated runs)
     double *usol;    // [d][N] velocity on solid nodes (written by the fused kernel)
     double *staging; // [4][N] doubles for field/population transfers
     int32_t *flags;  // [0] unstable, [1] domain
@@ -128,6 +130,7 @@ hipError_t launch_adj_rigid(lbm_ctx *c, const AdjArraysHost &h);
 hipError_t launch_adj_particles(lbm_ctx *c, const uint16_t *owner, const double *asol, const double *rec,
                                 double *Abar_out, double *rho_g, double *g_g);
 hipError_t launch_adj_initial(lbm_ctx *c, const double *Upbar, double *rho_g, double *g_g);
+
 
 // api.hip (shared with grad.hip)
 int step_impl(lbm_ctx *c, int64_t nsteps, double *rec_dev);

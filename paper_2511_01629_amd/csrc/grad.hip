@@ -6,15 +6,16 @@
 //
 // every > 1: the forward run snapshots the whole state (populations,
 // indicator, particle arrays) every `every` steps.  The backward pass restores
-// a segment's snapshot into the first of every + 1 population frames and
-// recomputes the segment with the lattice kernel reading frame n and writing
-// frame n + 1 directly (no copies), keeping each step's indicator; then it runs
-// the segment's adjoint steps in reverse.  All kernels are deterministic, so
-// the recomputed frames are bitwise those of the forward run.
+// a segment's snapshot into the first of every + 1 frames and recomputes the
+// segment with step n reading frame n and writing frame n + 1 directly, both
+// the populations and the indicator (the indicator frames are filled with
+// FLUID first, so the step rasterises into a clean map and no copy is made);
+// then it runs the segment's adjoint steps in reverse.  All kernels are
+// deterministic, so the recomputed frames are bitwise those of the forward run.
 //
 // every == 1: the forward run itself writes every frame (T + 1 population
-// buffers and T indicators -- e.g. 100 GB for 5000 steps of a 512x1024 FP32
-// lattice, which 288 GB of HBM holds), and the backward pass recomputes
+// buffers and T + 1 indicators -- e.g. 100 GB for 5000 steps of a 512x1024
+// FP32 lattice, which 288 GB of HBM holds), and the backward pass recomputes
 // nothing.
 #include <algorithm>
 #include <vector>
@@ -28,7 +29,7 @@ struct GradState {
     int every = 0, nsnap = 0;
     size_t fbytes = 0, obytes = 0, pbytes = 0;
     char *snap = nullptr;  // nsnap x (fbytes + obytes + pbytes)
-    char *hist = nullptr;  // every == 1: (T + 1) population frames, then T indicators
+    char *hist = nullptr;  // every == 1: (T + 1) population frames, then T + 1 indicators
     std::vector<PartDev> snapP;
     std::vector<int> snapCur;
     std::vector<int64_t> snapStep;
@@ -65,17 +66,42 @@ int snapshot(lbm_ctx *c, GradState *G, int k)
     return LBM_OK;
 }
 
-// Restore snapshot k; its populations go to fdst (NULL: the live buffer).
-int restore(lbm_ctx *c, GradState *G, int k, void *fdst = nullptr)
+// Restore snapshot k; its populations go to fdst and its indicator to odst
+// (NULL: the live buffers).
+int restore(lbm_ctx *c, GradState *G, int k, void *fdst = nullptr, void *odst = nullptr)
 {
     const char *src = G->snap + (size_t)k * (G->fbytes + G->obytes + G->pbytes);
     c->P = G->snapP[k];
     c->cur = G->snapCur[k];
     c->step = G->snapStep[k];
     HIPCHK(c, hipMemcpyAsync(fdst ? fdst : c->f[c->cur], src, G->fbytes, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->owner, src + G->fbytes, G->obytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(odst ? odst : c->owner, src + G->fbytes, G->obytes, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(part_base(c), src + G->fbytes + G->obytes, G->pbytes, hipMemcpyDeviceToDevice, c->stream));
     return LBM_OK;
+}
+
+// Steps s0 .. s0 + n - 1 with step s reading population frame s - s0 of fr and
+// indicator frame s - s0 of ow, and writing frame s - s0 + 1 of each.
+// Indicator frames 1 .. n are filled with FLUID first; frame 0 must hold the
+// indicator of step s0.  rec (optional): the particle records of the steps.
+// The live buffers are restored afterwards (the caller copies what it keeps).
+int run_frames(lbm_ctx *c, GradState *G, char *fr, char *ow, int64_t n, double *rec)
+{
+    HIPCHK(c, hipMemsetAsync(ow + G->obytes, 0xFF, (size_t)n * G->obytes, c->stream));
+    uint16_t *live = c->owner;
+    int rc = LBM_OK;
+    for (int64_t s = 0; s < n && rc == LBM_OK; ++s) {
+        c->f[c->cur] = fr + (size_t)s * G->fbytes;
+        c->f[c->cur ^ 1] = fr + (size_t)(s + 1) * G->fbytes;
+        c->owner = (uint16_t *)(ow + (size_t)s * G->obytes);
+        c->owner_next = (uint16_t *)(ow + (size_t)(s + 1) * G->obytes);
+        rc = step_impl(c, 1, rec ? rec + (size_t)s * c->np * REC_STRIDE : nullptr);
+    }
+    c->f[0] = c->fws[0];
+    c->f[1] = c->fws[1];
+    c->owner = live;
+    c->owner_next = nullptr;
+    return rc;
 }
 
 template <class Tp> int dev_alloc(lbm_ctx *c, Tp **p, size_t n, std::vector<void *> &owned)
@@ -120,26 +146,18 @@ int lbm_forward_checkpointed(lbm_ctx *c, int64_t nsteps, int32_t every)
     G->pbytes = part_bytes(c);
     HIPCHK(c, hipMalloc((void **)&G->rec, (size_t)nsteps * c->np * REC_STRIDE * sizeof(double)));
     if (every == 1) {
-        // keep every frame: the lattice kernel of step n reads frame n and writes frame n+1
-        HIPCHK(c, hipMalloc((void **)&G->hist, (size_t)(nsteps + 1) * G->fbytes + (size_t)nsteps * G->obytes));
+        // keep every frame: step n reads frame n and writes frame n + 1
+        HIPCHK(c, hipMalloc((void **)&G->hist, (size_t)(nsteps + 1) * (G->fbytes + G->obytes)));
         char *fr = G->hist, *ow = G->hist + (size_t)(nsteps + 1) * G->fbytes;
         HIPCHK(c, hipMemcpyAsync(fr, c->f[c->cur], G->fbytes, hipMemcpyDeviceToDevice, c->stream));
-        for (int64_t s = 0; s < nsteps; ++s) {
-            c->f[c->cur] = fr + (size_t)s * G->fbytes;
-            c->f[c->cur ^ 1] = fr + (size_t)(s + 1) * G->fbytes;
-            HIPCHK(c, hipMemcpyAsync(ow + (size_t)s * G->obytes, c->owner, G->obytes, hipMemcpyDeviceToDevice,
-                                     c->stream));
-            int rc = step_impl(c, 1, G->rec + (size_t)s * c->np * REC_STRIDE);
-            if (rc) {
-                c->f[0] = c->fws[0];
-                c->f[1] = c->fws[1];
-                return rc;
-            }
-        }
-        const void *last = c->f[c->cur];
-        c->f[0] = c->fws[0];
-        c->f[1] = c->fws[1];
-        HIPCHK(c, hipMemcpyAsync(c->f[c->cur], last, G->fbytes, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(ow, c->owner, G->obytes, hipMemcpyDeviceToDevice, c->stream));
+        int rc = run_frames(c, G, fr, ow, nsteps, G->rec);
+        if (rc) return rc;
+        // the final state back into the live buffers
+        HIPCHK(c, hipMemcpyAsync(c->f[c->cur], fr + (size_t)nsteps * G->fbytes, G->fbytes, hipMemcpyDeviceToDevice,
+                                 c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->owner, ow + (size_t)nsteps * G->obytes, G->obytes, hipMemcpyDeviceToDevice,
+                                 c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         return lbm_sync(c);
     }
@@ -182,8 +200,8 @@ int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau
            *g_g = nullptr, *uext_d = nullptr, *acc_d = nullptr;
     float *uext_f = nullptr, *acc_f = nullptr;
     const bool all = G->hist != nullptr;
-    // segment frames: every + 1 population buffers, then every indicators
-    const size_t segsize = all ? 1 : (size_t)(G->every + 1) * G->fbytes + (size_t)G->every * G->obytes;
+    // segment frames: every + 1 population buffers, then every + 1 indicators
+    const size_t segsize = all ? 1 : (size_t)(G->every + 1) * (G->fbytes + G->obytes);
     int rc = LBM_OK;
     if ((rc = dev_alloc(c, &seg, segsize, owned)) || (rc = dev_alloc(c, &lam, 2 * Q * N * lam_elt, owned)) ||
         (rc = dev_alloc(c, &asol, (size_t)c->d * N, owned)) || (rc = dev_alloc(c, &taup, nblocks, owned)) ||
@@ -204,6 +222,12 @@ int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau
         return c->err = "seed copy failed", LBM_EDEVICE;
     }
     int cx = 0, cu = 0, cl = 0; // which half of the ping-pong adjoint buffers is current
+    // arrays of the rigid adjoint of step n (X_bar and the adjoint of U ping-pong)
+    auto rigid_arrays = [&](int64_t n) {
+        return AdjArraysHost{G->rec + (size_t)n * np * REC_STRIDE, Xbar + 3 * np * cx, Abar, Upbar + 3 * np * cu,
+                             Xbar + 3 * np * (cx ^ 1), Upbar + 3 * np * (cu ^ 1), uext_d, uext_f, acc_d, acc_f,
+                             rho_g, g_g};
+    };
     const int64_t span = all ? G->T : G->every;
     const int nseg = all ? 1 : G->nsnap - 1;
     for (int sg = nseg - 1; sg >= 0 && rc == LBM_OK; --sg) {
@@ -215,27 +239,14 @@ int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau
         } else {
             fr = seg;
             ow = seg + (size_t)(G->every + 1) * G->fbytes;
-            if ((rc = restore(c, G, sg, fr))) break;
-            for (int64_t n = s0; n < s1 && rc == LBM_OK; ++n) {
-                c->f[c->cur] = fr + (size_t)(n - s0) * G->fbytes;
-                c->f[c->cur ^ 1] = fr + (size_t)(n - s0 + 1) * G->fbytes;
-                if (hipMemcpyAsync(ow + (size_t)(n - s0) * G->obytes, c->owner, G->obytes, hipMemcpyDeviceToDevice,
-                                   c->stream) != hipSuccess) {
-                    rc = LBM_EDEVICE;
-                    break;
-                }
-                rc = step_impl(c, 1, nullptr);
-            }
-            c->f[0] = c->fws[0];
-            c->f[1] = c->fws[1];
+            if ((rc = restore(c, G, sg, fr, ow))) break;
+            if ((rc = run_frames(c, G, fr, ow, s1 - s0, nullptr))) break;
         }
         for (int64_t n = s1 - 1; n >= s0 && rc == LBM_OK; --n) {
             const char *fprev = fr + (size_t)(n - s0) * G->fbytes;
             const uint16_t *own_n = (const uint16_t *)(ow + (size_t)(n - s0) * G->obytes);
             const double *rec_n = G->rec + (size_t)n * np * REC_STRIDE;
-            AdjArraysHost h{rec_n, Xbar + 3 * np * cx, Abar, Upbar + 3 * np * cu, Xbar + 3 * np * (cx ^ 1),
-                            Upbar + 3 * np * (cu ^ 1), uext_d, uext_f, acc_d, acc_f, rho_g, g_g};
-            if (launch_adj_rigid(c, h) != hipSuccess) rc = LBM_EDEVICE;
+            if (launch_adj_rigid(c, rigid_arrays(n)) != hipSuccess) rc = LBM_EDEVICE;
             cx ^= 1;
             cu ^= 1;
             char *lin = lam + (size_t)cl * Q * N * lam_elt, *lout = lam + (size_t)(cl ^ 1) * Q * N * lam_elt;

@@ -2,29 +2,36 @@
 // the rigid-body update (Algorithm 1) for gfx950.  All particle arithmetic is
 // FP64.
 //
-// A step runs two particle kernels after the lattice update, one workgroup
-// per particle each:
+// The particle side of a step is a few hundred to a few thousand nodes per
+// particle: it is bound by memory latency, not bandwidth.  Two launches, one
+// workgroup per particle each:
+//    k_sums          momentum sums over the scan box (sec. 2.4, eq. 22a-b);
+//                    in place, every owned node is reset to FLUID once read
+//                    (a node owned by i is matched by no other particle), which
+//                    clears the indicator for the next rasterisation.
+//    k_rigid_raster  Algorithm 1 (sec. 2.4) for the particle, with the
+//                    collision forces of sec. 2.3 (eq. 19-21) summed over the
+//                    other particles across lanes, then its new indicator
+//                    (sec. 2.1, eq. 9).
+// (A single workgroup doing all of it for a few bodies was measured slower:
+// it adds up the phases' latency chains on one compute unit.)
 //
-//  k_reduce<STEP>   momentum sums over the particle's scan box (sec. 2.4,
-//                   eq. 22a-b); each thread accumulates in a fixed order and a
-//                   fixed LDS tree combines the partials, so results are
-//                   bitwise reproducible.  The owned nodes are reset to FLUID
-//                   as they are read, which clears the indicator.
-//  k_rigid_raster   Algorithm 1 (sec. 2.4) for the particle, with the
-//                   collision forces of sec. 2.3 (eq. 19-21) summed over the
-//                   other particles across the workgroup's lanes, then the
-//                   particle's new indicator (sec. 2.1, eq. 9): every node of
-//                   its closed shape is claimed with a 16-bit atomic minimum,
-//                   so a shared node goes to the lowest index.  The inside
-//                   tests are FP64 with explicit round-to-nearest products and
-//                   sums, so no contraction moves a node across a boundary.
+// Indicator: every node of a particle's closed shape is claimed with a 16-bit
+// atomic minimum, so a node shared by two shapes goes to the lower index.  On
+// lattices of even width the two nodes of an aligned 32-bit word are claimed
+// together by one lane with one compare-and-swap that expects the cleared
+// value, so a claim costs one round trip unless another particle touches the
+// same word.  The inside tests are FP64 with explicit round-to-nearest
+// products and sums, so no contraction moves a node across a boundary.
+//
+// Indicator buffers: the sums read owner_in; the raster writes owner_out,
+// which must be all FLUID.  owner_in == owner_out is the in-place step (the
+// sums clear it); distinct buffers keep the old indicator (differentiated runs).
 //
 // New centres go to a second buffer (P.Xn), swapped by the host, because every
-// workgroup reads all old centres.  With K > 1 sub-steps, one workgroup
-// (k_rigid_substeps) integrates all particles together, then k_rigid_raster
-// only rasterises.
-#include "ctx.h"
+// workgroup reads all old centres.
 #include "lattice.h"
+#include "reduce.h"
 
 namespace lbm {
 
@@ -42,126 +49,189 @@ __device__ __forceinline__ bool inside_shape(int shape, double a, double b, doub
     return dadd(dmul(dmul(b, b), dmul(xi, xi)), dmul(dmul(a, a), dmul(eta, eta))) <= dmul(dmul(a, a), dmul(b, b));
 }
 
+// --------------------------------------------------------------- indicator
 
-// 16-bit atomic minimum through a 32-bit compare-and-swap on the aligned word.
-__device__ __forceinline__ void atomic_min_u16(uint16_t *addr, uint16_t val)
+__device__ __forceinline__ uint32_t min_halves(uint32_t a, uint32_t b)
 {
-    uintptr_t a = reinterpret_cast<uintptr_t>(addr);
-    unsigned int *word = reinterpret_cast<unsigned int *>(a & ~uintptr_t(3));
-    const unsigned int shift = (a & 2) ? 16u : 0u;
-    unsigned int old = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while (true) {
-        const unsigned int cur = (old >> shift) & 0xFFFFu;
-        if (cur <= val) return;
-        const unsigned int nw = (old & ~(0xFFFFu << shift)) | ((unsigned int)val << shift);
-        const unsigned int prev = atomicCAS(word, old, nw);
-        if (prev == old) return;
-        old = prev;
+    const uint32_t lo = min(a & 0xFFFFu, b & 0xFFFFu), hi = min(a >> 16, b >> 16);
+    return lo | (hi << 16);
+}
+
+// Finish lowering the two 16-bit owners of word w to `want` (0xFFFF in a half
+// that is not claimed) after a compare-and-swap that expected `exp` returned
+// `got`.  Owners only decrease, so the loop ends.
+__device__ __forceinline__ void claim_finish(uint32_t *w, uint32_t want, uint32_t exp, uint32_t got)
+{
+    while (got != exp) {
+        const uint32_t nw = min_halves(got, want);
+        if (nw == got) return;
+        exp = got;
+        got = atomicCAS(w, exp, nw);
     }
 }
 
-struct BoxIter {
-    int lo[3], ext[3];
-    long cells;
-};
-
-__device__ __forceinline__ BoxIter load_box(const PartDev &P, int i, int d)
+// Claim the nodes of particle i (shape at centre Xc, box [lo, hi]) in owner,
+// which holds FLUID wherever no other particle has claimed yet.  The items
+// (node pairs on even-width lattices, else single nodes) are spread over nl
+// lanes; this lane is `lane`.
+template <int U>
+__device__ void raster_items(uint16_t *owner, const Geom &g, int d, int i, const double *Xc, int shape, double a,
+                             double b, double cs, double sn, const int *lo, const int *hi, int lane, int nl)
 {
-    BoxIter b;
-    b.cells = 1;
-    for (int k = 0; k < 3; ++k) {
-        b.lo[k] = (k < d) ? P.lo[3 * i + k] : 0;
-        b.ext[k] = (k < d) ? P.hi[3 * i + k] - P.lo[3 * i + k] + 1 : 1;
-        if (b.ext[k] < 0) b.ext[k] = 0;
-        b.cells *= b.ext[k];
+    if (hi[0] < lo[0] || hi[1] < lo[1] || hi[2] < lo[2]) return;
+    const bool pairs = (g.nx & 1) == 0;
+    const int step = pairs ? 2 : 1;
+    // on an even-width lattice x and wrap(x) have the same parity, so an even
+    // unwrapped x starts an aligned word; x - 1 below the box is still a node
+    // of the lattice (lo is clipped at 0 on walls, and a periodic box spans
+    // less than one period)
+    const int xs = pairs ? lo[0] - (lo[0] & 1) : lo[0];
+    const int wx = (hi[0] - xs) / step + 1, ey = hi[1] - lo[1] + 1;
+    const int items = wx * ey * (hi[2] - lo[2] + 1);
+    uint32_t *words = reinterpret_cast<uint32_t *>(owner);
+    const uint32_t id = (uint32_t)i;
+    const double X0 = Xc[0], X1 = Xc[1], X2 = d == 3 ? Xc[2] : 0.0;
+    CellWalk w(wx, ey, lane, nl);
+    for (int base = lane; base < items; base += U * nl) {
+        uint32_t want[U], got[U];
+        int widx[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = base + u * nl;
+            want[u] = 0xFFFFFFFFu;
+            widx[u] = 0;
+            const int col = w.lx, ly = w.ly, lz = w.lz;
+            w.next();
+            if (t < items) {
+                const int x0 = xs + step * col, yu = lo[1] + ly, zu = lo[2] + lz;
+                const double dy = (double)yu - X1, dz = d == 3 ? (double)zu - X2 : 0.0;
+                const int n0 = wrap(x0, g.nx) + g.nx * (wrap(yu, g.ny) + g.ny * wrap(zu, g.nz));
+                const bool in0 = inside_shape(shape, a, b, cs, sn, (double)x0 - X0, dy, dz);
+                if (pairs) {
+                    const bool in1 = inside_shape(shape, a, b, cs, sn, (double)(x0 + 1) - X0, dy, dz);
+                    want[u] = (in0 ? id : 0xFFFFu) | ((in1 ? id : 0xFFFFu) << 16);
+                } else if (in0) {
+                    const uint32_t sh = (n0 & 1) ? 16u : 0u;
+                    want[u] = (id << sh) | (0xFFFFu << (16u - sh));
+                }
+                widx[u] = n0 >> 1;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            got[u] = want[u] != 0xFFFFFFFFu ? atomicCAS(words + widx[u], 0xFFFFFFFFu, want[u]) : 0xFFFFFFFFu;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (want[u] != 0xFFFFFFFFu) claim_finish(words + widx[u], want[u], 0xFFFFFFFFu, got[u]);
     }
-    return b;
 }
 
-__global__ __launch_bounds__(256) void k_raster_clear(uint16_t *__restrict__ owner, PartDev P, Geom g, int d)
+__global__ __launch_bounds__(256) void k_raster_clear(uint16_t *__restrict__ owner, PartDev P, Geom g)
 {
     const int i = blockIdx.x;
-    const BoxIter b = load_box(P, i, d);
-    for (long cidx = threadIdx.x; cidx < b.cells; cidx += blockDim.x) {
-        const int lx = (int)(cidx % b.ext[0]);
-        const int ly = (int)((cidx / b.ext[0]) % b.ext[1]);
-        const int lz = (int)(cidx / ((long)b.ext[0] * b.ext[1]));
-        const int x = wrap(b.lo[0] + lx, g.nx), y = wrap(b.lo[1] + ly, g.ny), z = wrap(b.lo[2] + lz, g.nz);
-        owner[x + g.nx * (y + g.ny * z)] = FLUID;
+    const Box b = make_box(P.lo + 3 * i, P.hi + 3 * i);
+    for (int c = threadIdx.x; c < b.cells; c += blockDim.x) {
+        int xu, yu, zu, node;
+        cell_at(b, c, g, xu, yu, zu, node);
+        owner[node] = FLUID;
     }
 }
 
+// ------------------------------------------------------------ momentum sums
 // Per-particle sums over the owned nodes of the scan box.
 //  2D: [0] N, [1..2] sum u, [3] sum r x u (z), [4] sum |r|^2
 //  3D: [0] N, [1..3] sum u, [4..6] sum r x u, [7..12] inertia xx yy zz xy xz yz
 // then U = sum u / N and omega = (sum r x u)/(sum |r|^2) (2D) or I^{-1} L (3D).
-//
-// STEP = true (inside a time step): every owned node is reset to FLUID once
-// read -- a node owned by particle i is read by no other particle's sum, so
-// this clears the whole indicator for the next rasterisation -- and the
-// quantities Algorithm 1 needs are prepared: U_bar = (U^n + U^{n-1})/2,
-// dtheta = (omega^n + omega^{n-1})/2, then U^{n-1} <- U^n, omega^{n-1} <- omega^n.
-// rec (optional) receives the step's record (layout REC_STRIDE in ctx.h).
-template <int D, bool STEP>
-__global__ __launch_bounds__(256) void k_reduce(uint16_t *__restrict__ owner, const double *__restrict__ usol,
-                                                 PartDev P, Geom g, double *__restrict__ rec)
+template <int D> struct NSums {
+    static constexpr int value = D == 2 ? 5 : 13;
+};
+
+// This lane's partial sums over cells lane, lane + nl, ... of box b, with
+// the loads of U cells in flight together.  owner_clr (NULL or owner_in):
+// reset each owned node to FLUID once read.
+template <int D, int U>
+__device__ __forceinline__ void cell_sums(const uint16_t *owner_in, uint16_t *owner_clr, const double *__restrict__ usol,
+                                          const Geom &g, int i, const double *Xc, const Box &b, int lane, int nl,
+                                          double *s)
 {
-    constexpr int NS = (D == 2) ? 5 : 13;
-    const int i = blockIdx.x;
-    const BoxIter b = load_box(P, i, D);
-    const double X0 = P.X[3 * i], X1 = P.X[3 * i + 1], X2 = (D == 3) ? P.X[3 * i + 2] : 0.0;
     const int N = (int)g.N;
-    double s[NS];
+    const double X0 = Xc[0], X1 = Xc[1], X2 = D == 3 ? Xc[2] : 0.0;
+    CellWalk w(b.ext[0] > 0 ? b.ext[0] : 1, b.ext[1] > 0 ? b.ext[1] : 1, lane, nl);
+    for (int base = lane; base < b.cells; base += U * nl) {
+        // all loads first (the velocity is read on every cell and used only
+        // on owned ones), so their latencies overlap
+        const CellWalk w0 = w;
+        uint16_t o[U];
+        double ux[U], uy[U], uz[U];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) s[k] = 0.0;
-    for (long cidx = threadIdx.x; cidx < b.cells; cidx += blockDim.x) {
-        const int lx = (int)(cidx % b.ext[0]);
-        const int ly = (int)((cidx / b.ext[0]) % b.ext[1]);
-        const int lz = (int)(cidx / ((long)b.ext[0] * b.ext[1]));
-        const int xu = b.lo[0] + lx, yu = b.lo[1] + ly, zu = b.lo[2] + lz;
-        const int node = wrap(xu, g.nx) + g.nx * (wrap(yu, g.ny) + g.ny * wrap(zu, g.nz));
-        if (owner[node] != (uint16_t)i) continue;
-        if (STEP) owner[node] = FLUID;
-        const double rx = (double)xu - X0, ry = (double)yu - X1;
-        const double ux = usol[node], uy = usol[N + node];
-        s[0] += 1.0;
-        s[1] += ux;
-        s[2] += uy;
-        if constexpr (D == 2) {
-            s[3] += rx * uy - ry * ux;
-            s[4] += rx * rx + ry * ry;
-        } else {
-            const double rz = (double)zu - X2, uz = usol[2 * N + node];
-            s[3] += uz;
-            s[4] += ry * uz - rz * uy;
-            s[5] += rz * ux - rx * uz;
-            s[6] += rx * uy - ry * ux;
-            const double rr = rx * rx + ry * ry + rz * rz;
-            s[7] += rr - rx * rx;
-            s[8] += rr - ry * ry;
-            s[9] += rr - rz * rz;
-            s[10] -= rx * ry;
-            s[11] -= rx * rz;
-            s[12] -= ry * rz;
+        for (int u = 0; u < U; ++u) {
+            int xu, yu, zu;
+            const int node = base + u * nl < b.cells ? walk_node(b, w, g, xu, yu, zu) : 0;
+            w.next();
+            o[u] = owner_in[node];
+            ux[u] = usol[node];
+            uy[u] = usol[N + node];
+            uz[u] = D == 3 ? usol[2 * N + node] : 0.0;
+        }
+        CellWalk w1 = w0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int xu, yu, zu;
+            const int node = walk_node(b, w1, g, xu, yu, zu);
+            w1.next();
+            if (base + u * nl >= b.cells || o[u] != (uint16_t)i) continue;
+            if (owner_clr) owner_clr[node] = FLUID;
+            const double rx = (double)xu - X0, ry = (double)yu - X1;
+            s[0] += 1.0;
+            s[1] += ux[u];
+            s[2] += uy[u];
+            if constexpr (D == 2) {
+                s[3] += rx * uy[u] - ry * ux[u];
+                s[4] += rx * rx + ry * ry;
+            } else {
+                const double rz = (double)zu - X2;
+                s[3] += uz[u];
+                s[4] += ry * uz[u] - rz * uy[u];
+                s[5] += rz * ux[u] - rx * uz[u];
+                s[6] += rx * uy[u] - ry * ux[u];
+                const double rr = rx * rx + ry * ry + rz * rz;
+                s[7] += rr - rx * rx;
+                s[8] += rr - ry * ry;
+                s[9] += rr - rz * rz;
+                s[10] -= rx * ry;
+                s[11] -= rx * rz;
+                s[12] -= ry * rz;
+            }
         }
     }
-    __shared__ double red[NS][256];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) red[k][threadIdx.x] = s[k];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-#pragma unroll
-            for (int k = 0; k < NS; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-        }
-        __syncthreads();
+}
+
+// State of particle i before the step, as the closing of the sums needs it.
+struct PrevState {
+    double X[3], theta, A[3], Uprev[3], Wprev[3];
+};
+
+__device__ __forceinline__ PrevState load_prev(const PartDev &P, int i)
+{
+    PrevState s;
+    for (int k = 0; k < 3; ++k) {
+        s.X[k] = P.X[3 * i + k];
+        s.A[k] = P.A[3 * i + k];
+        s.Uprev[k] = P.Uprev[3 * i + k];
+        s.Wprev[k] = P.Wprev[3 * i + k];
     }
-    if (threadIdx.x != 0) return;
-    double t[NS];
-    for (int k = 0; k < NS; ++k) {
-        t[k] = red[k][0];
-        P.sums[16 * i + k] = t[k];
-    }
+    s.theta = P.theta[i];
+    return s;
+}
+
+// From the totals t: N, U^n, omega^n.  STEP (inside a time step): the record
+// (layout REC_STRIDE in ctx.h), U_bar = (U^n + U^{n-1})/2, dtheta =
+// (omega^n + omega^{n-1})/2 (z component), then U^{n-1} <- U^n, omega^{n-1} <-
+// omega^n.  Returns N; Ub (3) and dth receive U_bar and dtheta.
+template <int D, bool STEP>
+__device__ __forceinline__ int close_sums(PartDev &P, int i, const double *t, const PrevState &ps, double *rec,
+                                          double *Ub, double &dth)
+{
     const int cnt = (int)t[0];
     P.N[i] = cnt;
     double U[3] = {0, 0, 0}, W[3] = {0, 0, 0};
@@ -193,24 +263,49 @@ __global__ __launch_bounds__(256) void k_reduce(uint16_t *__restrict__ owner, co
         if (rec) {
             double *r = rec + REC_STRIDE * i;
             for (int k = 0; k < 3; ++k) {
-                r[k] = P.X[3 * i + k];
+                r[k] = ps.X[k];
                 r[4 + k] = U[k];
                 r[7 + k] = W[k];
-                r[10 + k] = P.A[3 * i + k];
-                r[14 + k] = P.Uprev[3 * i + k];
+                r[10 + k] = ps.A[k];
+                r[14 + k] = ps.Uprev[k];
             }
-            r[3] = P.theta[i];
+            r[3] = ps.theta;
             r[13] = (double)cnt;
         }
-        P.dth[i] = 0.5 * (W[2] + P.Wprev[3 * i + 2]);
+        dth = 0.5 * (W[2] + ps.Wprev[2]);
+        P.dth[i] = dth;
         for (int k = 0; k < 3; ++k) {
-            P.Ub[3 * i + k] = 0.5 * (U[k] + P.Uprev[3 * i + k]);
+            Ub[k] = 0.5 * (U[k] + ps.Uprev[k]);
+            P.Ub[3 * i + k] = Ub[k];
             P.Uprev[3 * i + k] = U[k];
             P.Wprev[3 * i + k] = W[k];
         }
     }
+    return cnt;
 }
 
+// One workgroup of BS threads per particle.
+template <int D, bool STEP, int BS>
+__global__ __launch_bounds__(BS) void k_sums(const uint16_t *owner_in, uint16_t *owner_clr,
+                                             const double *__restrict__ usol, PartDev P, Geom g,
+                                             double *__restrict__ rec)
+{
+    constexpr int NS = NSums<D>::value;
+    __shared__ double part[BS / WAVE][NS];
+    const int i = blockIdx.x;
+    const PrevState ps = load_prev(P, i);
+    const Box b = make_box(P.lo + 3 * i, P.hi + 3 * i);
+    double s[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) s[k] = 0.0;
+    cell_sums<D, UNR>(owner_in, STEP ? owner_clr : nullptr, usol, g, i, ps.X, b, threadIdx.x, BS, s);
+    block_sum<NS, BS>(s, part);
+    if (threadIdx.x != 0) return;
+    double Ub[3], dth;
+    close_sums<D, STEP>(P, i, s, ps, rec, Ub, dth);
+}
+
+// ------------------------------------------------------- collision forces
 // Contribution of particle j to the particle-particle force on i at centres
 // Yi, Yj (sec. 2.3, eq. 19), minimum image on periodic axes.
 __device__ __forceinline__ void pair_force(const double *Yi, const double *Yj, double Ri, double Rj, double Ci,
@@ -219,7 +314,9 @@ __device__ __forceinline__ void pair_force(const double *Yi, const double *Yj, d
     const int n[3] = {g.nx, g.ny, g.nz};
     const int per[3] = {g.per_x, g.per_y, g.per_z};
     double dv[3] = {0, 0, 0};
-    for (int k = 0; k < rp.d; ++k) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (k >= rp.d) continue;
         dv[k] = Yi[k] - Yj[k];
         if (per[k]) {
             const double h = 0.5 * n[k];
@@ -235,7 +332,8 @@ __device__ __forceinline__ void pair_force(const double *Yi, const double *Yj, d
     const double s = (cut - dist) / rp.delta;
     const double mag = Ci / rp.eps_p * s * s;
     const double scale = rp.cform == 1 ? mag : mag / dist;
-    for (int k = 0; k < rp.d; ++k) F[k] += scale * dv[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) F[k] += scale * dv[k]; // dv = 0 beyond the lattice dimension
 }
 
 // Particle-wall forces through the mirror particle (sec. 2.3, eq. 20).
@@ -244,9 +342,11 @@ __device__ __forceinline__ void wall_force(const double *Yi, double Ri, double C
 {
     const int n[3] = {g.nx, g.ny, g.nz};
     const int per[3] = {g.per_x, g.per_y, g.per_z};
-    for (int k = 0; k < rp.d; ++k) {
-        if (per[k]) continue;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (k >= rp.d || per[k]) continue;
         const double walls[2] = {-0.5, n[k] - 0.5};
+#pragma unroll
         for (int s = 0; s < 2; ++s) {
             const double dv = Yi[k] - (2.0 * walls[s] - Yi[k]); // to the mirror particle
             const double dist = fabs(dv);
@@ -260,93 +360,87 @@ __device__ __forceinline__ void wall_force(const double *Yi, double Ri, double C
 
 // Solid-node acceleration a_i = b_i g + A_i of the lattice kernel
 // (b_i = 1 - rho_f/rho_s,i, or rho_s,i/rho_f - 1 with gravity_form 1).
-__device__ __forceinline__ void write_acc(PartDev &P, const RigidParams &rp, int i)
+__device__ __forceinline__ void write_acc(PartDev &P, const RigidParams &rp, int i, double rho, const double *A)
 {
-    const double bi = rp.gform == 0 ? 1.0 - rp.rho_f / P.rho_s[i] : P.rho_s[i] / rp.rho_f - 1.0;
+    const double bi = rp.gform == 0 ? 1.0 - rp.rho_f / rho : rho / rp.rho_f - 1.0;
     for (int k = 0; k < 3; ++k) {
-        const double acc = (k < rp.d) ? bi * rp.g[k] + P.A[3 * i + k] : 0.0;
+        const double acc = (k < rp.d) ? bi * rp.g[k] + A[k] : 0.0;
         P.acc_d[3 * i + k] = acc;
         P.acc_f[3 * i + k] = (float)acc;
     }
 }
 
-// Claim the nodes of particle i at centre Xc: scan box (bounding radius + 2
-// nodes, clipped on wall axes) stored for the sums and the next clear, then a
-// 16-bit atomic minimum on every node inside the shape.  Called by the whole
-// workgroup; s_X holds the centre.
-__device__ void raster_particle(uint16_t *__restrict__ owner, PartDev &P, const Geom &g, int d, int i,
-                                const double *s_X, int *s_lo, int *s_hi)
+// Closing of Algorithm 1 for particle i: centre Y after the sub-steps (or the
+// single step), summed corrections Dc.  A^{n+1} = 2 * summed corrections;
+// wraps periodic axes, flags a centre that left the box or a particle that
+// covered no node.  Writes X^{n+1} (to P.Xn and Xout), theta^{n+1} (returned),
+// the acceleration table entry.
+__device__ __forceinline__ double close_rigid(PartDev &P, const RigidParams &rp, const Geom &g, int i, const double *Y,
+                                              const double *Dc, int cnt, double rho, double theta, double dth,
+                                              int32_t *flags, double *Xout)
 {
-    if (threadIdx.x == 0) {
-        const int n[3] = {g.nx, g.ny, g.nz};
-        const int per[3] = {g.per_x, g.per_y, g.per_z};
-        const double R = P.a[i];
-        for (int k = 0; k < 3; ++k) {
-            int lo = 0, hi = -1; // empty box for a non-finite or runaway centre
-            if (k >= d) {
-                lo = hi = 0;
-            } else if (fabs(s_X[k]) < 1e9) {
-                lo = (int)floor(s_X[k] - R) - 2;
-                hi = (int)ceil(s_X[k] + R) + 2;
-                if (!per[k]) {
-                    lo = lo < 0 ? 0 : lo;
-                    hi = hi > n[k] - 1 ? n[k] - 1 : hi;
-                }
-            }
-            s_lo[k] = lo;
-            s_hi[k] = hi;
-            if (k < d) {
-                P.lo[3 * i + k] = lo;
-                P.hi[3 * i + k] = hi;
-            }
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int per[3] = {g.per_x, g.per_y, g.per_z};
+    double A[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k) {
+        if (k >= rp.d) {
+            P.Xn[3 * i + k] = 0.0;
+            P.A[3 * i + k] = 0.0;
+            Xout[k] = 0.0;
+            continue;
         }
+        double Xw = Y[k];
+        A[k] = 2.0 * Dc[k];
+        P.A[3 * i + k] = A[k];
+        if (per[k]) {
+            if (Xw >= n[k]) Xw -= n[k];
+            else if (Xw < 0.0) Xw += n[k];
+        } else if (!(Xw >= -0.5 && Xw <= n[k] - 0.5)) {
+            flags[1] = 1; // centre left the box
+        }
+        P.Xn[3 * i + k] = Xw;
+        Xout[k] = Xw;
     }
-    __syncthreads();
-    const int ext[3] = {s_hi[0] - s_lo[0] + 1, s_hi[1] - s_lo[1] + 1, s_hi[2] - s_lo[2] + 1};
-    if (ext[0] <= 0 || ext[1] <= 0 || ext[2] <= 0) return;
-    const long cells = (long)ext[0] * ext[1] * ext[2];
-    const int shape = P.shape[i];
-    const double a = P.a[i], b = P.b[i];
-    double cs = 1.0, sn = 0.0;
-    if (shape == LBM_ELLIPSE) {
-        cs = cos(P.theta[i]);
-        sn = sin(P.theta[i]);
+    if (cnt == 0) flags[1] = 1;
+    double th = theta;
+    if (rp.d == 2) {
+        th = theta + dth;
+        P.theta[i] = th;
     }
-    const double X0 = s_X[0], X1 = s_X[1], X2 = (d == 3) ? s_X[2] : 0.0;
-    for (long cidx = threadIdx.x; cidx < cells; cidx += blockDim.x) {
-        const int lx = (int)(cidx % ext[0]);
-        const int ly = (int)((cidx / ext[0]) % ext[1]);
-        const int lz = (int)(cidx / ((long)ext[0] * ext[1]));
-        const int xu = s_lo[0] + lx, yu = s_lo[1] + ly, zu = s_lo[2] + lz;
-        const double dx = (double)xu - X0, dy = (double)yu - X1, dz = (d == 3) ? (double)zu - X2 : 0.0;
-        if (!inside_shape(shape, a, b, cs, sn, dx, dy, dz)) continue;
-        const int x = wrap(xu, g.nx), y = wrap(yu, g.ny), z = wrap(zu, g.nz);
-        atomic_min_u16(owner + (x + g.nx * (y + g.ny * z)), (uint16_t)i);
-    }
+    write_acc(P, rp, i, rho, A);
+    return th;
 }
 
-// One workgroup per particle.  update = 1 (K = 1): Algorithm 1 for particle
-// i -- the collision forces at X^n and at the prediction X^n + U_bar summed
-// over all other particles in parallel and over the walls, the correction,
-// X^{n+1} into P.Xn, A^{n+1}, theta^{n+1} -- then the new indicator of i.
+// ----------------------------------------------- many bodies: Algorithm 1
+// One workgroup per particle.  update = 1 (K = 1): Algorithm 1 for particle i
+// -- the collision forces at X^n and at the prediction X^n + U_bar summed over
+// all other particles across lanes and over the walls, the correction, X^{n+1}
+// into P.Xn, A^{n+1}, theta^{n+1} -- then the new indicator of i in owner.
 // update = 0: rasterise i at P.X and refresh its acceleration entry.
-// The indicator must be all FLUID on entry (cleared by the step-mode sums).
-__global__ __launch_bounds__(256) void k_rigid_raster(uint16_t *__restrict__ owner, PartDev P, RigidParams rp, Geom g,
-                                                      int update, int32_t *__restrict__ flags)
+template <int BS>
+__global__ __launch_bounds__(BS) void k_rigid_raster(uint16_t *__restrict__ owner, PartDev P, RigidParams rp, Geom g,
+                                                     int update, int32_t *__restrict__ flags)
 {
     const int i = blockIdx.x, d = rp.d;
-    __shared__ double s_X[3];
+    __shared__ double s_X[3], s_cs, s_sn;
     __shared__ int s_lo[3], s_hi[3];
-    __shared__ double red[6][256];
+    __shared__ double part[BS / WAVE][6];
+    const double Ri = P.a[i], Ci = P.Cc[i], rho = P.rho_s[i], theta = P.theta[i], bi = P.b[i];
+    const int shape = P.shape[i];
+    double Xi[3], Yi[3];
+    for (int k = 0; k < 3; ++k) {
+        Xi[k] = P.X[3 * i + k];
+        Yi[k] = Xi[k] + (k < d ? P.Ub[3 * i + k] : 0.0);
+    }
     if (update) {
-        const double Ri = P.a[i], Ci = P.Cc[i];
-        double Xi[3], Yi[3];
-        for (int k = 0; k < 3; ++k) {
-            Xi[k] = P.X[3 * i + k];
-            Yi[k] = Xi[k] + (k < d ? P.Ub[3 * i + k] : 0.0);
-        }
-        double F0[3] = {0, 0, 0}, F1[3] = {0, 0, 0};
-        for (int j = threadIdx.x; j < rp.np; j += blockDim.x) {
+        const int cnt = P.N[i];
+        const double dth = P.dth[i];
+        // orientation of the new indicator, ahead of the force sums (d == 2 only
+        // turns; ellipses are 2D)
+        const double th1 = d == 2 ? theta + dth : theta;
+        const double cs = shape == LBM_ELLIPSE ? cos(th1) : 1.0, sn = shape == LBM_ELLIPSE ? sin(th1) : 0.0;
+        double F[6] = {0, 0, 0, 0, 0, 0};
+        for (int j = threadIdx.x; j < rp.np; j += BS) {
             if (j == i) continue;
             double Xj[3], Yj[3];
             for (int k = 0; k < 3; ++k) {
@@ -354,68 +448,53 @@ __global__ __launch_bounds__(256) void k_rigid_raster(uint16_t *__restrict__ own
                 Yj[k] = Xj[k] + (k < d ? P.Ub[3 * j + k] : 0.0);
             }
             const double Rj = P.a[j];
-            pair_force(Xi, Xj, Ri, Rj, Ci, rp, g, F0);
-            pair_force(Yi, Yj, Ri, Rj, Ci, rp, g, F1);
+            pair_force(Xi, Xj, Ri, Rj, Ci, rp, g, F);
+            pair_force(Yi, Yj, Ri, Rj, Ci, rp, g, F + 3);
         }
-        for (int k = 0; k < 3; ++k) {
-            red[k][threadIdx.x] = F0[k];
-            red[3 + k][threadIdx.x] = F1[k];
-        }
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w)
-                for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-            __syncthreads();
-        }
+        block_sum<6, BS>(F, part);
         if (threadIdx.x == 0) {
-            double G0[3] = {red[0][0], red[1][0], red[2][0]}, G1[3] = {red[3][0], red[4][0], red[5][0]};
-            wall_force(Xi, Ri, Ci, rp, g, G0);
-            wall_force(Yi, Ri, Ci, rp, g, G1);
-            const double M = P.rho_s[i] * (double)P.N[i];
+            wall_force(Xi, Ri, Ci, rp, g, F);
+            wall_force(Yi, Ri, Ci, rp, g, F + 3);
+            const double M = rho * (double)cnt;
             const double c = M > 0.0 ? 1.0 / (2.0 * M) : 0.0;
-            const int n[3] = {g.nx, g.ny, g.nz};
-            const int per[3] = {g.per_x, g.per_y, g.per_z};
+            double Y[3], Dc[3];
             for (int k = 0; k < 3; ++k) {
-                if (k >= d) {
-                    P.Xn[3 * i + k] = 0.0;
-                    s_X[k] = 0.0;
-                    continue;
-                }
-                const double corr = c * (G0[k] + G1[k]) / 2.0;
-                double Xw = Yi[k] + corr;
-                // A^{n+1} = 2 (X^{n+1} - X^n - U_bar) = 2 * correction displacement
-                P.A[3 * i + k] = 2.0 * corr;
-                if (per[k]) {
-                    if (Xw >= n[k]) Xw -= n[k];
-                    else if (Xw < 0.0) Xw += n[k];
-                } else if (!(Xw >= -0.5 && Xw <= n[k] - 0.5)) {
-                    flags[1] = 1; // centre left the box
-                }
-                P.Xn[3 * i + k] = Xw;
-                s_X[k] = Xw;
+                Dc[k] = k < d ? c * (F[k] + F[3 + k]) / 2.0 : 0.0;
+                Y[k] = Yi[k] + Dc[k];
             }
-            if (P.N[i] == 0) flags[1] = 1;
-            if (d == 2) P.theta[i] += P.dth[i];
-            write_acc(P, rp, i);
+            close_rigid(P, rp, g, i, Y, Dc, cnt, rho, theta, dth, flags, s_X);
+            s_cs = cs;
+            s_sn = sn;
         }
     } else if (threadIdx.x == 0) {
-        for (int k = 0; k < 3; ++k) s_X[k] = P.X[3 * i + k];
-        write_acc(P, rp, i);
+        double A[3];
+        for (int k = 0; k < 3; ++k) {
+            s_X[k] = Xi[k];
+            A[k] = P.A[3 * i + k];
+        }
+        write_acc(P, rp, i, rho, A);
+        s_cs = shape == LBM_ELLIPSE ? cos(theta) : 1.0;
+        s_sn = shape == LBM_ELLIPSE ? sin(theta) : 0.0;
+    }
+    if (threadIdx.x == 0) {
+        centre_box(s_X, Ri, g, d, s_lo, s_hi);
+        for (int k = 0; k < 3; ++k) { // unused axes get [0, 0]
+            P.lo[3 * i + k] = s_lo[k];
+            P.hi[3 * i + k] = s_hi[k];
+        }
     }
     __syncthreads();
-    raster_particle(owner, P, g, d, i, s_X, s_lo, s_hi);
+    raster_items<UNR>(owner, g, d, i, s_X, shape, Ri, bi, s_cs, s_sn, s_lo, s_hi, threadIdx.x, BS);
 }
 
-// Algorithm 1 with K > 1 sub-steps: every sub-step needs all predicted
-// positions, so one workgroup of 1024 threads sweeps the particles with a
-// barrier between sub-steps (Jacobi).  Writes P.Xn, A, theta and the
+// Algorithm 1 with K > 1 sub-steps: every sub-step needs all
+// predicted positions, so one workgroup of 1024 threads sweeps the particles
+// with a barrier between sub-steps (Jacobi).  Writes P.Xn, A, theta and the
 // acceleration table; the indicator is then set by k_rigid_raster(update=0)
 // on the swapped positions.
 __global__ __launch_bounds__(1024) void k_rigid_substeps(PartDev P, RigidParams rp, Geom g, int32_t *__restrict__ flags)
 {
     const int np = rp.np, d = rp.d, K = rp.K;
-    const int n[3] = {g.nx, g.ny, g.nz};
-    const int per[3] = {g.per_x, g.per_y, g.per_z};
     for (int i = threadIdx.x; i < np; i += blockDim.x)
         for (int k = 0; k < 3; ++k) {
             P.Y[3 * i + k] = P.X[3 * i + k];
@@ -450,24 +529,12 @@ __global__ __launch_bounds__(1024) void k_rigid_substeps(PartDev P, RigidParams 
         __syncthreads();
     }
     for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        double Y[3], Dc[3], Xo[3];
         for (int k = 0; k < 3; ++k) {
-            if (k >= d) {
-                P.Xn[3 * i + k] = 0.0;
-                continue;
-            }
-            double Xw = P.Y[3 * i + k];
-            P.A[3 * i + k] = 2.0 * P.Dc[3 * i + k];
-            if (per[k]) {
-                if (Xw >= n[k]) Xw -= n[k];
-                else if (Xw < 0.0) Xw += n[k];
-            } else if (!(Xw >= -0.5 && Xw <= n[k] - 0.5)) {
-                flags[1] = 1;
-            }
-            P.Xn[3 * i + k] = Xw;
+            Y[k] = P.Y[3 * i + k];
+            Dc[k] = P.Dc[3 * i + k];
         }
-        if (P.N[i] == 0) flags[1] = 1;
-        if (d == 2) P.theta[i] += P.dth[i];
-        write_acc(P, rp, i);
+        close_rigid(P, rp, g, i, Y, Dc, P.N[i], P.rho_s[i], P.theta[i], P.dth[i], flags, Xo);
     }
 }
 
@@ -488,6 +555,7 @@ __global__ __launch_bounds__(256) void k_copy(u32x4 *__restrict__ dst, const u32
     if (i < n16) dst[i] = src[i];
 }
 
+// ----------------------------------------------------------------- launchers
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s)
 {
     const size_t n16 = bytes / 16;
@@ -501,20 +569,34 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s)
 hipError_t launch_raster_clear(lbm_ctx *c)
 {
     if (c->np == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_raster_clear, dim3(c->np), dim3(256), 0, c->stream, c->owner, c->P, c->geo, c->d);
+    hipLaunchKernelGGL(k_raster_clear, dim3(c->np), dim3(256), 0, c->stream, c->owner, c->P, c->geo);
     return hipGetLastError();
 }
+
+// Workgroup size of the per-particle sums: 256 threads cover a 2D scan box in
+// one batch of loads; 3D boxes are ~10x larger.
+constexpr int SUMS_BS2 = 256, SUMS_BS3 = 512, RIGID_BS = 256;
 
 hipError_t launch_reduce(lbm_ctx *c, int step, double *rec)
 {
     if (c->np == 0) return hipSuccess;
-    dim3 grid(c->np), block(256);
+    const uint16_t *oin = c->owner;
+    uint16_t *oclr = c->owner_next ? nullptr : c->owner;
+    dim3 grid(c->np);
     if (c->d == 2) {
-        if (step) hipLaunchKernelGGL((k_reduce<2, true>), grid, block, 0, c->stream, c->owner, c->usol, c->P, c->geo, rec);
-        else hipLaunchKernelGGL((k_reduce<2, false>), grid, block, 0, c->stream, c->owner, c->usol, c->P, c->geo, rec);
+        if (step)
+            hipLaunchKernelGGL((k_sums<2, true, SUMS_BS2>), grid, dim3(SUMS_BS2), 0, c->stream, oin, oclr, c->usol, c->P,
+                               c->geo, rec);
+        else
+            hipLaunchKernelGGL((k_sums<2, false, SUMS_BS2>), grid, dim3(SUMS_BS2), 0, c->stream, oin, oclr, c->usol,
+                               c->P, c->geo, rec);
     } else {
-        if (step) hipLaunchKernelGGL((k_reduce<3, true>), grid, block, 0, c->stream, c->owner, c->usol, c->P, c->geo, rec);
-        else hipLaunchKernelGGL((k_reduce<3, false>), grid, block, 0, c->stream, c->owner, c->usol, c->P, c->geo, rec);
+        if (step)
+            hipLaunchKernelGGL((k_sums<3, true, SUMS_BS3>), grid, dim3(SUMS_BS3), 0, c->stream, oin, oclr, c->usol, c->P,
+                               c->geo, rec);
+        else
+            hipLaunchKernelGGL((k_sums<3, false, SUMS_BS3>), grid, dim3(SUMS_BS3), 0, c->stream, oin, oclr, c->usol,
+                               c->P, c->geo, rec);
     }
     return hipGetLastError();
 }
@@ -524,8 +606,9 @@ hipError_t launch_rigid_raster(lbm_ctx *c, int update)
     if (c->np == 0) return hipSuccess;
     RigidParams rp = c->rp;
     rp.np = c->np;
-    hipLaunchKernelGGL(k_rigid_raster, dim3(c->np), dim3(256), 0, c->stream, c->owner, c->P, rp, c->geo, update,
-                       c->flags);
+    uint16_t *out = c->owner_next ? c->owner_next : c->owner;
+    hipLaunchKernelGGL((k_rigid_raster<RIGID_BS>), dim3(c->np), dim3(RIGID_BS), 0, c->stream, out, c->P, rp, c->geo,
+                       update, c->flags);
     return hipGetLastError();
 }
 

@@ -68,6 +68,10 @@ def load():
         return _LIB
     if not os.path.exists(LIB_PATH):
         raise LbmUnavailable(f"{LIB_PATH} is not built; run `python -m paper_2511_01629_amd.build`")
+    # torch ships its own HIP runtime under the same soname as the system one;
+    # load torch first so the library binds to the runtime that owns torch's
+    # device memory and streams
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
     dp = C.POINTER(C.c_double)
@@ -183,7 +187,7 @@ class Simulation:
     def _check(self, rc, ctx=...):
         if rc != LBM_OK:
             c = self.ctx if ctx is ... else ctx
-            msg = self.lib.lbm_last_error(c).decode() if c else ""
+            msg = self.lib.lbm_last_error(c if c else None).decode()
             raise LbmError(rc, msg)
 
     def close(self):

@@ -8,65 +8,71 @@ Parameters: the 16 densities rho_s, tau (alpha = 1/tau follows it) and |g|.
 Two oracle gradients, both FP64 and both with the indicator sequence of the
 base run (a binary indicator makes L piecewise smooth; the derivative is the
 one of the step map with the indicator frozen):
-  * complex step: one run of the complex-valued oracle per parameter, with an
-    imaginary perturbation 1e-30 (exact to rounding);
+  * complex step, for every parameter: one run of the complex-valued oracle
+    with an imaginary perturbation 1e-30 (exact to rounding);
   * central differences with h_k = 1e-6 |theta_k|, the indicator replayed from
-    the centres and orientations recorded in the base run.
+    the centres and orientations recorded in the base run, for a subset of the
+    parameters (--fd) as an independent check of the complex step.
+
+Each parameter is one job, run in a child process, whose result is kept in
+--partial so that an interrupted run resumes where it stopped.
 
 Calls only oracle/; writes tests/golden/adjoint_512x1024_grad.json.
-    python tests/golden/make_adjoint_golden.py [--steps 5000]
+    python tests/golden/make_adjoint_golden.py --partial DIR [--jobs 3 --threads 2]
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import oracle as O  # noqa: E402
-from paper_2511_01629_amd.workloads import workload  # noqa: E402  (inputs only)
+NAME = "adjoint_512x1024"
+FD_DEFAULT = "rho_s[0],rho_s[9],tau,gmag"
 
 
-def loss_of(o, axis=1):
-    return float(o.particles()["X"][:, axis].mean())
+def _setup():
+    from paper_2511_01629_amd.workloads import workload  # inputs only
 
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                                                  "adjoint_512x1024_grad.json"))
-    args = ap.parse_args()
-    cfg, parts, _, _ = workload("adjoint_512x1024")
-    T = args.steps
-    npart = len(parts)
+    cfg, parts, _, _ = workload(NAME)
     gmag = float(np.linalg.norm(cfg["g"]))
-    t0 = time.time()
-    base = O.Oracle(cfg, parts)
-    rec = base.step(T, record=True)
-    L0 = loss_of(base)
-    replay = (rec[:, :, 0:3].copy(), rec[:, :, 3].copy())
-    print(f"base run {time.time() - t0:.0f} s, L = {L0!r}", flush=True)
-
-    names = [f"rho_s[{i}]" for i in range(npart)] + ["tau", "gmag"]
+    names = [f"rho_s[{i}]" for i in range(len(parts))] + ["tau", "gmag"]
     values = [p["rho_s"] for p in parts] + [cfg["tau"], gmag]
-    cs, fd = [], []
-    for k, name in enumerate(names):
-        seed = dict(d_rho_s=[0.0] * npart, d_tau=0.0, d_gmag=0.0, h=1e-30)
-        if k < npart:
-            seed["d_rho_s"][k] = 1.0
-        elif name == "tau":
-            seed["d_tau"] = 1.0
-        else:
-            seed["d_gmag"] = 1.0
-        oc = O.Oracle(cfg, parts, complex_step=seed)
-        oc.step(T)
-        cs.append(float(oc.particles(imag=True)["X"][:, 1].mean() / seed["h"]))
-        del oc
+    return cfg, parts, gmag, names, values
+
+
+def _mean_height(o, imag=False):
+    return float(o.particles(imag=imag)["X"][:, 1].mean())
+
+
+def run_one(k, steps, partial, do_fd):
+    """Complex-step (and optionally central-difference) derivative for parameter k."""
+    from oracle import oracle as O
+
+    cfg, parts, gmag, names, values = _setup()
+    name, npart = names[k], len(parts)
+    seed = dict(d_rho_s=[0.0] * npart, d_tau=0.0, d_gmag=0.0, h=1e-30)
+    if k < npart:
+        seed["d_rho_s"][k] = 1.0
+    elif name == "tau":
+        seed["d_tau"] = 1.0
+    else:
+        seed["d_gmag"] = 1.0
+    t0 = time.time()
+    oc = O.Oracle(cfg, parts, complex_step=seed)
+    oc.step(steps)
+    cs = _mean_height(oc, imag=True) / seed["h"]
+    del oc
+    fd = None
+    if do_fd:
+        base = np.load(os.path.join(partial, "base.npz"))
+        replay = (np.ascontiguousarray(base["X"]), np.ascontiguousarray(base["theta"]))
         h = 1e-6 * abs(values[k])
         Ls = []
         for sgn in (+1, -1):
@@ -80,16 +86,73 @@ def main():
                 c2["g"] = tuple(np.asarray(cfg["g"]) * (gmag + sgn * h) / gmag)
             o = O.Oracle(c2, p2)
             o.set_replay(0, *replay)
-            o.step(T)
-            Ls.append(loss_of(o))
+            o.step(steps)
+            Ls.append(_mean_height(o))
             del o
-        fd.append((Ls[0] - Ls[1]) / (2 * h))
-        print(f"{name}: complex step {cs[-1]!r}  central diff {fd[-1]!r}  ({time.time() - t0:.0f} s)", flush=True)
+        fd = (Ls[0] - Ls[1]) / (2 * h)
+    out = dict(k=k, name=name, complex_step=cs, central_diff=fd, seconds=time.time() - t0)
+    tmp = os.path.join(partial, f"p{k:02d}.json.tmp")
+    with open(tmp, "w") as f:
+        json.dump(out, f)
+    os.replace(tmp, os.path.join(partial, f"p{k:02d}.json"))
 
-    out = dict(workload="adjoint_512x1024", steps=T, loss="mean final Y of the 16 disks", loss_value=L0,
-               params=names, values=values, grad_complex_step=cs, grad_central_diff=fd,
-               fd_rel_step=1e-6, complex_step_h=1e-30,
-               note="FP64 oracle; indicator frozen at the base run (replayed for the differences)")
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--partial", required=True, help="directory for per-parameter results")
+    ap.add_argument("--jobs", type=int, default=3)
+    ap.add_argument("--threads", type=int, default=2, help="OpenMP threads per job")
+    ap.add_argument("--fd", default=FD_DEFAULT, help="parameters that also get central differences")
+    ap.add_argument("--one", type=int, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                  f"{NAME}_grad.json"))
+    args = ap.parse_args()
+    os.makedirs(args.partial, exist_ok=True)
+    fd_names = set(s for s in args.fd.split(",") if s)
+    cfg, parts, gmag, names, values = _setup()
+    if args.one is not None:
+        run_one(args.one, args.steps, args.partial, names[args.one] in fd_names)
+        return
+
+    from oracle import oracle as O
+
+    t0 = time.time()
+    meta = os.path.join(args.partial, "base.json")
+    if os.path.exists(meta) and json.load(open(meta))["steps"] == args.steps:
+        L0 = json.load(open(meta))["loss"]
+    else:
+        base = O.Oracle(cfg, parts)
+        rec = base.step(args.steps, record=True)
+        L0 = _mean_height(base)
+        np.savez(os.path.join(args.partial, "base.npz"), X=rec[:, :, 0:3].copy(), theta=rec[:, :, 3].copy())
+        with open(meta, "w") as f:
+            json.dump(dict(steps=args.steps, loss=L0), f)
+        del base
+    print(f"base run done ({time.time() - t0:.0f} s), L = {L0!r}", flush=True)
+
+    todo = [k for k in range(len(names)) if not os.path.exists(os.path.join(args.partial, f"p{k:02d}.json"))]
+    env = dict(os.environ, OMP_NUM_THREADS=str(args.threads))
+
+    def job(k):
+        cmd = [sys.executable, os.path.abspath(__file__), "--one", str(k), "--steps", str(args.steps),
+               "--partial", args.partial, "--fd", args.fd]
+        r = subprocess.run(cmd, env=env)
+        res = json.load(open(os.path.join(args.partial, f"p{k:02d}.json"))) if r.returncode == 0 else None
+        print(f"{names[k]}: rc {r.returncode} {res} ({time.time() - t0:.0f} s)", flush=True)
+        return r.returncode
+
+    with ThreadPoolExecutor(args.jobs) as ex:
+        rcs = list(ex.map(job, todo))
+    if any(rcs):
+        sys.exit("some parameter jobs failed; run again to resume")
+
+    res = [json.load(open(os.path.join(args.partial, f"p{k:02d}.json"))) for k in range(len(names))]
+    out = dict(workload=NAME, steps=args.steps, loss="mean final Y of the 16 disks", loss_value=L0,
+               params=names, values=values, grad_complex_step=[r["complex_step"] for r in res],
+               grad_central_diff=[r["central_diff"] for r in res], fd_rel_step=1e-6, complex_step_h=1e-30,
+               note="FP64 oracle; indicator frozen at the base run (replayed for the differences); "
+                    "central differences only where not null")
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", args.out)

@@ -74,4 +74,9 @@ def test_null_arguments():
     assert lib.lbm_create(None, None) == lbm.LBM_EINVAL
     assert lib.lbm_destroy(None) == lbm.LBM_EINVAL
     assert lib.lbm_step(None, 1) == lbm.LBM_EINVAL
-    assert lib.lbm_last_error(None) == b"no context"
+    # a rejected configuration leaves its reason for lbm_last_error(NULL)
+    bad = lbm.make_config(_base(), storage="f32", max_particles=8)
+    bad.tau = 0.4
+    out = C.c_void_p()
+    assert lib.lbm_create(C.byref(bad), C.byref(out)) == lbm.LBM_EINVAL and not out.value
+    assert b"tau" in lib.lbm_last_error(None)

@@ -153,3 +153,17 @@ def test_autograd_wrapper_matches_oracle():
     o = O.Oracle(cfg, parts)
     o.step(50)
     assert abs(loss.item() - o.particles()["X"][:, 1].mean()) < 1e-10
+
+
+def test_adjoint_many_bodies_f64():
+    """70 bodies: the particle adjoints run one workgroup per particle."""
+    banner("adjoint many bodies f64")
+    parts = place((96, 128), [("disk", 3.0, 3.0)] * 70, seed=33, rho_range=(1.3, 1.8), upper_axis=1, gap=0.3,
+                  margin=0.3)
+    cfg = dict(lattice="D2Q9", n=(96, 128, 1), periodic=(0, 0, 0), tau=0.65, g=(0.0, -3e-4, 0.0))
+    w = np.random.default_rng(6).normal(size=(len(parts), 3))
+    w[:, 2] = 0.0
+    steps = 30
+    go = oracle_gradient(cfg, parts, steps, w)
+    ga = gpu_gradient(cfg, parts, steps, 10, w)
+    _check(ga, go, 1e-8)

@@ -175,3 +175,37 @@ def test_substeps_k3():
     cfg = dict(lattice="D2Q9", n=(64, 96, 1), periodic=(0, 0, 0), tau=0.6, g=(0.0, -2e-4, 0.0), K=3)
     _, _, rg, _ = _compare_run(cfg, parts, 200, xtol=1e-11)
     assert (np.abs(rg[:, :, 10:12]).max(axis=(1, 2)) > 0).sum() > 20
+
+
+def test_many_bodies_contacts():
+    """80 bodies, more than the one-workgroup particle kernel takes: the sums
+    and Algorithm 1 run one workgroup per particle; contacts, x periodic, even
+    width (two nodes per indicator claim)."""
+    banner("many bodies 128x160")
+    kinds = [("disk", 3.0, 3.0)] * 56 + [("ellipse", 4.0, 2.0)] * 24
+    parts = place((128, 160), kinds, seed=11, rho_range=(1.2, 1.8), upper_axis=1, gap=0.3, margin=0.3)
+    cfg = dict(lattice="D2Q9", n=(128, 160, 1), periodic=(1, 0, 0), tau=0.6, g=(0.0, -2e-4, 0.0))
+    _, _, rg, _ = _compare_run(cfg, parts, 150, xtol=1e-11)
+    assert (np.abs(rg[:, :, 10:12]).max(axis=(1, 2)) > 0).sum() > 50
+
+
+def test_many_bodies_substeps_k3():
+    """The many-body path with K = 3 (one-workgroup sub-step integration, then
+    the indicator), odd width (one node per claim)."""
+    banner("many bodies K=3 127x160")
+    kinds = [("disk", 3.0, 3.0)] * 70
+    parts = place((127, 160), kinds, seed=13, rho_range=(1.2, 1.8), upper_axis=1, gap=0.3, margin=0.3)
+    cfg = dict(lattice="D2Q9", n=(127, 160, 1), periodic=(0, 0, 0), tau=0.6, g=(0.0, -2e-4, 0.0), K=3)
+    _, _, rg, _ = _compare_run(cfg, parts, 100, xtol=1e-11)
+    assert (np.abs(rg[:, :, 10:12]).max(axis=(1, 2)) > 0).sum() > 20
+
+
+def test_large_boxes_3d():
+    """Six spheres of radius 6: few bodies, but scan boxes too large for the
+    one-workgroup kernel; odd width, z periodic."""
+    banner("large boxes 3d 41x48x40")
+    parts = place((41, 48, 40), [("sphere", 6.0, 6.0)] * 6, seed=12, rho_range=(1.2, 1.6), upper_axis=1, gap=0.5,
+                  margin=0.3)
+    cfg = dict(lattice="D3Q19", n=(41, 48, 40), periodic=(0, 0, 1), tau=0.65, g=(0.0, -5e-4, 0.0))
+    f0 = random_state((40, 48, 41), 19, 1e-3, seed=6)
+    _compare_run(cfg, parts, 10, f0=f0)
