@@ -30,8 +30,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 MATH = {"f64": "f64", "f32": "f32", "f16": "f32", "bf16": "f32"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = ["paper_2511_01629_amd/csrc/stream_collide.hip", "paper_2511_01629_amd/csrc/lattice.h",
-                  "paper_2511_01629_amd/csrc/ctx.h"]
+KERNEL_SOURCES = ["paper_2511_01629_amd/csrc/stream_collide.hip", "paper_2511_01629_amd/csrc/node.h",
+                  "paper_2511_01629_amd/csrc/lattice.h", "paper_2511_01629_amd/csrc/ctx.h",
+                  "paper_2511_01629_amd/csrc/dispatch.h"]
 
 
 def log(msg):
@@ -58,6 +59,48 @@ def measured_traffic(key):
         return None
     w = t.get("workloads", {}).get(key)
     return None if w is None else w.get("bytes_per_launch")
+
+
+def _counter_kib(csv_path, kernel_prefix):
+    """Mean value (KiB per dispatch) of the counter in a rocprofv3 counter CSV
+    over the dispatches of kernels whose name contains kernel_prefix."""
+    import csv
+
+    vals = []
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if kernel_prefix in r["Kernel_Name"]:
+                vals.append(float(r["Counter_Value"]))
+    if not vals:
+        raise SystemExit(f"no dispatch of {kernel_prefix} in {csv_path}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def record_traffic(root, storages, workload_name, copy_bytes):
+    """Turn the FETCH_SIZE and WRITE_SIZE counter runs under root
+    (pmc_FETCH_SIZE_<storage>/, pmc_WRITE_SIZE_<storage>/, each holding the
+    rocprofv3 run_counter_collection.csv of `bench.py --steps 5 --warmup 2
+    --no-modes --no-cpu --storage <storage>`) into profiles/traffic.json:
+    HBM bytes per launch of the fused kernel, each counter scaled by what it
+    reads for the library's copy kernel on copy_bytes read + copy_bytes written
+    in the same run."""
+    out = {"source_sha": kernel_source_sha(), "sources": KERNEL_SOURCES, "workloads": {}}
+    for st in storages:
+        entry = {}
+        for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+            path = os.path.join(root, f"pmc_{ctr}_{st}", "run_counter_collection.csv")
+            k_kib, k_n = _counter_kib(path, "k_stream_collide")
+            c_kib, c_n = _counter_kib(path, "k_copy")
+            scale = copy_bytes / 1024.0 / c_kib
+            entry[ctr] = {"kernel_kib": k_kib, "kernel_dispatches": k_n, "copy_kib": c_kib, "copy_dispatches": c_n,
+                          "scale": scale, "bytes": k_kib * 1024.0 * scale}
+        entry["bytes_per_launch"] = entry["FETCH_SIZE"]["bytes"] + entry["WRITE_SIZE"]["bytes"]
+        out["workloads"][f"{workload_name}/{st}"] = entry
+        log(f"{workload_name}/{st}: {entry['bytes_per_launch'] / 1e6:.1f} MB per launch "
+            f"(read scale {entry['FETCH_SIZE']['scale']:.3f}, write scale {entry['WRITE_SIZE']['scale']:.3f})")
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    log(f"wrote {TRAFFIC_FILE}")
 
 
 def run_mode(name, storage, steps, warmup, profile=True):
@@ -100,9 +143,10 @@ def run_mode(name, storage, steps, warmup, profile=True):
     return out
 
 
-def run_adjoint(name, storage, every):
+def run_adjoint(name, storage, every, max_steps=None):
     """Forward with checkpoints + hand-written adjoint on the differentiated
-    workload; fwd+adj MLUPS counts each node-step once."""
+    workload; fwd+adj MLUPS counts each node-step once.  max_steps shortens the
+    run (profiling)."""
     import torch
 
     import numpy as np
@@ -111,6 +155,8 @@ def run_adjoint(name, storage, every):
     from paper_2511_01629_amd.workloads import workload
 
     cfg, parts, steps, _ = workload(name)
+    if max_steps:
+        steps = min(steps, max_steps)
     sim = lbm.Simulation(cfg, parts, storage=storage, device=0)
     N = sim.N
     seed = np.zeros((len(parts), 3))
@@ -138,7 +184,10 @@ def run_adjoint(name, storage, every):
                 grad_rho_s_first=float(g_rho[0]))
 
 
-def copy_ceiling(nbytes=2 << 30, reps=20):
+COPY_BYTES = 2 << 30  # copy-ceiling buffer: the counter calibration relies on this size
+
+
+def copy_ceiling(nbytes=COPY_BYTES, reps=20):
     import torch
 
     from paper_2511_01629_amd import lbm
@@ -193,7 +242,15 @@ def main():
     ap.add_argument("--no-modes", action="store_true", help="headline configuration only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the forward + adjoint leg (checkpoint every 100, then every step kept)")
+    ap.add_argument("--adj-steps", type=int, default=None, help="shorten the forward + adjoint leg (profiling)")
+    ap.add_argument("--record-traffic", metavar="DIR", default=None,
+                    help="write profiles/traffic.json from the counter runs under DIR (no GPU needed)")
     args = ap.parse_args()
+    if args.record_traffic:
+        record_traffic(args.record_traffic, ("f32", "f16"), args.workload, COPY_BYTES)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path shards as "
               f"slabs with halo exchange, which this build does not run)", file=sys.stderr)
@@ -206,6 +263,12 @@ def main():
     lbm.load()
     torch.cuda.init()
     log(f"device: {torch.cuda.get_device_name(0)}")
+    if args.adjoint_only:
+        for every in (100, 1):
+            adj = run_adjoint("adjoint_512x1024", "f32", every, args.adj_steps)
+            log(f"every {every}: {adj['mlups']:.0f} MLUPS fwd+adj ({adj['ms_forward']:.1f} ms forward, "
+                f"{adj['ms_backward']:.1f} ms backward, {adj['steps']} steps), {adj['frac']:.3f} of roofline")
+        return
     log(f"headline {args.workload} {args.storage}: warmup {args.warmup}, steps {args.steps}")
     head = run_mode(args.workload, args.storage, args.steps, args.warmup)
     log(f"  {head['mlups']:.0f} MLUPS, fused kernel {head['kernel_gbs']:.0f} GB/s ({head['kernel_frac']:.3f})")
@@ -222,7 +285,7 @@ def main():
     if not args.no_modes:
         log("forward + adjoint adjoint_512x1024 f32 (5000 steps; checkpoint every 100, and every step kept)")
         for every in (100, 1):
-            adj = run_adjoint("adjoint_512x1024", "f32", every)
+            adj = run_adjoint("adjoint_512x1024", "f32", every, args.adj_steps)
             modes[f"adjoint_512x1024/f32/fwd+adj/every{every}"] = adj
             log(f"  every {every}: {adj['mlups']:.0f} MLUPS fwd+adj ({adj['ms_forward']:.0f} ms forward, "
                 f"{adj['ms_backward']:.0f} ms backward), {adj['frac']:.3f} of roofline")

@@ -179,7 +179,8 @@ int lbm_forward_checkpointed(lbm_ctx *ctx, int64_t nsteps, int32_t every);
 int lbm_backward(lbm_ctx *ctx, const double *dL_dX, double *g_rho_s, double *g_tau, double *g_gmag);
 
 /* Per-kernel timing with HIP events (measurement aid).  While enabled,
- * every kernel lbm_step queues is bracketed by events, and lbm_step waits
+ * every kernel lbm_step queues records its own start and end in a pair of
+ * events (the kernel's execution, without the dispatch latency), and lbm_step waits
  * for the stream before returning.  lbm_profile_read returns, per kernel
  * class, the summed duration in milliseconds and the launch count since the
  * last reset (reset = 1 clears them afterwards).  Classes, in order:

@@ -1,6 +1,7 @@
 // ctx.h -- the context behind the C ABI and the launchers each kernel file
 // provides.  Private to the library.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -97,8 +98,11 @@ struct lbm_ctx {
     // differentiated run (lbm_forward_checkpointed / lbm_backward)
     GradState *grad;
     int fresh; // no step since the last lbm_set_particles
-    // per-kernel event timing (lbm_profile)
+    // per-kernel event timing (lbm_profile): while tev[0] is set, the next
+    // launch through lbm::launch records its own start and end in tev
     int prof;
+    hipEvent_t tev[2];
+    int tev_used;
     std::vector<hipEvent_t> ev_pool;
     double prof_ms[LBM_NKERNELS];
     int64_t prof_cnt[LBM_NKERNELS];
@@ -106,6 +110,22 @@ struct lbm_ctx {
 };
 
 namespace lbm {
+
+// Launch a kernel on the context stream.  While a step is profiled, the
+// kernel's own start and end timestamps go to the context's event pair (the
+// time between them excludes the dispatch latency an event recorded on the
+// stream around the launch would add).
+template <typename... Args, typename F>
+inline hipError_t launch(lbm_ctx *c, F kernel, dim3 grid, dim3 block, Args... args)
+{
+    if (c->tev[0]) {
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, c->stream, c->tev[0], c->tev[1], 0, args...);
+        c->tev_used = 1;
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, 0, c->stream, args...);
+    }
+    return hipGetLastError();
+}
 
 // stream_collide.hip
 hipError_t launch_stream_collide(lbm_ctx *c, const void *fin, void *fout);

@@ -582,23 +582,13 @@ hipError_t launch_reduce(lbm_ctx *c, int step, double *rec)
     if (c->np == 0) return hipSuccess;
     const uint16_t *oin = c->owner;
     uint16_t *oclr = c->owner_next ? nullptr : c->owner;
-    dim3 grid(c->np);
-    if (c->d == 2) {
-        if (step)
-            hipLaunchKernelGGL((k_sums<2, true, SUMS_BS2>), grid, dim3(SUMS_BS2), 0, c->stream, oin, oclr, c->usol, c->P,
-                               c->geo, rec);
-        else
-            hipLaunchKernelGGL((k_sums<2, false, SUMS_BS2>), grid, dim3(SUMS_BS2), 0, c->stream, oin, oclr, c->usol,
-                               c->P, c->geo, rec);
-    } else {
-        if (step)
-            hipLaunchKernelGGL((k_sums<3, true, SUMS_BS3>), grid, dim3(SUMS_BS3), 0, c->stream, oin, oclr, c->usol, c->P,
-                               c->geo, rec);
-        else
-            hipLaunchKernelGGL((k_sums<3, false, SUMS_BS3>), grid, dim3(SUMS_BS3), 0, c->stream, oin, oclr, c->usol,
-                               c->P, c->geo, rec);
-    }
-    return hipGetLastError();
+    const dim3 grid(c->np);
+    const double *us = c->usol;
+    if (c->d == 2)
+        return step ? launch(c, k_sums<2, true, SUMS_BS2>, grid, dim3(SUMS_BS2), oin, oclr, us, c->P, c->geo, rec)
+                    : launch(c, k_sums<2, false, SUMS_BS2>, grid, dim3(SUMS_BS2), oin, oclr, us, c->P, c->geo, rec);
+    return step ? launch(c, k_sums<3, true, SUMS_BS3>, grid, dim3(SUMS_BS3), oin, oclr, us, c->P, c->geo, rec)
+                : launch(c, k_sums<3, false, SUMS_BS3>, grid, dim3(SUMS_BS3), oin, oclr, us, c->P, c->geo, rec);
 }
 
 hipError_t launch_rigid_raster(lbm_ctx *c, int update)
@@ -607,9 +597,7 @@ hipError_t launch_rigid_raster(lbm_ctx *c, int update)
     RigidParams rp = c->rp;
     rp.np = c->np;
     uint16_t *out = c->owner_next ? c->owner_next : c->owner;
-    hipLaunchKernelGGL((k_rigid_raster<RIGID_BS>), dim3(c->np), dim3(RIGID_BS), 0, c->stream, out, c->P, rp, c->geo,
-                       update, c->flags);
-    return hipGetLastError();
+    return launch(c, k_rigid_raster<RIGID_BS>, dim3(c->np), dim3(RIGID_BS), out, c->P, rp, c->geo, update, c->flags);
 }
 
 hipError_t launch_rigid_substeps(lbm_ctx *c)
@@ -617,8 +605,7 @@ hipError_t launch_rigid_substeps(lbm_ctx *c)
     if (c->np == 0) return hipSuccess;
     RigidParams rp = c->rp;
     rp.np = c->np;
-    hipLaunchKernelGGL(k_rigid_substeps, dim3(1), dim3(1024), 0, c->stream, c->P, rp, c->geo, c->flags);
-    return hipGetLastError();
+    return launch(c, k_rigid_substeps, dim3(1), dim3(1024), c->P, rp, c->geo, c->flags);
 }
 
 hipError_t launch_owner_to_int(lbm_ctx *c, int32_t *out)

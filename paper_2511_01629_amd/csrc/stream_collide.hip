@@ -179,10 +179,8 @@ hipError_t launch_stream_collide(lbm_ctx *c, const void *fin, void *fout)
         using St = decltype(S);
         using Tt = decltype(T);
         const Tt *acc = std::is_same<Tt, double>::value ? (const Tt *)c->P.acc_d : (const Tt *)c->P.acc_f;
-        hipLaunchKernelGGL((k_stream_collide<Lt, St, Tt>), dim3(blocks), dim3(256), 0, c->stream,
-                           (const typename St::raw *)fin, (typename St::raw *)fout, c->owner, acc, c->usol, c->flags,
-                           c->geo, c->sp, gx);
-        return hipGetLastError();
+        return launch(c, k_stream_collide<Lt, St, Tt>, dim3(blocks), dim3(256), (const typename St::raw *)fin,
+                      (typename St::raw *)fout, (const uint16_t *)c->owner, acc, c->usol, c->flags, c->geo, c->sp, gx);
     });
 }
 
