@@ -84,6 +84,19 @@ template <> __device__ __forceinline__ float ldc<StBF16, float>(const uint16_t *
     return __uint_as_float((uint32_t)*p << 16);
 }
 
+// Raw element <-> arithmetic type without a memory access (LDS staging);
+// the same conversions as ld / st.
+template <class S, class T> __device__ __forceinline__ T from_raw(typename S::raw r);
+template <class S, class T> __device__ __forceinline__ typename S::raw to_raw(T v);
+template <> __device__ __forceinline__ double from_raw<StF64, double>(double r) { return r; }
+template <> __device__ __forceinline__ float from_raw<StF32, float>(float r) { return r; }
+template <> __device__ __forceinline__ float from_raw<StF16, float>(_Float16 r) { return (float)r; }
+template <> __device__ __forceinline__ float from_raw<StBF16, float>(uint16_t r) { return __uint_as_float((uint32_t)r << 16); }
+template <> __device__ __forceinline__ double to_raw<StF64, double>(double v) { return v; }
+template <> __device__ __forceinline__ float to_raw<StF32, float>(float v) { return v; }
+template <> __device__ __forceinline__ _Float16 to_raw<StF16, float>(float v) { return (_Float16)v; }
+template <> __device__ __forceinline__ uint16_t to_raw<StBF16, float>(float v) { return f32_to_bf16_rne(v); }
+
 constexpr uint16_t FLUID = 0xFFFFu; // owner-map value of a fluid node
 
 } // namespace lbm

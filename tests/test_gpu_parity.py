@@ -23,6 +23,7 @@ TOL = 1e-12
     ("D2Q9", (33, 20, 1), (1, 1, 0)),
     ("D3Q19", (13, 11, 9), (0, 0, 0)),
     ("D3Q19", (13, 11, 9), (1, 0, 1)),
+    ("D3Q19", (12, 11, 9), (1, 1, 0)),
 ])
 def test_fluid_step_random_state(kind, n, periodic):
     """Pull streaming with bounce-back/wrap and the BGK collision from a random
@@ -42,6 +43,28 @@ def test_fluid_step_random_state(kind, n, periodic):
     ug, pg, _ = sim.fields()
     uo, po, _ = ora.fields()
     assert rel(ug, uo) < TOL and rel(pg, po) < TOL
+
+
+@pytest.mark.parametrize("n,periodic", [
+    ((12, 11, 9), (0, 0, 0)),    # one partial segment, walls on every side
+    ((12, 11, 9), (1, 1, 0)),
+    ((520, 3, 4), (1, 0, 1)),    # three segments: the x halo across segment edges, periodic wrap
+    ((520, 3, 4), (0, 1, 0)),
+])
+def test_fluid_step_random_state_f32_3d(n, periodic):
+    """D3Q19 in FP32 storage, the rows staged through LDS (nx a multiple of 4):
+    the same steps as the FP64 oracle, to FP32 rounding (a few ulp of the
+    populations per step)."""
+    banner(f"fluid random f32 D3Q19 {n} {periodic}")
+    cfg = dict(lattice="D3Q19", n=n, periodic=periodic, tau=0.7, fluid_accel=(2e-5, -1e-5, 3e-6))
+    f0 = random_state((n[2], n[1], n[0]), 19, 2e-3, seed=12).astype(np.float32).astype(np.float64)
+    sim, ora = pair(cfg, [], storage="f32", f0=f0)
+    for steps in (1, 4):
+        sim.step(steps)
+        ora.step(steps)
+        e = rel(sim.populations(), ora.f())
+        print(f"[measured] f32 3D {n} {periodic} after {steps}: {e:.2e}", flush=True)
+        assert e < 5e-6, e
 
 
 def test_penalize_all_random_state():
@@ -98,13 +121,20 @@ def test_particles_random_state_2d():
     assert np.abs(rg[:, :, 10:12]).max() > 1e-6  # contact forces acted
 
 
-def test_particles_3d():
-    banner("particles 3d")
-    cfg = dict(lattice="D3Q19", n=(17, 15, 19), periodic=(0, 1, 0), tau=0.65, g=(0.0, 0.0, -5e-4))
+@pytest.mark.parametrize("nx,storage", [(17, "f64"), (20, "f32")])
+def test_particles_3d(nx, storage):
+    """Two spheres in D3Q19; in FP32 storage with nx a multiple of 4 the rows
+    are staged through LDS."""
+    banner(f"particles 3d nx={nx} {storage}")
+    cfg = dict(lattice="D3Q19", n=(nx, 15, 19), periodic=(0, 1, 0), tau=0.65, g=(0.0, 0.0, -5e-4))
     parts = [dict(shape="sphere", rho_s=1.6, a=3.0, x=(7.0, 7.5, 9.0)),
              dict(shape="sphere", rho_s=1.3, a=3.5, x=(12.2, 8.0, 12.4))]
-    f0 = random_state((19, 15, 17), 19, 1e-3, seed=4)
-    _compare_run(cfg, parts, 12, f0=f0)
+    f0 = random_state((19, 15, nx), 19, 1e-3, seed=4)
+    if storage == "f64":
+        _compare_run(cfg, parts, 12, f0=f0)
+    else:
+        _compare_run(cfg, parts, 12, f0=f0.astype(np.float32).astype(np.float64), storage="f32", tol=5e-6,
+                     xtol=1e-7)
 
 
 def test_floating_disk_workload():
