@@ -543,36 +543,36 @@ static AdjArrays adj_arrays(const AdjArraysHost &h)
                      h.uext_d, h.uext_f, h.acc_d, h.acc_f, h.rho_g,    h.g_g};
 }
 
-hipError_t launch_adj_rigid(lbm_ctx *c, const AdjArraysHost &h)
+hipError_t launch_adj_rigid(lbm_ctx *c, const PartDev &P, const AdjArraysHost &h)
 {
     if (c->np == 0) return hipSuccess;
     RigidParams rp = c->rp;
     rp.np = c->np;
-    hipLaunchKernelGGL(k_adj_rigid, dim3(c->np), dim3(256), 0, c->stream, adj_arrays(h), c->P, rp, c->geo);
+    hipLaunchKernelGGL(k_adj_rigid, dim3(c->np), dim3(256), 0, c->stream, adj_arrays(h), P, rp, c->geo);
     return hipGetLastError();
 }
 
-hipError_t launch_adj_particles(lbm_ctx *c, const uint16_t *owner, const double *asol, const double *rec,
-                                double *Abar_out, double *rho_g, double *g_g)
+hipError_t launch_adj_particles(lbm_ctx *c, const PartDev &P, const uint16_t *owner, const double *asol,
+                                const double *rec, double *Abar_out, double *rho_g, double *g_g)
 {
     if (c->np == 0) return hipSuccess;
     RigidParams rp = c->rp;
     rp.np = c->np;
     if (c->d == 2)
-        hipLaunchKernelGGL(k_adj_particles<2>, dim3(c->np), dim3(256), 0, c->stream, owner, asol, rec, c->P, rp, c->geo,
+        hipLaunchKernelGGL(k_adj_particles<2>, dim3(c->np), dim3(256), 0, c->stream, owner, asol, rec, P, rp, c->geo,
                            Abar_out, rho_g, g_g);
     else
-        hipLaunchKernelGGL(k_adj_particles<3>, dim3(c->np), dim3(256), 0, c->stream, owner, asol, rec, c->P, rp, c->geo,
+        hipLaunchKernelGGL(k_adj_particles<3>, dim3(c->np), dim3(256), 0, c->stream, owner, asol, rec, P, rp, c->geo,
                            Abar_out, rho_g, g_g);
     return hipGetLastError();
 }
 
-hipError_t launch_adj_initial(lbm_ctx *c, const double *Upbar, double *rho_g, double *g_g)
+hipError_t launch_adj_initial(lbm_ctx *c, const PartDev &P, const double *Upbar, double *rho_g, double *g_g)
 {
     if (c->np == 0) return hipSuccess;
     RigidParams rp = c->rp;
     rp.np = c->np;
-    hipLaunchKernelGGL(k_adj_initial, dim3((c->np + 255) / 256), dim3(256), 0, c->stream, c->P, rp, Upbar, rho_g, g_g);
+    hipLaunchKernelGGL(k_adj_initial, dim3((c->np + 255) / 256), dim3(256), 0, c->stream, P, rp, Upbar, rho_g, g_g);
     return hipGetLastError();
 }
 

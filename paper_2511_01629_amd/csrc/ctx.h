@@ -146,10 +146,11 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 hipError_t launch_adj_lattice(lbm_ctx *c, const void *fprev, const uint16_t *owner, const double *uext_d,
                               const float *uext_f, const double *acc_d, const float *acc_f, const void *lam_in,
                               void *lam_out, double *asol, double *tau_part);
-hipError_t launch_adj_rigid(lbm_ctx *c, const AdjArraysHost &h);
-hipError_t launch_adj_particles(lbm_ctx *c, const uint16_t *owner, const double *asol, const double *rec,
-                                double *Abar_out, double *rho_g, double *g_g);
-hipError_t launch_adj_initial(lbm_ctx *c, const double *Upbar, double *rho_g, double *g_g);
+// The particle adjoints read only the constants rho_s, a, b, Cc and shape of P.
+hipError_t launch_adj_rigid(lbm_ctx *c, const PartDev &P, const AdjArraysHost &h);
+hipError_t launch_adj_particles(lbm_ctx *c, const PartDev &P, const uint16_t *owner, const double *asol,
+                                const double *rec, double *Abar_out, double *rho_g, double *g_g);
+hipError_t launch_adj_initial(lbm_ctx *c, const PartDev &P, const double *Upbar, double *rho_g, double *g_g);
 
 
 // api.hip (shared with grad.hip)

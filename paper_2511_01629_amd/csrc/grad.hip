@@ -191,19 +191,41 @@ int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau
     const int gx = (c->geo.nx + 255) / 256;
     const size_t nblocks = (size_t)gx * c->geo.ny * c->geo.nz;
     std::vector<void *> owned;
+    const hipStream_t main_stream = c->stream;
+    // every > 1 with several segments: segment s - 1 is recomputed on a second
+    // stream (default priority) into the other of two segment buffers while
+    // the adjoint sweeps segment s; events order the two.
+    hipStream_t side = nullptr;
+    hipEvent_t ready[2] = {nullptr, nullptr}, freed[2] = {nullptr, nullptr};
+    bool freed_set[2] = {false, false};
     auto cleanup = [&]() {
-        (void)hipStreamSynchronize(c->stream);
+        c->stream = main_stream;
+        (void)hipStreamSynchronize(main_stream);
+        if (side) {
+            (void)hipStreamSynchronize(side);
+            (void)hipStreamDestroy(side);
+        }
+        for (int b = 0; b < 2; ++b) {
+            if (ready[b]) (void)hipEventDestroy(ready[b]);
+            if (freed[b]) (void)hipEventDestroy(freed[b]);
+        }
         for (void *p : owned) (void)hipFree(p);
     };
-    char *seg = nullptr, *lam = nullptr;
+    char *seg = nullptr, *seg2 = nullptr, *lam = nullptr;
+    double *cst = nullptr;
+    int32_t *cshape = nullptr;
     double *asol = nullptr, *taup = nullptr, *Xbar = nullptr, *Abar = nullptr, *Upbar = nullptr, *rho_g = nullptr,
            *g_g = nullptr, *uext_d = nullptr, *acc_d = nullptr;
     float *uext_f = nullptr, *acc_f = nullptr;
     const bool all = G->hist != nullptr;
+    const int nseg = all ? 1 : G->nsnap - 1;
+    const bool overlap = !all && nseg > 1;
     // segment frames: every + 1 population buffers, then every + 1 indicators
     const size_t segsize = all ? 1 : (size_t)(G->every + 1) * (G->fbytes + G->obytes);
     int rc = LBM_OK;
-    if ((rc = dev_alloc(c, &seg, segsize, owned)) || (rc = dev_alloc(c, &lam, 2 * Q * N * lam_elt, owned)) ||
+    if ((rc = dev_alloc(c, &seg, segsize, owned)) || (overlap && (rc = dev_alloc(c, &seg2, segsize, owned))) ||
+        (rc = dev_alloc(c, &cst, 4 * (size_t)np, owned)) || (rc = dev_alloc(c, &cshape, (size_t)np, owned)) ||
+        (rc = dev_alloc(c, &lam, 2 * Q * N * lam_elt, owned)) ||
         (rc = dev_alloc(c, &asol, (size_t)c->d * N, owned)) || (rc = dev_alloc(c, &taup, nblocks, owned)) ||
         (rc = dev_alloc(c, &Xbar, 6 * (size_t)np, owned)) || (rc = dev_alloc(c, &Abar, 3 * (size_t)np, owned)) ||
         (rc = dev_alloc(c, &Upbar, 6 * (size_t)np, owned)) || (rc = dev_alloc(c, &rho_g, np, owned)) ||
@@ -213,6 +235,51 @@ int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau
         cleanup();
         return rc;
     }
+    // the particle constants the adjoint kernels read, in memory of their own
+    // (a snapshot restore on the side stream rewrites the workspace copies)
+    PartDev Pc = c->P;
+    Pc.rho_s = cst;
+    Pc.a = cst + np;
+    Pc.b = cst + 2 * np;
+    Pc.Cc = cst + 3 * np;
+    Pc.shape = cshape;
+    if (hipMemcpyAsync(Pc.rho_s, c->P.rho_s, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(Pc.a, c->P.a, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(Pc.b, c->P.b, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(Pc.Cc, c->P.Cc, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(Pc.shape, c->P.shape, np * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+        cleanup();
+        return c->err = "constant copy failed", LBM_EDEVICE;
+    }
+    if (overlap) {
+        bool ok = hipStreamCreateWithFlags(&side, hipStreamNonBlocking) == hipSuccess;
+        for (int b = 0; b < 2 && ok; ++b)
+            ok = hipEventCreateWithFlags(&ready[b], hipEventDisableTiming) == hipSuccess &&
+                 hipEventCreateWithFlags(&freed[b], hipEventDisableTiming) == hipSuccess;
+        // the side stream starts after everything queued so far on the main one
+        ok = ok && hipEventRecord(freed[1], main_stream) == hipSuccess &&
+             hipStreamWaitEvent(side, freed[1], 0) == hipSuccess;
+        if (!ok) {
+            cleanup();
+            return c->err = "stream or event creation failed", LBM_EDEVICE;
+        }
+    }
+    char *segbuf[2] = {seg, overlap ? seg2 : seg};
+    const int64_t span = all ? G->T : G->every;
+    // recompute segment sg into its buffer on the side stream
+    auto recompute = [&](int sg) -> int {
+        const int b = sg & 1;
+        char *fr = segbuf[b], *ow = segbuf[b] + (size_t)(G->every + 1) * G->fbytes;
+        const int64_t s0 = (int64_t)sg * span, s1 = std::min<int64_t>(s0 + span, G->T);
+        if (freed_set[b] && hipStreamWaitEvent(side, freed[b], 0) != hipSuccess) return LBM_EDEVICE;
+        c->stream = side;
+        int r = restore(c, G, sg, fr, ow);
+        if (r == LBM_OK) r = run_frames(c, G, fr, ow, s1 - s0, nullptr);
+        c->stream = main_stream;
+        if (r == LBM_OK && hipEventRecord(ready[b], side) != hipSuccess) r = LBM_EDEVICE;
+        return r;
+    };
+
     // seed: X_bar^T = dL/dX_final; everything else zero
     std::vector<double> seed(3 * (size_t)np, 0.0);
     for (int i = 0; i < np; ++i)
@@ -228,14 +295,22 @@ int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau
                              Xbar + 3 * np * (cx ^ 1), Upbar + 3 * np * (cu ^ 1), uext_d, uext_f, acc_d, acc_f,
                              rho_g, g_g};
     };
-    const int64_t span = all ? G->T : G->every;
-    const int nseg = all ? 1 : G->nsnap - 1;
+    if (overlap) rc = recompute(nseg - 1);
     for (int sg = nseg - 1; sg >= 0 && rc == LBM_OK; --sg) {
         const int64_t s0 = (int64_t)sg * span, s1 = std::min<int64_t>(s0 + span, G->T);
         char *fr, *ow; // frame n - s0 of populations / indicators
         if (all) {
             fr = G->hist;
             ow = G->hist + (size_t)(G->T + 1) * G->fbytes;
+        } else if (overlap) {
+            // queue the next segment's recomputation first, then this segment's sweep
+            if (sg >= 1 && (rc = recompute(sg - 1))) break;
+            if (hipStreamWaitEvent(main_stream, ready[sg & 1], 0) != hipSuccess) {
+                rc = LBM_EDEVICE;
+                break;
+            }
+            fr = segbuf[sg & 1];
+            ow = fr + (size_t)(G->every + 1) * G->fbytes;
         } else {
             fr = seg;
             ow = seg + (size_t)(G->every + 1) * G->fbytes;
@@ -246,7 +321,7 @@ int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau
             const char *fprev = fr + (size_t)(n - s0) * G->fbytes;
             const uint16_t *own_n = (const uint16_t *)(ow + (size_t)(n - s0) * G->obytes);
             const double *rec_n = G->rec + (size_t)n * np * REC_STRIDE;
-            if (launch_adj_rigid(c, rigid_arrays(n)) != hipSuccess) rc = LBM_EDEVICE;
+            if (launch_adj_rigid(c, Pc, rigid_arrays(n)) != hipSuccess) rc = LBM_EDEVICE;
             cx ^= 1;
             cu ^= 1;
             char *lin = lam + (size_t)cl * Q * N * lam_elt, *lout = lam + (size_t)(cl ^ 1) * Q * N * lam_elt;
@@ -254,11 +329,16 @@ int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau
                 launch_adj_lattice(c, fprev, own_n, uext_d, uext_f, acc_d, acc_f, lin, lout, asol, taup) != hipSuccess)
                 rc = LBM_EDEVICE;
             cl ^= 1;
-            if (rc == LBM_OK && launch_adj_particles(c, own_n, asol, rec_n, Abar, rho_g, g_g) != hipSuccess)
+            if (rc == LBM_OK && launch_adj_particles(c, Pc, own_n, asol, rec_n, Abar, rho_g, g_g) != hipSuccess)
                 rc = LBM_EDEVICE;
         }
+        if (overlap && rc == LBM_OK) {
+            // this segment's buffer may be recomputed into once its sweep is done
+            if (hipEventRecord(freed[sg & 1], main_stream) != hipSuccess) rc = LBM_EDEVICE;
+            freed_set[sg & 1] = true;
+        }
     }
-    if (rc == LBM_OK && launch_adj_initial(c, Upbar + 3 * np * cu, rho_g, g_g) != hipSuccess) rc = LBM_EDEVICE;
+    if (rc == LBM_OK && launch_adj_initial(c, Pc, Upbar + 3 * np * cu, rho_g, g_g) != hipSuccess) rc = LBM_EDEVICE;
     std::vector<double> hr(np), hg(np), ht(nblocks);
     if (rc == LBM_OK) {
         if (hipMemcpyAsync(hr.data(), rho_g, np * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
