@@ -23,7 +23,7 @@ constexpr size_t ALIGN = 256;
 
 // message of the last lbm_workspace_size / lbm_create failure on this thread
 thread_local std::string g_create_err = "no error";
-constexpr int PART_DOUBLES = 3 * 8 + 5 + 3 + 16 + 3 * 5 + 1; // X Xn theta U W Uprev Wprev A, rho a b C, acc, sums, Ub Y Ys Y2 Dc, dth
+constexpr int PART_DOUBLES = 3 * 7 + 1 + 4 + 3 + 3 + 3 * 5 + 1; // X Xn U W Uprev Wprev A, theta, rho a b C, acc, Unext, Ub Y Ys Y2 Dc, dth
 constexpr double CS2 = 1.0 / 3.0;
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
@@ -161,7 +161,7 @@ void carve(lbm_ctx *c, const Layout &L)
     c->P.b = take(1);
     c->P.Cc = take(1);
     c->P.acc_d = take(3);
-    c->P.sums = take(16);
+    c->P.Unext = take(3);
     c->P.Y = take(3);
     c->P.Ys = take(3);
     c->P.Y2 = take(3);
@@ -178,9 +178,11 @@ void carve(lbm_ctx *c, const Layout &L)
 
 } // namespace
 
-// One step queues the lattice update, the momentum sums (which also clear the
-// indicator) and Algorithm 1 with the new indicator (K = 1; K > 1 adds the
-// sub-step integration before it).  With profiling on, each launch is
+// One step queues the lattice update and then, with K = 1 and slots
+// (lbm_set_particles sets them up), Algorithm 1 with the new indicator from
+// the partial sums the lattice kernel wrote; otherwise the momentum sums
+// (which also clear the indicator) and Algorithm 1 with the new indicator
+// (K > 1 adds the sub-step integration before it).  With profiling on, each launch is
 // timed by a pair of pooled events attached to the kernel's own start and end
 // (hipExtLaunchKernelGGL), whose durations are summed per class.
 int lbm::step_impl(lbm_ctx *c, int64_t nsteps, double *rec_dev)
@@ -210,12 +212,19 @@ int lbm::step_impl(lbm_ctx *c, int64_t nsteps, double *rec_dev)
         return hipSuccess;
     };
     for (int64_t s = 0; s < nsteps; ++s) {
+        ++c->epoch; // the stamp of this step's slots
         void *bufs[2] = {c->f[c->cur], c->f[c->cur ^ 1]};
         HIPCHK(c, timed(0, [](lbm_ctx *cc, void *b) { return launch_stream_collide(cc, ((void **)b)[0], ((void **)b)[1]); },
                         bufs));
         c->cur ^= 1;
         double *rec = rec_dev ? rec_dev + (size_t)s * c->np * REC_STRIDE : nullptr;
-        if (c->rp.K == 1) {
+        if (c->rp.K == 1 && c->fused) {
+            // the lattice kernel took the sums: Algorithm 1 and the indicator from the slots
+            HIPCHK(c, timed(2, [](lbm_ctx *cc, void *r) { return launch_rigid_fused(cc, (double *)r); }, rec));
+            std::swap(c->P.X, c->P.Xn);
+            std::swap(c->P.U, c->P.Unext);
+            c->P.Uprev = c->P.U;
+        } else if (c->rp.K == 1) {
             HIPCHK(c, timed(1, [](lbm_ctx *cc, void *r) { return launch_reduce(cc, 1, (double *)r); }, rec));
             HIPCHK(c, timed(2, [](lbm_ctx *cc, void *) { return launch_rigid_raster(cc, 1); }, nullptr));
             std::swap(c->P.X, c->P.Xn);
@@ -318,6 +327,10 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
     c->rec_dev = nullptr;
     c->rec_cap = 0;
     c->owner_next = nullptr;
+    c->slots = nullptr;
+    c->slots_bytes = 0;
+    c->slot_stride = c->slot_kw = c->fused = 0;
+    c->epoch = 0;
     c->prof = 0;
     c->tev[0] = c->tev[1] = nullptr;
     c->tev_used = 0;
@@ -376,6 +389,7 @@ int lbm_destroy(lbm_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     if (c->own_mem) (void)hipFree(c->ws);
     if (c->rec_dev) (void)hipFree(c->rec_dev);
+    if (c->slots) (void)hipFree(c->slots);
     free_grad(c);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
@@ -436,11 +450,40 @@ int lbm_set_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
     HIPCHK(c, hipMemcpyAsync(c->P.shape, shape.data(), sizeof(int32_t) * cap, hipMemcpyHostToDevice, c->stream));
     c->np = n;
     c->host_parts.assign(p, p + n);
+    // fused-sums step (K = 1): slots of (scan-box row) x (wavefronts a box row
+    // can touch) per particle; a box spans at most ceil(2a) + 7 nodes per axis
+    c->fused = 0;
+    if (c->rp.K == 1 && n > 0) {
+        int ext = 0;
+        for (int i = 0; i < n; ++i) ext = std::max(ext, (int)ceil(2.0 * p[i].a) + 7);
+        const int wn = (c->geo.nx + 63) / 64;
+        const int kw = std::min(wn, (ext + 63) / 64 + 3);
+        const int64_t rows = d == 2 ? ext : (int64_t)ext * ext;
+        const int64_t stride = rows * kw;
+        if (stride < 65536) {
+            const size_t need = (size_t)cap * stride * ((d == 2 ? 5 : 13) + 1) * sizeof(double);
+            if (need > c->slots_bytes) {
+                if (c->slots) HIPCHK(c, hipFree(c->slots));
+                c->slots = nullptr;
+                c->slots_bytes = 0;
+                HIPCHK(c, hipMalloc((void **)&c->slots, need));
+                c->slots_bytes = need;
+            }
+            // NaN stamps: no slot counts until a step writes it
+            HIPCHK(c, hipMemsetAsync(c->slots, 0xFF, c->slots_bytes, c->stream));
+            c->slot_stride = (int)stride;
+            c->slot_kw = kw;
+            c->fused = 1;
+        }
+    }
     // indicator, acceleration table, U^0 and omega^0 on the current populations
     HIPCHK(c, launch_rigid_raster(c, 0));
     HIPCHK(c, launch_fields(c, c->f[c->cur], c->usol, nullptr, 1));
     HIPCHK(c, launch_reduce(c, 0, nullptr));
-    HIPCHK(c, hipMemcpyAsync(c->P.Uprev, c->P.U, b3, hipMemcpyDeviceToDevice, c->stream));
+    // U^{-1} = U^0.  With fused sums U^{n-1} is read from U itself (U^n goes to
+    // Unext, swapped in after the step), so U_prev is an alias of U.
+    if (c->fused) c->P.Uprev = c->P.U;
+    else if (c->P.Uprev != c->P.U) HIPCHK(c, hipMemcpyAsync(c->P.Uprev, c->P.U, b3, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->P.Wprev, c->P.W, b3, hipMemcpyDeviceToDevice, c->stream));
     std::vector<int32_t> Nn(cap, 0);
     HIPCHK(c, hipMemcpyAsync(Nn.data(), c->P.N, sizeof(int32_t) * cap, hipMemcpyDeviceToHost, c->stream));
@@ -562,9 +605,10 @@ int lbm_get_particles(lbm_ctx *c, lbm_particle *out, int32_t n)
     if (n > c->np) return fail(c, LBM_EINVAL, "more particles requested than set");
     (void)hipSetDevice(c->device);
     if (c->np > 0) {
-        // measure U^n, omega^n on the current populations
+        // measure U and omega on the current populations, into scratch arrays
+        // (the step state, U^{n-1} included, stays as it is)
         HIPCHK(c, launch_fields(c, c->f[c->cur], c->usol, nullptr, 1));
-        HIPCHK(c, launch_reduce(c, 0, nullptr));
+        HIPCHK(c, launch_reduce(c, 0, nullptr, 1));
     }
     const int cap = c->cap;
     std::vector<double> X(3 * cap), th(cap), U(3 * cap), W(3 * cap), Up(3 * cap), Wp(3 * cap), A(3 * cap);
@@ -572,8 +616,8 @@ int lbm_get_particles(lbm_ctx *c, lbm_particle *out, int32_t n)
     const size_t b3 = sizeof(double) * 3 * cap;
     HIPCHK(c, hipMemcpyAsync(X.data(), c->P.X, b3, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(th.data(), c->P.theta, sizeof(double) * cap, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(U.data(), c->P.U, b3, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(W.data(), c->P.W, b3, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(U.data(), c->np > 0 ? c->P.Y : c->P.U, b3, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(W.data(), c->np > 0 ? c->P.Ys : c->P.W, b3, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(Up.data(), c->P.Uprev, b3, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(Wp.data(), c->P.Wprev, b3, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(A.data(), c->P.A, b3, hipMemcpyDeviceToHost, c->stream));

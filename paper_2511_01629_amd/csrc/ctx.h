@@ -25,11 +25,27 @@ struct PartDev {
     double *rho_s, *a, *b, *Cc;                    // [cap]; Cc = collision constant C_i
     double *acc_d;                                 // [cap*3] solid-node acceleration (FP64 mode)
     float *acc_f;                                  // [cap*3] the same in FP32
-    double *sums;                                  // [cap*16] momentum sums of the last reduction
+    double *Unext;                                 // [cap*3] U^n written by the fused-sums step (swapped with U)
     double *Ub, *dth;                              // U_bar = (U^n + U^{n-1})/2 [cap*3], theta increment [cap]
     double *Y, *Ys, *Y2, *Dc;                      // [cap*3] sub-step scratch (Dc: summed corrections)
     int32_t *shape, *N;                            // [cap]
     int32_t *lo, *hi;                              // [cap*3] scan box (unwrapped node coords)
+};
+
+// Per-particle partial momentum sums written by the lattice kernel (the
+// fused-sums step, K = 1): one slot per (particle, scan-box row, wavefront of
+// that row), each [stamp, sums...]; a slot counts for the step whose stamp it
+// carries, so nothing is ever cleared.  Slot s of particle i starts at
+// slots + (i * stride + s) * width.
+struct SlotParams {
+    double *slots;
+    const double *X;        // particle centres of the step
+    const int32_t *lo, *hi; // the step's scan boxes
+    int stride, kw, wn;     // slots per particle, wavefront slots per row, wavefronts per lattice row
+    double stamp;
+    uint16_t *clear;        // the owner map to reset to FLUID as it is read (in-place steps), or NULL
+    int32_t *flags;         // [1] set if a node falls outside its particle's slots (cannot happen
+                            // for boxes built by the raster; a guard, not a path)
 };
 
 // Everything a kernel needs to know about the lattice.
@@ -91,6 +107,11 @@ struct lbm_ctx {
     int32_t *flags;  // [0] unstable, [1] domain
     lbm::PartDev P;
     int np, cap;
+    // fused-sums step (K = 1): slot buffer (library-owned), its layout, the stamp counter
+    double *slots;
+    size_t slots_bytes;
+    int slot_stride, slot_kw, fused;
+    int64_t epoch;
     int64_t step;
     double *rec_dev;
     size_t rec_cap;
@@ -136,9 +157,11 @@ hipError_t launch_set_populations(lbm_ctx *c, const double *fn, void *fout, int 
 
 // particles.hip
 hipError_t launch_raster_clear(lbm_ctx *c);
-hipError_t launch_reduce(lbm_ctx *c, int step, double *rec);
+hipError_t launch_reduce(lbm_ctx *c, int step, double *rec, int scratch = 0);
 hipError_t launch_rigid_raster(lbm_ctx *c, int update);
 hipError_t launch_rigid_substeps(lbm_ctx *c);
+hipError_t launch_rigid_fused(lbm_ctx *c, double *rec); // Algorithm 1 + raster from the slots
+SlotParams slot_params(lbm_ctx *c, bool on);
 hipError_t launch_owner_to_int(lbm_ctx *c, int32_t *out);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 

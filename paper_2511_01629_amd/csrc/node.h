@@ -97,10 +97,12 @@ __device__ __forceinline__ T feq_q(int q, T p3, T cu, T u15)
 
 // Collision of one node, in place: f holds the pulled populations on entry
 // and f~ on return (right side of eq. 10 with F of eq. 14 and, on solid
-// nodes, S of eq. 17).  Writes the velocity of solid nodes for the sums.
+// nodes, S of eq. 17).  Writes the velocity of solid nodes for the sums and
+// returns the node's velocity u (eq. 15a).
 template <class L, class T>
 __device__ __forceinline__ void collide_node(T *f, uint16_t own, const T *__restrict__ acc_tab, const StepParams &sp,
-                                             int32_t *__restrict__ flags, double *__restrict__ usol, int idx, int N)
+                                             int32_t *__restrict__ flags, double *__restrict__ usol, int idx, int N,
+                                             T &uxo, T &uyo, T &uzo)
 {
     const bool solid = own != FLUID;
     T ax = 0, ay = 0, az = 0;
@@ -115,6 +117,9 @@ __device__ __forceinline__ void collide_node(T *f, uint16_t own, const T *__rest
     }
     T ux, uy, uz, p;
     moments<L, T>(f, ax, ay, az, ux, uy, uz, p);
+    uxo = ux;
+    uyo = uy;
+    uzo = uz;
     const T uu = ux * ux + uy * uy + uz * uz;
     if (!(uu < T(0.09))) flags[0] = 1; // |u| > 0.3 or not finite
     const T om = (T)sp.omega;

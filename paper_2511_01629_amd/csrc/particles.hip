@@ -487,6 +487,168 @@ __global__ __launch_bounds__(BS) void k_rigid_raster(uint16_t *__restrict__ owne
     raster_items<UNR>(owner, g, d, i, s_X, shape, Ri, bi, s_cs, s_sn, s_lo, s_hi, threadIdx.x, BS);
 }
 
+// ------------------------------------- fused-sums step: Algorithm 1 from slots
+// K = 1 with the momentum sums taken by the lattice kernel (SlotParams): one
+// workgroup per particle i
+//  1. sums its own slots of this step (fixed thread -> slot map, butterfly +
+//     LDS): N_i, U_i^n, omega_i^n, the record, U_bar_i, dtheta_i;
+//  2. for every other particle j close enough to interact at X^n or at the
+//     prediction (|X_i - X_j| <= R_i + R_j + delta + 0.6; the lattice sentinel
+//     bounds every node speed, hence |U_bar| <= 0.3), one lane sums j's slots
+//     in slot order to get U_j^n and U_bar_j = (U_j^n + U_j^{n-1})/2, then
+//     evaluates the pair forces at X^n and at the prediction;
+//  3. closes Algorithm 1 and rasterises the new indicator, as k_rigid_raster.
+// U^{n-1} of every particle is read from P.U, which nothing writes during the
+// launch: U^n goes to P.Unext, and the host swaps the two afterwards.
+template <int D, int W1>
+__device__ __forceinline__ void slot_velocity(const SlotParams &sl, int j, double *U)
+{
+    const double *sj = sl.slots + (size_t)j * sl.stride * W1;
+    double n = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int t = 0; t < sl.stride; ++t) {
+        const double *v = sj + (size_t)t * W1;
+        if (v[0] != sl.stamp) continue;
+        n += v[1];
+        s0 += v[2];
+        s1 += v[3];
+        if (D == 3) s2 += v[4];
+    }
+    U[0] = n > 0.0 ? s0 / n : 0.0;
+    U[1] = n > 0.0 ? s1 / n : 0.0;
+    U[2] = (D == 3 && n > 0.0) ? s2 / n : 0.0;
+}
+
+template <int D, int BS>
+__global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner, PartDev P, RigidParams rp, Geom g,
+                                                    SlotParams sl, double *__restrict__ rec, int32_t *__restrict__ flags)
+{
+    constexpr int NS = NSums<D>::value, W1 = NS + 1;
+    const int i = blockIdx.x, np = rp.np;
+    __shared__ double part[BS / WAVE][NS > 6 ? NS : 6];
+    __shared__ double s_X[3], s_cs, s_sn, s_Ub[3], s_dth;
+    __shared__ int s_lo[3], s_hi[3], s_N;
+    const double Ri = P.a[i], Ci = P.Cc[i], rho = P.rho_s[i], theta = P.theta[i], bi = P.b[i];
+    const int shape = P.shape[i];
+    double Xi[3];
+    for (int k = 0; k < 3; ++k) Xi[k] = P.X[3 * i + k];
+    PrevState ps = load_prev(P, i);
+    for (int k = 0; k < 3; ++k) ps.Uprev[k] = P.U[3 * i + k]; // U^{n-1}
+
+    // 1. own sums
+    double s[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) s[k] = 0.0;
+    const double *si = sl.slots + (size_t)i * sl.stride * W1;
+    for (int t = threadIdx.x; t < sl.stride; t += BS) {
+        const double *v = si + (size_t)t * W1;
+        if (v[0] != sl.stamp) continue;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) s[k] += v[1 + k];
+    }
+    block_sum<NS, BS>(s, reinterpret_cast<double(*)[NS]>(&part[0][0]));
+    if (threadIdx.x == 0) {
+        const int cnt = (int)s[0];
+        P.N[i] = cnt;
+        double U[3] = {0, 0, 0}, W[3] = {0, 0, 0};
+        if (cnt > 0) {
+            if constexpr (D == 2) {
+                U[0] = s[1] / s[0];
+                U[1] = s[2] / s[0];
+                W[2] = s[3] / s[4];
+            } else {
+                U[0] = s[1] / s[0];
+                U[1] = s[2] / s[0];
+                U[2] = s[3] / s[0];
+                const double L0 = s[4], L1 = s[5], L2 = s[6];
+                const double a = s[7], e = s[8], f = s[9], bxy = s[10], cxz = s[11], dyz = s[12];
+                const double A00 = e * f - dyz * dyz, A01 = cxz * dyz - bxy * f, A02 = bxy * dyz - cxz * e;
+                const double A11 = a * f - cxz * cxz, A12 = bxy * cxz - a * dyz, A22 = a * e - bxy * bxy;
+                const double det = a * A00 + bxy * A01 + cxz * A02;
+                W[0] = (A00 * L0 + A01 * L1 + A02 * L2) / det;
+                W[1] = (A01 * L0 + A11 * L1 + A12 * L2) / det;
+                W[2] = (A02 * L0 + A12 * L1 + A22 * L2) / det;
+            }
+        }
+        if (rec) {
+            double *r = rec + REC_STRIDE * i;
+            for (int k = 0; k < 3; ++k) {
+                r[k] = ps.X[k];
+                r[4 + k] = U[k];
+                r[7 + k] = W[k];
+                r[10 + k] = ps.A[k];
+                r[14 + k] = ps.Uprev[k];
+            }
+            r[3] = ps.theta;
+            r[13] = (double)cnt;
+        }
+        s_dth = 0.5 * (W[2] + ps.Wprev[2]);
+        P.dth[i] = s_dth;
+        for (int k = 0; k < 3; ++k) {
+            s_Ub[k] = 0.5 * (U[k] + ps.Uprev[k]);
+            P.Ub[3 * i + k] = s_Ub[k];
+            P.Unext[3 * i + k] = U[k];
+            P.W[3 * i + k] = W[k];
+            P.Wprev[3 * i + k] = W[k];
+        }
+        s_N = cnt;
+    }
+    __syncthreads();
+
+    // 2. pair forces with the particles in reach
+    double Yi[3];
+    for (int k = 0; k < 3; ++k) Yi[k] = Xi[k] + (k < D ? s_Ub[k] : 0.0);
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int per[3] = {g.per_x, g.per_y, g.per_z};
+    double F[6] = {0, 0, 0, 0, 0, 0};
+    for (int j = threadIdx.x; j < np; j += BS) {
+        if (j == i) continue;
+        double Xj[3], dv2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            Xj[k] = P.X[3 * j + k];
+            if (k >= D) continue;
+            double dk = Xi[k] - Xj[k];
+            if (per[k]) {
+                const double h = 0.5 * n[k];
+                if (dk > h) dk -= n[k];
+                else if (dk < -h) dk += n[k];
+            }
+            dv2 += dk * dk;
+        }
+        const double Rj = P.a[j], reach = Ri + Rj + rp.delta + 0.6;
+        if (dv2 > reach * reach) continue;
+        double Uj[3], Yj[3];
+        slot_velocity<D, W1>(sl, j, Uj);
+        for (int k = 0; k < 3; ++k) Yj[k] = Xj[k] + (k < D ? 0.5 * (Uj[k] + P.U[3 * j + k]) : 0.0);
+        pair_force(Xi, Xj, Ri, Rj, Ci, rp, g, F);
+        pair_force(Yi, Yj, Ri, Rj, Ci, rp, g, F + 3);
+    }
+    block_sum<6, BS>(F, reinterpret_cast<double(*)[6]>(&part[0][0]));
+
+    // 3. close Algorithm 1, then the new indicator
+    if (threadIdx.x == 0) {
+        wall_force(Xi, Ri, Ci, rp, g, F);
+        wall_force(Yi, Ri, Ci, rp, g, F + 3);
+        const int cnt = s_N;
+        const double M = rho * (double)cnt;
+        const double c = M > 0.0 ? 1.0 / (2.0 * M) : 0.0;
+        double Y[3], Dc[3];
+        for (int k = 0; k < 3; ++k) {
+            Dc[k] = k < D ? c * (F[k] + F[3 + k]) / 2.0 : 0.0;
+            Y[k] = Yi[k] + Dc[k];
+        }
+        const double th = close_rigid(P, rp, g, i, Y, Dc, cnt, rho, theta, s_dth, flags, s_X);
+        s_cs = shape == LBM_ELLIPSE ? cos(th) : 1.0;
+        s_sn = shape == LBM_ELLIPSE ? sin(th) : 0.0;
+        centre_box(s_X, Ri, g, D, s_lo, s_hi);
+        for (int k = 0; k < 3; ++k) {
+            P.lo[3 * i + k] = s_lo[k];
+            P.hi[3 * i + k] = s_hi[k];
+        }
+    }
+    __syncthreads();
+    raster_items<UNR>(owner, g, D, i, s_X, shape, Ri, bi, s_cs, s_sn, s_lo, s_hi, threadIdx.x, BS);
+}
+
 // Algorithm 1 with K > 1 sub-steps: every sub-step needs all
 // predicted positions, so one workgroup of 1024 threads sweeps the particles
 // with a barrier between sub-steps (Jacobi).  Writes P.Xn, A, theta and the
@@ -577,18 +739,27 @@ hipError_t launch_raster_clear(lbm_ctx *c)
 // one batch of loads; 3D boxes are ~10x larger.
 constexpr int SUMS_BS2 = 256, SUMS_BS3 = 512, RIGID_BS = 256;
 
-hipError_t launch_reduce(lbm_ctx *c, int step, double *rec)
+// step = 1: the sums of a step (clear the indicator, prepare Algorithm 1);
+// step = 0: U and omega measured on the current state, into P.U and P.W
+// (lbm_set_particles: U^0) or, with scratch = 1, into P.Y and P.Ys, leaving
+// the state untouched (lbm_get_particles).
+hipError_t launch_reduce(lbm_ctx *c, int step, double *rec, int scratch)
 {
     if (c->np == 0) return hipSuccess;
     const uint16_t *oin = c->owner;
     uint16_t *oclr = c->owner_next ? nullptr : c->owner;
     const dim3 grid(c->np);
     const double *us = c->usol;
+    PartDev P = c->P;
+    if (!step && scratch) {
+        P.U = c->P.Y;
+        P.W = c->P.Ys;
+    }
     if (c->d == 2)
-        return step ? launch(c, k_sums<2, true, SUMS_BS2>, grid, dim3(SUMS_BS2), oin, oclr, us, c->P, c->geo, rec)
-                    : launch(c, k_sums<2, false, SUMS_BS2>, grid, dim3(SUMS_BS2), oin, oclr, us, c->P, c->geo, rec);
-    return step ? launch(c, k_sums<3, true, SUMS_BS3>, grid, dim3(SUMS_BS3), oin, oclr, us, c->P, c->geo, rec)
-                : launch(c, k_sums<3, false, SUMS_BS3>, grid, dim3(SUMS_BS3), oin, oclr, us, c->P, c->geo, rec);
+        return step ? launch(c, k_sums<2, true, SUMS_BS2>, grid, dim3(SUMS_BS2), oin, oclr, us, P, c->geo, rec)
+                    : launch(c, k_sums<2, false, SUMS_BS2>, grid, dim3(SUMS_BS2), oin, oclr, us, P, c->geo, rec);
+    return step ? launch(c, k_sums<3, true, SUMS_BS3>, grid, dim3(SUMS_BS3), oin, oclr, us, P, c->geo, rec)
+                : launch(c, k_sums<3, false, SUMS_BS3>, grid, dim3(SUMS_BS3), oin, oclr, us, P, c->geo, rec);
 }
 
 hipError_t launch_rigid_raster(lbm_ctx *c, int update)
@@ -606,6 +777,37 @@ hipError_t launch_rigid_substeps(lbm_ctx *c)
     RigidParams rp = c->rp;
     rp.np = c->np;
     return launch(c, k_rigid_substeps, dim3(1), dim3(1024), c->P, rp, c->geo, c->flags);
+}
+
+SlotParams slot_params(lbm_ctx *c, bool on)
+{
+    SlotParams sl{};
+    if (!on || !c->slots || c->np == 0) return sl; // slots == NULL: no fused sums
+    sl.slots = c->slots;
+    sl.X = c->P.X;
+    sl.lo = c->P.lo;
+    sl.hi = c->P.hi;
+    sl.stride = c->slot_stride;
+    sl.kw = c->slot_kw;
+    sl.wn = (c->geo.nx + WAVE - 1) / WAVE;
+    sl.stamp = (double)c->epoch;
+    sl.clear = c->owner_next ? nullptr : c->owner;
+    sl.flags = c->flags;
+    return sl;
+}
+
+hipError_t launch_rigid_fused(lbm_ctx *c, double *rec)
+{
+    if (c->np == 0) return hipSuccess;
+    RigidParams rp = c->rp;
+    rp.np = c->np;
+    const SlotParams sl = slot_params(c, true);
+    if (!sl.slots) return hipErrorInvalidValue;
+    uint16_t *out = c->owner_next ? c->owner_next : c->owner;
+    if (c->d == 2)
+        return launch(c, k_rigid_fused<2, RIGID_BS>, dim3(c->np), dim3(RIGID_BS), out, c->P, rp, c->geo, sl, rec,
+                      c->flags);
+    return launch(c, k_rigid_fused<3, RIGID_BS>, dim3(c->np), dim3(RIGID_BS), out, c->P, rp, c->geo, sl, rec, c->flags);
 }
 
 hipError_t launch_owner_to_int(lbm_ctx *c, int32_t *out)

@@ -127,6 +127,82 @@ __device__ __forceinline__ int walk_node(const Box &b, const CellWalk &w, const 
     return wrap(xu, g.nx) + g.nx * (wrap(yu, g.ny) + g.ny * wrap(zu, g.nz));
 }
 
+// Keyed wavefront sums of the momentum moments of one step's solid nodes
+// into the slots (the fused-sums step).  Called by every lane of the
+// wavefront with uniform control flow; `active` lanes hold a solid node
+// (x, y, z) of particle `own` with velocity u.  The key of a node is its
+// particle and its slot: the row of the particle's scan box it lies in and
+// the wavefront of the lattice row, counted from the box's first one, so
+// every slot has exactly one writing wavefront.  Each distinct key in the
+// wavefront is summed with the butterfly (fixed order) and written by its
+// lowest lane, with the stamp of the step.  Moments as in the momentum sums:
+// 2D [N, u_x, u_y, r x u, |r|^2], 3D [N, u (3), r x u (3), inertia xx yy zz xy xz yz].
+template <int D>
+__device__ void slot_sums(bool active, uint16_t own, int x, int y, int z, double ux, double uy, double uz,
+                          const SlotParams &sp, const Geom &g)
+{
+    constexpr int NS = D == 2 ? 5 : 13;
+    unsigned long long pending = __ballot(active);
+    if (pending == 0ull) return;
+    const int lane = threadIdx.x & (WAVE - 1);
+    uint32_t key = 0xFFFFFFFFu;
+    double rx = 0.0, ry = 0.0, rz = 0.0;
+    if (active) {
+        const int i = own;
+        const int lo0 = sp.lo[3 * i], lo1 = sp.lo[3 * i + 1], lo2 = sp.lo[3 * i + 2];
+        const int hi0 = sp.hi[3 * i], hi1 = sp.hi[3 * i + 1];
+        int xu = x, yu = y, zu = z; // unwrapped into the box (it spans less than a period)
+        if (g.per_x) xu = xu < lo0 ? xu + g.nx : (xu > hi0 ? xu - g.nx : xu);
+        if (g.per_y) yu = yu < lo1 ? yu + g.ny : (yu > hi1 ? yu - g.ny : yu);
+        if (D == 3 && g.per_z) {
+            const int hi2 = sp.hi[3 * i + 2];
+            zu = zu < lo2 ? zu + g.nz : (zu > hi2 ? zu - g.nz : zu);
+        }
+        const int row = (yu - lo1) + (hi1 - lo1 + 1) * (zu - lo2);
+        const int j = ((x / WAVE) - (wrap(lo0, g.nx) / WAVE) + sp.wn) % sp.wn;
+        if (row >= 0 && j < sp.kw && row * sp.kw + j < sp.stride) key = ((uint32_t)i << 16) | (uint32_t)(row * sp.kw + j);
+        else sp.flags[1] = 1;
+        rx = (double)xu - sp.X[3 * i];
+        ry = (double)yu - sp.X[3 * i + 1];
+        rz = D == 3 ? (double)zu - sp.X[3 * i + 2] : 0.0;
+    }
+    pending = __ballot(key != 0xFFFFFFFFu);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const uint32_t k = (uint32_t)__shfl((int)key, leader);
+        const bool mine = key == k;
+        double v[NS];
+        v[0] = mine ? 1.0 : 0.0;
+        v[1] = mine ? ux : 0.0;
+        v[2] = mine ? uy : 0.0;
+        if constexpr (D == 2) {
+            v[3] = mine ? rx * uy - ry * ux : 0.0;
+            v[4] = mine ? rx * rx + ry * ry : 0.0;
+        } else {
+            const double rr = rx * rx + ry * ry + rz * rz;
+            v[3] = mine ? uz : 0.0;
+            v[4] = mine ? ry * uz - rz * uy : 0.0;
+            v[5] = mine ? rz * ux - rx * uz : 0.0;
+            v[6] = mine ? rx * uy - ry * ux : 0.0;
+            v[7] = mine ? rr - rx * rx : 0.0;
+            v[8] = mine ? rr - ry * ry : 0.0;
+            v[9] = mine ? rr - rz * rz : 0.0;
+            v[10] = mine ? -(rx * ry) : 0.0;
+            v[11] = mine ? -(rx * rz) : 0.0;
+            v[12] = mine ? -(ry * rz) : 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < NS; ++m) v[m] = wave_sum(v[m]);
+        if (lane == leader) {
+            double *out = sp.slots + ((size_t)(k >> 16) * sp.stride + (k & 0xFFFFu)) * (NS + 1);
+            out[0] = sp.stamp;
+#pragma unroll
+            for (int m = 0; m < NS; ++m) out[1 + m] = v[m];
+        }
+        pending &= ~__ballot(mine);
+    }
+}
+
 // Cell c of box b: unwrapped coordinates and the (wrapped) node index.
 __device__ __forceinline__ void cell_at(const Box &b, int c, const Geom &g, int &xu, int &yu, int &zu, int &node)
 {

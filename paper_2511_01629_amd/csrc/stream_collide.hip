@@ -14,6 +14,7 @@
 // their velocity (FP64) for the per-particle momentum sums.
 #include "dispatch.h"
 #include "node.h"
+#include "reduce.h"
 
 namespace lbm {
 
@@ -26,16 +27,20 @@ namespace lbm {
 // lane (element-aligned 2-wide loads, or aligned loads with a DPP lane shift
 // for the x-shifted directions), two strided nodes per lane, and an XCD-aware
 // remap of the workgroup order.
+//
+// With slots (the fused-sums step), the solid nodes also add their momentum
+// moments to their particle's slots (keyed wavefront sums) and, on in-place
+// steps, reset their owner entry, which no other lane reads.
 template <class L, class S, class T>
 __global__ __launch_bounds__(256) void k_stream_collide(const typename S::raw *__restrict__ fin,
-                                                         typename S::raw *__restrict__ fout,
-                                                         const uint16_t *__restrict__ owner,
+                                                         typename S::raw *__restrict__ fout, const uint16_t *owner,
                                                          const T *__restrict__ acc_tab, double *__restrict__ usol,
-                                                         int32_t *__restrict__ flags, Geom g, StepParams sp, int gx)
+                                                         int32_t *__restrict__ flags, Geom g, StepParams sp, int gx,
+                                                         SlotParams sl)
 {
     const int row = blockIdx.x / gx, bx = blockIdx.x - row * gx; // uniform
     const int x = bx * 256 + (int)threadIdx.x;
-    if (x >= g.nx) return;
+    const bool valid = x < g.nx;
     int y, z;
     if (L::D == 2) {
         y = row;
@@ -46,11 +51,21 @@ __global__ __launch_bounds__(256) void k_stream_collide(const typename S::raw *_
     }
     const int N = (int)g.N;
     const int idx = row * g.nx + x;
-    T f[L::Q];
-    pull<L, S, T>(fin, idx, x, y, z, g, N, f);
-    collide_node<L, T>(f, owner[idx], acc_tab, sp, flags, usol, idx, N);
+    uint16_t own = FLUID;
+    T ux = 0, uy = 0, uz = 0;
+    if (valid) {
+        T f[L::Q];
+        pull<L, S, T>(fin, idx, x, y, z, g, N, f);
+        own = owner[idx];
+        collide_node<L, T>(f, own, acc_tab, sp, flags, usol, idx, N, ux, uy, uz);
 #pragma unroll
-    for (int q = 0; q < L::Q; ++q) st<S, T>(fout + q * N + idx, f[q]);
+        for (int q = 0; q < L::Q; ++q) st<S, T>(fout + q * N + idx, f[q]);
+    }
+    if (sl.slots) { // uniform
+        const bool solid = valid && own != FLUID;
+        slot_sums<L::D>(solid, own, x, y, z, (double)ux, (double)uy, (double)uz, sl, g);
+        if (solid && sl.clear) sl.clear[idx] = FLUID;
+    }
 }
 
 // D3Q19 variant with the source rows staged through LDS, so that every
@@ -78,9 +93,9 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 template <class L, class S, class T, int TPB>
 __global__ __launch_bounds__(TPB) void k_stream_collide_lds(const typename S::raw *__restrict__ fin,
                                                              typename S::raw *__restrict__ fout,
-                                                             const uint16_t *__restrict__ owner,
-                                                             const T *__restrict__ acc_tab, double *__restrict__ usol,
-                                                             int32_t *__restrict__ flags, Geom g, StepParams sp, int gx)
+                                                             const uint16_t *owner, const T *__restrict__ acc_tab,
+                                                             double *__restrict__ usol, int32_t *__restrict__ flags,
+                                                             Geom g, StepParams sp, int gx, SlotParams sl)
 {
     using raw = typename S::raw;
     constexpr int Q = L::Q, NPL = 16 / (int)sizeof(raw), W = NPL * TPB;
@@ -162,17 +177,27 @@ __global__ __launch_bounds__(TPB) void k_stream_collide_lds(const typename S::ra
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
         const int i = tid + k * TPB;
-        if (i >= Wv) continue;
-        T f[Q];
+        const bool valid = i < Wv; // consecutive lanes hold consecutive nodes
+        uint16_t own = FLUID;
+        T ux = 0, uy = 0, uz = 0;
+        if (valid) {
+            T f[Q];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            int j = i - sh[q];
-            j = j < 0 ? W : (j >= Wv ? W + 1 : j);
-            f[q] = from_raw<S, T>(buf[q * RL + j]);
+            for (int q = 0; q < Q; ++q) {
+                int j = i - sh[q];
+                j = j < 0 ? W : (j >= Wv ? W + 1 : j);
+                f[q] = from_raw<S, T>(buf[q * RL + j]);
+            }
+            own = own_s[i];
+            collide_node<L, T>(f, own, acc_tab, sp, flags, usol, rbase + x0 + i, N, ux, uy, uz);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) res[k][q] = to_raw<S, T>(f[q]);
         }
-        collide_node<L, T>(f, own_s[i], acc_tab, sp, flags, usol, rbase + x0 + i, N);
-#pragma unroll
-        for (int q = 0; q < Q; ++q) res[k][q] = to_raw<S, T>(f[q]);
+        if (sl.slots) { // uniform
+            const bool solid = valid && own != FLUID;
+            slot_sums<L::D>(solid, own, x0 + i, y, z, (double)ux, (double)uy, (double)uz, sl, g);
+            if (solid && sl.clear) sl.clear[rbase + x0 + i] = FLUID;
+        }
     }
     __syncthreads();
 
@@ -313,6 +338,7 @@ static inline unsigned blocks_for(int64_t N) { return (unsigned)((N + 255) / 256
 
 hipError_t launch_stream_collide(lbm_ctx *c, const void *fin, void *fout)
 {
+    const SlotParams sl = slot_params(c, c->fused != 0);
     const int gx = (c->geo.nx + 255) / 256;
     const unsigned blocks = (unsigned)gx * (unsigned)(c->geo.ny * c->geo.nz);
     return dispatch(c, [&](auto L, auto S, auto T) {
@@ -332,14 +358,15 @@ hipError_t launch_stream_collide(lbm_ctx *c, const void *fin, void *fout)
                     const unsigned bs = (unsigned)gxs * (unsigned)(c->geo.ny * c->geo.nz);
                     return launch(c, k_stream_collide_lds<Lt, St, Tt, TPB>, dim3(bs), dim3(TPB),
                                   (const typename St::raw *)fin, (typename St::raw *)fout, (const uint16_t *)c->owner,
-                                  acc, c->usol, c->flags, c->geo, c->sp, gxs);
+                                  acc, c->usol, c->flags, c->geo, c->sp, gxs, sl);
                 };
                 if (c->geo.nx >= 128 * NPL) return staged(std::integral_constant<int, 128>{});
                 return staged(std::integral_constant<int, 64>{});
             }
         }
         return launch(c, k_stream_collide<Lt, St, Tt>, dim3(blocks), dim3(256), (const typename St::raw *)fin,
-                      (typename St::raw *)fout, (const uint16_t *)c->owner, acc, c->usol, c->flags, c->geo, c->sp, gx);
+                      (typename St::raw *)fout, (const uint16_t *)c->owner, acc, c->usol, c->flags, c->geo, c->sp, gx,
+                      sl);
     });
 }
 
