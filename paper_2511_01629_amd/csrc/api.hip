@@ -329,7 +329,7 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
     c->owner_next = nullptr;
     c->slots = nullptr;
     c->slots_bytes = 0;
-    c->slot_stride = c->slot_kw = c->fused = 0;
+    c->slot_stride = c->slot_mx = c->slot_my = c->slot_mz = c->slot_sy = c->slot_sz = c->fused = 0;
     c->epoch = 0;
     c->prof = 0;
     c->tev[0] = c->tev[1] = nullptr;
@@ -450,18 +450,38 @@ int lbm_set_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
     HIPCHK(c, hipMemcpyAsync(c->P.shape, shape.data(), sizeof(int32_t) * cap, hipMemcpyHostToDevice, c->stream));
     c->np = n;
     c->host_parts.assign(p, p + n);
-    // fused-sums step (K = 1): slots of (scan-box row) x (wavefronts a box row
-    // can touch) per particle; a box spans at most ceil(2a) + 7 nodes per axis
+    // fused-sums step (K = 1): per-particle slot tables keyed by the wrapped
+    // row and the wavefront index (slot_of).  A scan box spans at most
+    // ceil(2a) + 7 nodes per axis; the key sizes are powers of two at least
+    // that many rows and wavefronts, and on a periodic axis must divide the
+    // period (or cover it), so that no two rows or wavefronts of a box share a
+    // slot; on a periodic x axis a box must also stay 63 nodes short of the
+    // period, so that a wavefront never holds nodes of two images of one box.
+    // Otherwise the momentum sums run as a kernel of their own.
     c->fused = 0;
     if (c->rp.K == 1 && n > 0) {
+        const Geom &g = c->geo;
         int ext = 0;
         for (int i = 0; i < n; ++i) ext = std::max(ext, (int)ceil(2.0 * p[i].a) + 7);
-        const int wn = (c->geo.nx + 63) / 64;
-        const int kw = std::min(wn, (ext + 63) / 64 + 3);
-        const int64_t rows = d == 2 ? ext : (int64_t)ext * ext;
-        const int64_t stride = rows * kw;
-        if (stride < 65536) {
-            const size_t need = (size_t)cap * stride * ((d == 2 ? 5 : 13) + 1) * sizeof(double);
+        auto pow2 = [](int v) {
+            int q = 1;
+            while (q < v) q <<= 1;
+            return q;
+        };
+        auto lg = [](int v) {
+            int k = 0;
+            while ((1 << k) < v) ++k;
+            return k;
+        };
+        const int wn = (g.nx + 63) / 64;
+        const int kwn = std::min(wn, (ext + 62) / 64 + 1 + (g.per_x && g.nx % 64 ? 1 : 0));
+        const int Mx = pow2(kwn), My = pow2(ext), Mz = d == 3 ? pow2(ext) : 1;
+        auto axis_ok = [&](int per, int len, int M) { return !per || (ext <= len && (len % M == 0 || M >= len)); };
+        bool ok = axis_ok(g.per_y, g.ny, My) && (d == 2 || axis_ok(g.per_z, g.nz, Mz));
+        ok = ok && (!g.per_x || (ext + 63 <= g.nx && (wn % Mx == 0 || Mx >= wn)));
+        const int64_t stride = (int64_t)Mx * My * Mz;
+        const size_t need = (size_t)cap * (size_t)stride * ((d == 2 ? 3 : 5) + 2) * sizeof(double);
+        if (ok && stride <= 65536 && need <= ((size_t)1 << 30)) {
             if (need > c->slots_bytes) {
                 if (c->slots) HIPCHK(c, hipFree(c->slots));
                 c->slots = nullptr;
@@ -472,7 +492,11 @@ int lbm_set_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
             // NaN stamps: no slot counts until a step writes it
             HIPCHK(c, hipMemsetAsync(c->slots, 0xFF, c->slots_bytes, c->stream));
             c->slot_stride = (int)stride;
-            c->slot_kw = kw;
+            c->slot_mx = Mx - 1;
+            c->slot_my = My - 1;
+            c->slot_mz = Mz - 1;
+            c->slot_sy = lg(Mx);
+            c->slot_sz = lg(Mx) + lg(My);
             c->fused = 1;
         }
     }

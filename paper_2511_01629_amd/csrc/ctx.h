@@ -33,19 +33,17 @@ struct PartDev {
 };
 
 // Per-particle partial momentum sums written by the lattice kernel (the
-// fused-sums step, K = 1): one slot per (particle, scan-box row, wavefront of
-// that row), each [stamp, sums...]; a slot counts for the step whose stamp it
-// carries, so nothing is ever cleared.  Slot s of particle i starts at
-// slots + (i * stride + s) * width.
+// fused-sums step, K = 1): one slot per (particle, lattice row key, wavefront
+// key), each [stamp, lane mask, sums...]; a slot counts for the step whose
+// stamp it carries, so nothing is ever cleared.  Slot s of particle i starts
+// at slots + (i * stride + s) * width.
 struct SlotParams {
-    double *slots;
-    const double *X;        // particle centres of the step
-    const int32_t *lo, *hi; // the step's scan boxes
-    int stride, kw, wn;     // slots per particle, wavefront slots per row, wavefronts per lattice row
-    double stamp;
-    uint16_t *clear;        // the owner map to reset to FLUID as it is read (in-place steps), or NULL
-    int32_t *flags;         // [1] set if a node falls outside its particle's slots (cannot happen
-                            // for boxes built by the raster; a guard, not a path)
+    double *slots;      // [np][stride][NV + 2] records: stamp, lane mask, sums
+    int stride;         // slots per particle
+    int mx, my, mz;     // wavefront, y and z keys: masks of powers of two
+    int sy, sz;         // shifts of the y and z keys
+    double stamp;       // this step's stamp
+    uint16_t *clear;    // the owner map to reset to FLUID as it is read (in-place steps), or NULL
 };
 
 // Everything a kernel needs to know about the lattice.
@@ -102,7 +100,7 @@ struct lbm_ctx {
     uint16_t *owner;      // indicator the next step reads
     uint16_t *owner_next; // NULL: steps update `owner` in place; else the (all FLUID)
                           // buffer the next step's indicator goes to (differentiated runs)
-    double *usol;    // [d][N] velocity on solid nodes (written by the fused kernel)
+    double *usol;    // [d][N] velocity on solid nodes (written by the lattice kernel unless it takes the sums)
     double *staging; // [4][N] doubles for field/population transfers
     int32_t *flags;  // [0] unstable, [1] domain
     lbm::PartDev P;
@@ -110,7 +108,7 @@ struct lbm_ctx {
     // fused-sums step (K = 1): slot buffer (library-owned), its layout, the stamp counter
     double *slots;
     size_t slots_bytes;
-    int slot_stride, slot_kw, fused;
+    int slot_stride, slot_mx, slot_my, slot_mz, slot_sy, slot_sz, fused;
     int64_t epoch;
     int64_t step;
     double *rec_dev;

@@ -97,8 +97,8 @@ __device__ __forceinline__ T feq_q(int q, T p3, T cu, T u15)
 
 // Collision of one node, in place: f holds the pulled populations on entry
 // and f~ on return (right side of eq. 10 with F of eq. 14 and, on solid
-// nodes, S of eq. 17).  Writes the velocity of solid nodes for the sums and
-// returns the node's velocity u (eq. 15a).
+// nodes, S of eq. 17).  Writes the velocity of solid nodes for the sums
+// (unless usol is NULL) and returns the node's velocity u (eq. 15a).
 template <class L, class T>
 __device__ __forceinline__ void collide_node(T *f, uint16_t own, const T *__restrict__ acc_tab, const StepParams &sp,
                                              int32_t *__restrict__ flags, double *__restrict__ usol, int idx, int N,
@@ -169,7 +169,7 @@ __device__ __forceinline__ void collide_node(T *f, uint16_t own, const T *__rest
         const T F = gpre * T(L::w[q]) * (T(3) * (ca - ua) + T(9) * cu * ca);
         f[q] = f[q] - om * fneq[q] + F + Sq;
     }
-    if (solid) {
+    if (solid && usol) {
         usol[idx] = (double)ux;
         usol[N + idx] = (double)uy;
         if (L::D == 3) usol[2 * N + idx] = (double)uz;

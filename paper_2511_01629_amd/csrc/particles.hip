@@ -488,45 +488,72 @@ __global__ __launch_bounds__(BS) void k_rigid_raster(uint16_t *__restrict__ owne
 }
 
 // ------------------------------------- fused-sums step: Algorithm 1 from slots
-// K = 1 with the momentum sums taken by the lattice kernel (SlotParams): one
+// K = 1 with the momentum sums taken by the lattice kernel (slot_sums): one
 // workgroup per particle i
-//  1. sums its own slots of this step (fixed thread -> slot map, butterfly +
-//     LDS): N_i, U_i^n, omega_i^n, the record, U_bar_i, dtheta_i;
-//  2. for every other particle j close enough to interact at X^n or at the
-//     prediction (|X_i - X_j| <= R_i + R_j + delta + 0.6; the lattice sentinel
-//     bounds every node speed, hence |U_bar| <= 0.3), one lane sums j's slots
-//     in slot order to get U_j^n and U_bar_j = (U_j^n + U_j^{n-1})/2, then
-//     evaluates the pair forces at X^n and at the prediction;
+//  1. sums its own slots of this step: thread t takes the scan-box rows t,
+//     t + BS, ... and, along each, the wavefronts the box touches; a record
+//     with this step's stamp is shifted to moments about X_i^n (its row and
+//     first node are known), and the workgroup sum (fixed order) gives N_i,
+//     U_i^n, omega_i^n, the record, U_bar_i and dtheta_i;
+//  2. lists, in index order, the particles j close enough to interact at X^n
+//     or at the prediction (|X_i - X_j| <= R_i + R_j + delta + 0.6: the
+//     lattice sentinel bounds every node speed by 0.3, hence |U_bar| <= 0.3);
+//     for each, the workgroup sums the count and velocity of all of j's
+//     records with this step's stamp (j's box is not needed, which is as well:
+//     j's own workgroup is replacing it) to get U_j^n and
+//     U_bar_j = (U_j^n + U_j^{n-1})/2, and thread 0 adds the pair forces at X^n
+//     and at the prediction;
 //  3. closes Algorithm 1 and rasterises the new indicator, as k_rigid_raster.
 // U^{n-1} of every particle is read from P.U, which nothing writes during the
 // launch: U^n goes to P.Unext, and the host swaps the two afterwards.
-template <int D, int W1>
-__device__ __forceinline__ void slot_velocity(const SlotParams &sl, int j, double *U)
+
+// Adds the moments about the particle centre of one slot record (see
+// slot_sums) whose first node sits at (X_0 + dx, X_1 + dy, X_2 + dz): 2D
+// [N, U (2), L_z, sum |r|^2], 3D [N, U (3), L (3), inertia xx yy zz xy xz yz],
+// the moments of the momentum-sum kernel.  A node at lane offset s of the
+// slot has r = (s + dx, dy, dz).
+template <int D>
+__device__ __forceinline__ void add_slot(const double *v, double dx, double dy, double dz, double *c)
 {
-    const double *sj = sl.slots + (size_t)j * sl.stride * W1;
-    double n = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int t = 0; t < sl.stride; ++t) {
-        const double *v = sj + (size_t)t * W1;
-        if (v[0] != sl.stamp) continue;
-        n += v[1];
-        s0 += v[2];
-        s1 += v[3];
-        if (D == 3) s2 += v[4];
+    double n, s1, s2;
+    mask_moments((unsigned long long)__double_as_longlong(v[1]), n, s1, s2);
+    const double sxx = s2 + 2.0 * dx * s1 + n * dx * dx; // sum of r_x^2
+    if constexpr (D == 2) {
+        const double vx = v[2], vy = v[3], vs = v[4];
+        c[0] += n;
+        c[1] += vx;
+        c[2] += vy;
+        c[3] += vs + dx * vy - dy * vx;
+        c[4] += sxx + n * dy * dy;
+    } else {
+        const double vx = v[2], vy = v[3], vz = v[4], vsy = v[5], vsz = v[6];
+        const double syy = n * dy * dy, szz = n * dz * dz, sx = s1 + n * dx; // sum of r_x
+        c[0] += n;
+        c[1] += vx;
+        c[2] += vy;
+        c[3] += vz;
+        c[4] += dy * vz - dz * vy;
+        c[5] += dz * vx - (vsz + dx * vz);
+        c[6] += (vsy + dx * vy) - dy * vx;
+        c[7] += syy + szz;
+        c[8] += sxx + szz;
+        c[9] += sxx + syy;
+        c[10] -= dy * sx;
+        c[11] -= dz * sx;
+        c[12] -= n * dy * dz;
     }
-    U[0] = n > 0.0 ? s0 / n : 0.0;
-    U[1] = n > 0.0 ? s1 / n : 0.0;
-    U[2] = (D == 3 && n > 0.0) ? s2 / n : 0.0;
 }
 
 template <int D, int BS>
 __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner, PartDev P, RigidParams rp, Geom g,
                                                     SlotParams sl, double *__restrict__ rec, int32_t *__restrict__ flags)
 {
-    constexpr int NS = NSums<D>::value, W1 = NS + 1;
+    constexpr int NS = NSums<D>::value, W1 = (D == 2 ? 3 : 5) + 2;
     const int i = blockIdx.x, np = rp.np;
-    __shared__ double part[BS / WAVE][NS > 6 ? NS : 6];
+    __shared__ double part[BS / WAVE][NS];
     __shared__ double s_X[3], s_cs, s_sn, s_Ub[3], s_dth;
     __shared__ int s_lo[3], s_hi[3], s_N;
+    __shared__ int s_list[BS], s_cnt[BS / WAVE];
     const double Ri = P.a[i], Ci = P.Cc[i], rho = P.rho_s[i], theta = P.theta[i], bi = P.b[i];
     const int shape = P.shape[i];
     double Xi[3];
@@ -534,18 +561,28 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
     PrevState ps = load_prev(P, i);
     for (int k = 0; k < 3; ++k) ps.Uprev[k] = P.U[3 * i + k]; // U^{n-1}
 
-    // 1. own sums
+    // 1. own sums over the scan box the indicator was rasterised with
     double s[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) s[k] = 0.0;
-    const double *si = sl.slots + (size_t)i * sl.stride * W1;
-    for (int t = threadIdx.x; t < sl.stride; t += BS) {
-        const double *v = si + (size_t)t * W1;
-        if (v[0] != sl.stamp) continue;
-#pragma unroll
-        for (int k = 0; k < NS; ++k) s[k] += v[1 + k];
+    {
+        const double *si = sl.slots + (size_t)i * sl.stride * W1;
+        const int lo0 = P.lo[3 * i], hi0 = P.hi[3 * i], lo1 = P.lo[3 * i + 1], lo2 = P.lo[3 * i + 2];
+        const int e1 = P.hi[3 * i + 1] - lo1 + 1, e2 = P.hi[3 * i + 2] - lo2 + 1;
+        const int rows = e1 > 0 && e2 > 0 ? e1 * e2 : 0;
+        for (int r = threadIdx.x; r < rows; r += BS) {
+            const int yu = lo1 + r % e1, zu = lo2 + r / e1;
+            const int rkey = ((wrap(zu, g.nz) & sl.mz) << sl.sz) | ((wrap(yu, g.ny) & sl.my) << sl.sy);
+            const double dy = (double)yu - Xi[1], dz = D == 3 ? (double)zu - Xi[2] : 0.0;
+            for (int xu = lo0; xu <= hi0;) {
+                const int wx = wrap(xu, g.nx), w = wx >> 6, base = xu - (wx & (WAVE - 1));
+                xu = base + min(WAVE, g.nx - (w << 6));
+                const double *v = si + (size_t)(rkey | (w & sl.mx)) * W1;
+                if (v[0] == sl.stamp) add_slot<D>(v, (double)base - Xi[0], dy, dz, s);
+            }
+        }
     }
-    block_sum<NS, BS>(s, reinterpret_cast<double(*)[NS]>(&part[0][0]));
+    block_sum<NS, BS>(s, part);
     if (threadIdx.x == 0) {
         const int cnt = (int)s[0];
         P.N[i] = cnt;
@@ -594,35 +631,68 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
     }
     __syncthreads();
 
-    // 2. pair forces with the particles in reach
+    // 2. pair forces with the particles in reach (thread 0 accumulates, in
+    // index order)
     double Yi[3];
     for (int k = 0; k < 3; ++k) Yi[k] = Xi[k] + (k < D ? s_Ub[k] : 0.0);
     const int n[3] = {g.nx, g.ny, g.nz};
     const int per[3] = {g.per_x, g.per_y, g.per_z};
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     double F[6] = {0, 0, 0, 0, 0, 0};
-    for (int j = threadIdx.x; j < np; j += BS) {
-        if (j == i) continue;
-        double Xj[3], dv2 = 0.0;
-        for (int k = 0; k < 3; ++k) {
-            Xj[k] = P.X[3 * j + k];
-            if (k >= D) continue;
-            double dk = Xi[k] - Xj[k];
-            if (per[k]) {
-                const double h = 0.5 * n[k];
-                if (dk > h) dk -= n[k];
-                else if (dk < -h) dk += n[k];
+    for (int j0 = 0; j0 < np; j0 += BS) { // uniform
+        const int j = j0 + (int)threadIdx.x;
+        bool in = false;
+        if (j < np && j != i) {
+            double dv2 = 0.0;
+            for (int k = 0; k < D; ++k) {
+                double dk = Xi[k] - P.X[3 * j + k];
+                if (per[k]) {
+                    const double h = 0.5 * n[k];
+                    if (dk > h) dk -= n[k];
+                    else if (dk < -h) dk += n[k];
+                }
+                dv2 += dk * dk;
             }
-            dv2 += dk * dk;
+            const double reach = Ri + P.a[j] + rp.delta + 0.6;
+            in = dv2 <= reach * reach;
         }
-        const double Rj = P.a[j], reach = Ri + Rj + rp.delta + 0.6;
-        if (dv2 > reach * reach) continue;
-        double Uj[3], Yj[3];
-        slot_velocity<D, W1>(sl, j, Uj);
-        for (int k = 0; k < 3; ++k) Yj[k] = Xj[k] + (k < D ? 0.5 * (Uj[k] + P.U[3 * j + k]) : 0.0);
-        pair_force(Xi, Xj, Ri, Rj, Ci, rp, g, F);
-        pair_force(Yi, Yj, Ri, Rj, Ci, rp, g, F + 3);
+        const unsigned long long m = __ballot(in);
+        if (lane == 0) s_cnt[wv] = __popcll(m);
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int q = 0; q < BS / WAVE; ++q) {
+            off += q < wv ? s_cnt[q] : 0;
+            tot += s_cnt[q];
+        }
+        if (in) s_list[off + __popcll(m & ((1ull << lane) - 1ull))] = j;
+        __syncthreads();
+        for (int t = 0; t < tot; ++t) { // uniform
+            const int jj = s_list[t];
+            const double *sj = sl.slots + (size_t)jj * sl.stride * W1;
+            double u[4] = {0, 0, 0, 0};
+            for (int q = threadIdx.x; q < sl.stride; q += BS) {
+                const double *v = sj + (size_t)q * W1;
+                if (v[0] != sl.stamp) continue;
+                u[0] += (double)__popcll((unsigned long long)__double_as_longlong(v[1]));
+                u[1] += v[2];
+                u[2] += v[3];
+                if (D == 3) u[3] += v[4];
+            }
+            block_sum<4, BS>(u, reinterpret_cast<double(*)[4]>(&part[0][0]));
+            if (threadIdx.x == 0) {
+                double Xj[3], Yj[3];
+                for (int k = 0; k < 3; ++k) {
+                    Xj[k] = P.X[3 * jj + k];
+                    const double Uj = (k < D && u[0] > 0.0) ? u[1 + k] / u[0] : 0.0;
+                    Yj[k] = Xj[k] + (k < D ? 0.5 * (Uj + P.U[3 * jj + k]) : 0.0);
+                }
+                const double Rj = P.a[jj];
+                pair_force(Xi, Xj, Ri, Rj, Ci, rp, g, F);
+                pair_force(Yi, Yj, Ri, Rj, Ci, rp, g, F + 3);
+            }
+            __syncthreads(); // part is reused
+        }
     }
-    block_sum<6, BS>(F, reinterpret_cast<double(*)[6]>(&part[0][0]));
 
     // 3. close Algorithm 1, then the new indicator
     if (threadIdx.x == 0) {
@@ -784,15 +854,14 @@ SlotParams slot_params(lbm_ctx *c, bool on)
     SlotParams sl{};
     if (!on || !c->slots || c->np == 0) return sl; // slots == NULL: no fused sums
     sl.slots = c->slots;
-    sl.X = c->P.X;
-    sl.lo = c->P.lo;
-    sl.hi = c->P.hi;
     sl.stride = c->slot_stride;
-    sl.kw = c->slot_kw;
-    sl.wn = (c->geo.nx + WAVE - 1) / WAVE;
+    sl.mx = c->slot_mx;
+    sl.my = c->slot_my;
+    sl.mz = c->slot_mz;
+    sl.sy = c->slot_sy;
+    sl.sz = c->slot_sz;
     sl.stamp = (double)c->epoch;
     sl.clear = c->owner_next ? nullptr : c->owner;
-    sl.flags = c->flags;
     return sl;
 }
 

@@ -15,11 +15,44 @@ namespace lbm {
 constexpr int WAVE = 64;
 constexpr int UNR = 8; // cells whose loads a lane keeps in flight together
 
+// Cross-row step of a wavefront sum, with the gfx950 lane swaps: given v in
+// both operands, v_permlane16_swap exchanges the odd 16-lane rows of one with
+// the even rows of the other (v_permlane32_swap: the upper half of one with
+// the lower half of the other), so the two results hold the two members of
+// every row pair (half pair), and their sum is the same, added in the same
+// order, on every lane.
+template <bool HALVES>
+__device__ __forceinline__ double swap_add(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+    unsigned l0, l1, h0, h1;
+    if constexpr (HALVES) {
+        const auto L = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto H = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        l0 = L[0], l1 = L[1], h0 = H[0], h1 = H[1];
+    } else {
+        const auto L = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto H = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        l0 = L[0], l1 = L[1], h0 = H[0], h1 = H[1];
+    }
+    return __longlong_as_double((long long)(((unsigned long long)h0 << 32) | l0)) +
+           __longlong_as_double((long long)(((unsigned long long)h1 << 32) | l1));
+}
+
+// Sum over the 64 lanes of a wavefront, every lane getting the same bits,
+// without an LDS round trip.  Within each row of 16 lanes the partner values
+// move over the DPP network: lanes xor 1, xor 2 (quad permutes), then the
+// half-row and row mirrors, each step adding a value computed the same way on
+// both sides; then rows 0+1 and 2+3, then the two halves (swap_add).  Must be
+// called with all 64 lanes active.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-    return v;
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x141, 0xF, 0xF, false); // row_half_mirror
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x140, 0xF, 0xF, false); // row_mirror
+    return swap_add<true>(swap_add<false>(v));
 }
 
 // Sum NS values over a workgroup of BS threads; the totals land in thread 0.
@@ -127,79 +160,82 @@ __device__ __forceinline__ int walk_node(const Box &b, const CellWalk &w, const 
     return wrap(xu, g.nx) + g.nx * (wrap(yu, g.ny) + g.ny * wrap(zu, g.nz));
 }
 
-// Keyed wavefront sums of the momentum moments of one step's solid nodes
-// into the slots (the fused-sums step).  Called by every lane of the
-// wavefront with uniform control flow; `active` lanes hold a solid node
-// (x, y, z) of particle `own` with velocity u.  The key of a node is its
-// particle and its slot: the row of the particle's scan box it lies in and
-// the wavefront of the lattice row, counted from the box's first one, so
-// every slot has exactly one writing wavefront.  Each distinct key in the
-// wavefront is summed with the butterfly (fixed order) and written by its
-// lowest lane, with the stamp of the step.  Moments as in the momentum sums:
-// 2D [N, u_x, u_y, r x u, |r|^2], 3D [N, u (3), r x u (3), inertia xx yy zz xy xz yz].
+// Slot of a solid node in its particle's table (the fused-sums step).  A
+// slot is one wavefront of one lattice row: the row is keyed by its wrapped y
+// (and z) modulo powers of two My, Mz, the wavefront by its index in the row
+// modulo a power of two Mx.  The sizes are chosen at set-up so that the rows
+// and wavefronts of any scan box map to distinct slots (each at least the
+// box's extent in rows, or wavefronts it can touch, and on a periodic axis a
+// divisor of the period or at least the period), so the key needs nothing
+// but the node's coordinates.
+__device__ __forceinline__ uint32_t slot_of(int x, int y, int z, const SlotParams &sl)
+{
+    return (uint32_t)(((z & sl.mz) << sl.sz) | ((y & sl.my) << sl.sy) | ((x >> 6) & sl.mx));
+}
+
+// Moments of the bit positions set in a wavefront mask: count, sum and sum
+// of squares of the positions (bit-plane popcounts; exact integers).
+__device__ __forceinline__ void mask_moments(unsigned long long m, double &n, double &s1, double &s2)
+{
+    const unsigned long long P[6] = {0xAAAAAAAAAAAAAAAAull, 0xCCCCCCCCCCCCCCCCull, 0xF0F0F0F0F0F0F0F0ull,
+                                     0xFF00FF00FF00FF00ull, 0xFFFF0000FFFF0000ull, 0xFFFFFFFF00000000ull};
+    long long a = 0, b = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        a += (long long)__popcll(m & P[i]) << i;
+        b += (long long)__popcll(m & P[i]) << (2 * i);
+#pragma unroll
+        for (int j = i + 1; j < 6; ++j) b += (long long)__popcll(m & P[i] & P[j]) << (i + j + 1);
+    }
+    n = (double)__popcll(m);
+    s1 = (double)a;
+    s2 = (double)b;
+}
+
+// Per-slot sums of one step's solid nodes (the fused-sums step), taken in
+// the lattice kernel.  Called by every lane of the wavefront with uniform
+// control flow; `active` lanes hold a solid node (x, y, z) of particle own
+// with velocity u.  For each distinct (particle, slot) key among the lanes,
+// its lowest lane writes the record [stamp, lane mask, sums]: the mask gives
+// the count and the lane offsets s = x mod 64 of the nodes, and the sums are
+// 2D [u_x, u_y, s u_y], 3D [u_x, u_y, u_z, s u_y, s u_z], each a fixed-order
+// wavefront sum.  The particle kernel shifts these to moments about the
+// particle centre, knowing the slot's row and first node.
 template <int D>
 __device__ void slot_sums(bool active, uint16_t own, int x, int y, int z, double ux, double uy, double uz,
-                          const SlotParams &sp, const Geom &g)
+                          const SlotParams &sl)
 {
-    constexpr int NS = D == 2 ? 5 : 13;
-    unsigned long long pending = __ballot(active);
-    if (pending == 0ull) return;
+    constexpr int NV = D == 2 ? 3 : 5;
+    if (__ballot(active) == 0ull) return;
+    const uint32_t key = active ? ((uint32_t)own << 16) | slot_of(x, y, z, sl) : 0xFFFFFFFFu;
+    const double s = (double)(x & (WAVE - 1));
     const int lane = threadIdx.x & (WAVE - 1);
-    uint32_t key = 0xFFFFFFFFu;
-    double rx = 0.0, ry = 0.0, rz = 0.0;
-    if (active) {
-        const int i = own;
-        const int lo0 = sp.lo[3 * i], lo1 = sp.lo[3 * i + 1], lo2 = sp.lo[3 * i + 2];
-        const int hi0 = sp.hi[3 * i], hi1 = sp.hi[3 * i + 1];
-        int xu = x, yu = y, zu = z; // unwrapped into the box (it spans less than a period)
-        if (g.per_x) xu = xu < lo0 ? xu + g.nx : (xu > hi0 ? xu - g.nx : xu);
-        if (g.per_y) yu = yu < lo1 ? yu + g.ny : (yu > hi1 ? yu - g.ny : yu);
-        if (D == 3 && g.per_z) {
-            const int hi2 = sp.hi[3 * i + 2];
-            zu = zu < lo2 ? zu + g.nz : (zu > hi2 ? zu - g.nz : zu);
-        }
-        const int row = (yu - lo1) + (hi1 - lo1 + 1) * (zu - lo2);
-        const int j = ((x / WAVE) - (wrap(lo0, g.nx) / WAVE) + sp.wn) % sp.wn;
-        if (row >= 0 && j < sp.kw && row * sp.kw + j < sp.stride) key = ((uint32_t)i << 16) | (uint32_t)(row * sp.kw + j);
-        else sp.flags[1] = 1;
-        rx = (double)xu - sp.X[3 * i];
-        ry = (double)yu - sp.X[3 * i + 1];
-        rz = D == 3 ? (double)zu - sp.X[3 * i + 2] : 0.0;
-    }
-    pending = __ballot(key != 0xFFFFFFFFu);
+    unsigned long long pending = __ballot(active);
     while (pending) {
         const int leader = __ffsll((long long)pending) - 1;
-        const uint32_t k = (uint32_t)__shfl((int)key, leader);
+        const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
         const bool mine = key == k;
-        double v[NS];
-        v[0] = mine ? 1.0 : 0.0;
-        v[1] = mine ? ux : 0.0;
-        v[2] = mine ? uy : 0.0;
+        const unsigned long long mask = __ballot(mine);
+        double v[NV];
+        v[0] = mine ? ux : 0.0;
+        v[1] = mine ? uy : 0.0;
         if constexpr (D == 2) {
-            v[3] = mine ? rx * uy - ry * ux : 0.0;
-            v[4] = mine ? rx * rx + ry * ry : 0.0;
+            v[2] = mine ? s * uy : 0.0;
         } else {
-            const double rr = rx * rx + ry * ry + rz * rz;
-            v[3] = mine ? uz : 0.0;
-            v[4] = mine ? ry * uz - rz * uy : 0.0;
-            v[5] = mine ? rz * ux - rx * uz : 0.0;
-            v[6] = mine ? rx * uy - ry * ux : 0.0;
-            v[7] = mine ? rr - rx * rx : 0.0;
-            v[8] = mine ? rr - ry * ry : 0.0;
-            v[9] = mine ? rr - rz * rz : 0.0;
-            v[10] = mine ? -(rx * ry) : 0.0;
-            v[11] = mine ? -(rx * rz) : 0.0;
-            v[12] = mine ? -(ry * rz) : 0.0;
+            v[2] = mine ? uz : 0.0;
+            v[3] = mine ? s * uy : 0.0;
+            v[4] = mine ? s * uz : 0.0;
         }
 #pragma unroll
-        for (int m = 0; m < NS; ++m) v[m] = wave_sum(v[m]);
+        for (int m = 0; m < NV; ++m) v[m] = wave_sum(v[m]);
         if (lane == leader) {
-            double *out = sp.slots + ((size_t)(k >> 16) * sp.stride + (k & 0xFFFFu)) * (NS + 1);
-            out[0] = sp.stamp;
+            double *out = sl.slots + ((size_t)(k >> 16) * sl.stride + (k & 0xFFFFu)) * (NV + 2);
+            out[0] = sl.stamp;
+            out[1] = __longlong_as_double((long long)mask);
 #pragma unroll
-            for (int m = 0; m < NS; ++m) out[1 + m] = v[m];
+            for (int m = 0; m < NV; ++m) out[2 + m] = v[m];
         }
-        pending &= ~__ballot(mine);
+        pending &= ~mask;
     }
 }
 

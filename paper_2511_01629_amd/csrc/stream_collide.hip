@@ -10,8 +10,9 @@
 // once: 2 Q s bytes per node, the HBM roofline of the step.
 //
 // The owner map (uint16, FLUID = 0xFFFF) selects the solid branch; a
-// wavefront with no solid node never executes it.  Solid nodes also write
-// their velocity (FP64) for the per-particle momentum sums.
+// wavefront with no solid node never executes it.  Solid nodes also hand
+// their velocity to the per-particle momentum sums: as per-slot wavefront
+// sums (slot_sums), or, where the step has no slots, as an FP64 field.
 #include "dispatch.h"
 #include "node.h"
 #include "reduce.h"
@@ -29,8 +30,8 @@ namespace lbm {
 // remap of the workgroup order.
 //
 // With slots (the fused-sums step), the solid nodes also add their momentum
-// moments to their particle's slots (keyed wavefront sums) and, on in-place
-// steps, reset their owner entry, which no other lane reads.
+// sums to their particle's slots (keyed wavefront sums, no table lookups) and,
+// on in-place steps, reset their owner entry, which no other lane reads.
 template <class L, class S, class T>
 __global__ __launch_bounds__(256) void k_stream_collide(const typename S::raw *__restrict__ fin,
                                                          typename S::raw *__restrict__ fout, const uint16_t *owner,
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(const typename S::raw *_
     }
     if (sl.slots) { // uniform
         const bool solid = valid && own != FLUID;
-        slot_sums<L::D>(solid, own, x, y, z, (double)ux, (double)uy, (double)uz, sl, g);
+        slot_sums<L::D>(solid, own, x, y, z, (double)ux, (double)uy, (double)uz, sl);
         if (solid && sl.clear) sl.clear[idx] = FLUID;
     }
 }
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(TPB) void k_stream_collide_lds(const typename S::ra
         }
         if (sl.slots) { // uniform
             const bool solid = valid && own != FLUID;
-            slot_sums<L::D>(solid, own, x0 + i, y, z, (double)ux, (double)uy, (double)uz, sl, g);
+            slot_sums<L::D>(solid, own, x0 + i, y, z, (double)ux, (double)uy, (double)uz, sl);
             if (solid && sl.clear) sl.clear[rbase + x0 + i] = FLUID;
         }
     }
@@ -339,6 +340,7 @@ static inline unsigned blocks_for(int64_t N) { return (unsigned)((N + 255) / 256
 hipError_t launch_stream_collide(lbm_ctx *c, const void *fin, void *fout)
 {
     const SlotParams sl = slot_params(c, c->fused != 0);
+    double *usol = sl.slots ? nullptr : c->usol; // the slots replace the velocity field of the sums
     const int gx = (c->geo.nx + 255) / 256;
     const unsigned blocks = (unsigned)gx * (unsigned)(c->geo.ny * c->geo.nz);
     return dispatch(c, [&](auto L, auto S, auto T) {
@@ -358,14 +360,14 @@ hipError_t launch_stream_collide(lbm_ctx *c, const void *fin, void *fout)
                     const unsigned bs = (unsigned)gxs * (unsigned)(c->geo.ny * c->geo.nz);
                     return launch(c, k_stream_collide_lds<Lt, St, Tt, TPB>, dim3(bs), dim3(TPB),
                                   (const typename St::raw *)fin, (typename St::raw *)fout, (const uint16_t *)c->owner,
-                                  acc, c->usol, c->flags, c->geo, c->sp, gxs, sl);
+                                  acc, usol, c->flags, c->geo, c->sp, gxs, sl);
                 };
                 if (c->geo.nx >= 128 * NPL) return staged(std::integral_constant<int, 128>{});
                 return staged(std::integral_constant<int, 64>{});
             }
         }
         return launch(c, k_stream_collide<Lt, St, Tt>, dim3(blocks), dim3(256), (const typename St::raw *)fin,
-                      (typename St::raw *)fout, (const uint16_t *)c->owner, acc, c->usol, c->flags, c->geo, c->sp, gx,
+                      (typename St::raw *)fout, (const uint16_t *)c->owner, acc, usol, c->flags, c->geo, c->sp, gx,
                       sl);
     });
 }

@@ -77,9 +77,17 @@ def test_penalize_all_random_state():
     assert rel(sim.populations(), ora.f()) < TOL
 
 
-def _compare_run(cfg, parts, steps, f0=None, storage="f64", tol=TOL, xtol=TOL):
+def _compare_run(cfg, parts, steps, f0=None, storage="f64", tol=TOL, xtol=TOL, fused=None):
+    """fused: if not None, whether the step must take the momentum sums in the
+    lattice kernel (no separate momentum-sum launches)."""
     sim, ora = pair(cfg, parts, storage=storage, f0=f0)
+    if fused is not None:
+        sim.profile(True)
     rg = sim.step_record(steps)
+    if fused is not None:
+        launches = sim.profile_read()["reduce_clear"][1]
+        sim.profile(False)
+        assert (launches == 0) == fused, launches
     ro = ora.step(steps, record=True)
     # per-step records: X theta U omega A N
     scaleX = max(np.abs(ro[:, :, 0:3]).max(), 1.0)
@@ -117,7 +125,8 @@ def test_particles_random_state_2d():
              dict(shape="disk", rho_s=1.2, a=5.0, x=(19.0, 17.1, 0.0)),
              dict(shape="ellipse", rho_s=1.4, a=6.0, b=3.0, x=(40.5, 6.3, 0.0), theta=0.9)]
     f0 = random_state((1, 37, 45), 9, 1e-3, seed=3)
-    _, _, rg, _ = _compare_run(cfg, parts, 30, f0=f0)
+    # boxes wider than the period less a wavefront: sums in a kernel of their own
+    _, _, rg, _ = _compare_run(cfg, parts, 30, f0=f0, fused=False)
     assert np.abs(rg[:, :, 10:12]).max() > 1e-6  # contact forces acted
 
 
@@ -215,8 +224,41 @@ def test_many_bodies_contacts():
     kinds = [("disk", 3.0, 3.0)] * 56 + [("ellipse", 4.0, 2.0)] * 24
     parts = place((128, 160), kinds, seed=11, rho_range=(1.2, 1.8), upper_axis=1, gap=0.3, margin=0.3)
     cfg = dict(lattice="D2Q9", n=(128, 160, 1), periodic=(1, 0, 0), tau=0.6, g=(0.0, -2e-4, 0.0))
-    _, _, rg, _ = _compare_run(cfg, parts, 150, xtol=1e-11)
+    _, _, rg, _ = _compare_run(cfg, parts, 150, xtol=1e-11, fused=True)
     assert (np.abs(rg[:, :, 10:12]).max(axis=(1, 2)) > 0).sum() > 50
+
+
+def test_fused_sums_periodic_wrap_2d():
+    """Momentum sums taken by the lattice kernel, with scan boxes wrapping both
+    periodic axes and a ragged last wavefront in x (200 = 3 x 64 + 8)."""
+    banner("fused sums wrap 2d 200x128")
+    cfg = dict(lattice="D2Q9", n=(200, 128, 1), periodic=(1, 1, 0), tau=0.7, g=(0.0, -3e-4, 0.0))
+    parts = [dict(shape="disk", rho_s=1.5, a=6.0, x=(1.5, 60.0, 0.0)),
+             dict(shape="disk", rho_s=1.3, a=5.0, x=(197.2, 20.3, 0.0)),
+             dict(shape="ellipse", rho_s=1.4, a=7.0, b=3.5, x=(100.4, 1.2, 0.0), theta=0.4),
+             dict(shape="disk", rho_s=1.6, a=4.0, x=(63.6, 126.5, 0.0)),
+             dict(shape="disk", rho_s=1.2, a=4.5, x=(140.0, 70.0, 0.0))]
+    f0 = random_state((1, 128, 200), 9, 1e-3, seed=21)
+    _compare_run(cfg, parts, 40, f0=f0, fused=True)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_fused_sums_periodic_wrap_3d(storage):
+    """D3Q19 with every axis periodic, spheres wrapping each of them, a ragged
+    last wavefront (132 = 2 x 64 + 4); in FP32 the rows are staged through
+    LDS."""
+    banner(f"fused sums wrap 3d 132x32x32 {storage}")
+    cfg = dict(lattice="D3Q19", n=(132, 32, 32), periodic=(1, 1, 1), tau=0.65, g=(0.0, 0.0, -4e-4))
+    parts = [dict(shape="sphere", rho_s=1.6, a=4.0, x=(1.0, 8.0, 8.0)),
+             dict(shape="sphere", rho_s=1.3, a=3.5, x=(129.9, 24.0, 30.9)),
+             dict(shape="sphere", rho_s=1.4, a=4.0, x=(65.0, 0.7, 16.0)),
+             dict(shape="sphere", rho_s=1.5, a=3.0, x=(64.0, 20.0, 1.0))]
+    f0 = random_state((32, 32, 132), 19, 1e-3, seed=22)
+    if storage == "f64":
+        _compare_run(cfg, parts, 8, f0=f0, fused=True)
+    else:
+        _compare_run(cfg, parts, 8, f0=f0.astype(np.float32).astype(np.float64), storage="f32", tol=5e-6,
+                     xtol=1e-7, fused=True)
 
 
 def test_many_bodies_substeps_k3():
