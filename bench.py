@@ -32,7 +32,7 @@ MATH = {"f64": "f64", "f32": "f32", "f16": "f32", "bf16": "f32"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = ["paper_2511_01629_amd/csrc/stream_collide.hip", "paper_2511_01629_amd/csrc/node.h",
                   "paper_2511_01629_amd/csrc/lattice.h", "paper_2511_01629_amd/csrc/ctx.h",
-                  "paper_2511_01629_amd/csrc/dispatch.h"]
+                  "paper_2511_01629_amd/csrc/dispatch.h", "paper_2511_01629_amd/csrc/reduce.h"]
 
 
 def log(msg):

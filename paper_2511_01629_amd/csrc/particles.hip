@@ -561,7 +561,16 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
     PrevState ps = load_prev(P, i);
     for (int k = 0; k < 3; ++k) ps.Uprev[k] = P.U[3 * i + k]; // U^{n-1}
 
-    // 1. own sums over the scan box the indicator was rasterised with
+    // the first BS candidates of step 2, loaded now rather than after the sums
+    double Xc[3] = {0, 0, 0}, Rc = 0.0;
+    if ((int)threadIdx.x < np) {
+        for (int k = 0; k < D; ++k) Xc[k] = P.X[3 * threadIdx.x + k];
+        Rc = P.a[threadIdx.x];
+    }
+
+    // 1. own sums over the scan box the indicator was rasterised with: item t
+    // is the k-th wavefront (k = t mod Mx) of box row t / Mx; every record is
+    // loaded whole, then kept if it carries this step's stamp
     double s[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) s[k] = 0.0;
@@ -570,16 +579,27 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
         const int lo0 = P.lo[3 * i], hi0 = P.hi[3 * i], lo1 = P.lo[3 * i + 1], lo2 = P.lo[3 * i + 2];
         const int e1 = P.hi[3 * i + 1] - lo1 + 1, e2 = P.hi[3 * i + 2] - lo2 + 1;
         const int rows = e1 > 0 && e2 > 0 ? e1 * e2 : 0;
-        for (int r = threadIdx.x; r < rows; r += BS) {
+        const int lk = __ffs(sl.mx + 1) - 1; // Mx = 2^lk wavefront keys
+        for (int t = threadIdx.x; t < (rows << lk); t += BS) {
+            const int r = t >> lk, k = t & sl.mx;
+            int xu = lo0, w = 0, base = 0;
+            bool found = false;
+            for (int q = 0; q <= k && xu <= hi0; ++q) { // walk to the k-th wavefront
+                const int wx = wrap(xu, g.nx);
+                w = wx >> 6;
+                base = xu - (wx & (WAVE - 1));
+                found = q == k;
+                xu = base + min(WAVE, g.nx - (w << 6));
+            }
+            if (!found) continue; // the box touches fewer than k + 1 wavefronts
             const int yu = lo1 + r % e1, zu = lo2 + r / e1;
             const int rkey = ((wrap(zu, g.nz) & sl.mz) << sl.sz) | ((wrap(yu, g.ny) & sl.my) << sl.sy);
-            const double dy = (double)yu - Xi[1], dz = D == 3 ? (double)zu - Xi[2] : 0.0;
-            for (int xu = lo0; xu <= hi0;) {
-                const int wx = wrap(xu, g.nx), w = wx >> 6, base = xu - (wx & (WAVE - 1));
-                xu = base + min(WAVE, g.nx - (w << 6));
-                const double *v = si + (size_t)(rkey | (w & sl.mx)) * W1;
-                if (v[0] == sl.stamp) add_slot<D>(v, (double)base - Xi[0], dy, dz, s);
-            }
+            const double *v = si + (size_t)(rkey | (w & sl.mx)) * W1;
+            double rv[W1];
+#pragma unroll
+            for (int m = 0; m < W1; ++m) rv[m] = v[m];
+            if (rv[0] == sl.stamp)
+                add_slot<D>(rv, (double)base - Xi[0], (double)yu - Xi[1], D == 3 ? (double)zu - Xi[2] : 0.0, s);
         }
     }
     block_sum<NS, BS>(s, part);
@@ -643,9 +663,13 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
         const int j = j0 + (int)threadIdx.x;
         bool in = false;
         if (j < np && j != i) {
+            if (j0 > 0) {
+                for (int k = 0; k < D; ++k) Xc[k] = P.X[3 * j + k];
+                Rc = P.a[j];
+            }
             double dv2 = 0.0;
             for (int k = 0; k < D; ++k) {
-                double dk = Xi[k] - P.X[3 * j + k];
+                double dk = Xi[k] - Xc[k];
                 if (per[k]) {
                     const double h = 0.5 * n[k];
                     if (dk > h) dk -= n[k];
@@ -653,7 +677,7 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
                 }
                 dv2 += dk * dk;
             }
-            const double reach = Ri + P.a[j] + rp.delta + 0.6;
+            const double reach = Ri + Rc + rp.delta + 0.6;
             in = dv2 <= reach * reach;
         }
         const unsigned long long m = __ballot(in);
