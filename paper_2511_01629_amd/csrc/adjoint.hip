@@ -24,6 +24,11 @@
 //                   per-workgroup partial of dL/dtau.
 //   k_adj_particles per particle: A_bar^n = sum of a_bar over its nodes, and
 //                   the density and |g| partials through a = b g + A.
+// Where the forward step has momentum-sum slots, the lattice adjoint sums
+// a_bar per (particle, slot) record instead of writing it per node, and one
+// kernel per particle (k_adj_fused) closes A_bar^n from the records and then
+// runs the rigid adjoint of step n - 1: two launches per step instead of
+// three.
 #include "dispatch.h"
 #include "node.h"
 #include "reduce.h"
@@ -31,30 +36,65 @@
 namespace lbm {
 
 // ----------------------------------------------------------- lattice adjoint
+// The a_bar of one step's solid nodes summed per (particle, slot) record
+// (the slot layout of the forward's momentum sums, slot_of): for each
+// distinct key among the lanes, its lowest lane writes [stamp, sum a_bar
+// (D)], each a fixed-order wavefront sum.  Called by every lane of the
+// wavefront with uniform control flow.
+template <int D>
+__device__ void slot_abar(bool active, uint16_t own, int x, int y, int z, const double *ab, const SlotParams &sl)
+{
+    if (__ballot(active) == 0ull) return;
+    const uint32_t key = active ? ((uint32_t)own << 16) | slot_of(x, y, z, sl) : 0xFFFFFFFFu;
+    const int lane = threadIdx.x & (WAVE - 1);
+    unsigned long long pending = __ballot(active);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
+        const bool mine = key == k;
+        const unsigned long long mask = __ballot(mine);
+        double v[D];
+#pragma unroll
+        for (int m = 0; m < D; ++m) v[m] = wave_sum(mine ? ab[m] : 0.0);
+        if (lane == leader) {
+            double *out = sl.slots + ((size_t)(k >> 16) * sl.stride + (k & 0xFFFFu)) * (D + 1);
+            out[0] = sl.stamp;
+#pragma unroll
+            for (int m = 0; m < D; ++m) out[1 + m] = v[m];
+        }
+        pending &= ~mask;
+    }
+}
+
 template <class L, class S, class T>
 __global__ __launch_bounds__(256) void k_adj_lattice(const typename S::raw *__restrict__ fprev,
                                                       const uint16_t *__restrict__ owner, const T *__restrict__ acc_tab,
                                                       const T *__restrict__ uext, const T *__restrict__ lam_in,
                                                       T *__restrict__ lam_out, double *__restrict__ asol,
-                                                      double *__restrict__ tau_part, Geom g, StepParams sp, int gx)
+                                                      double *__restrict__ tau_part, Geom g, StepParams sp, int gx,
+                                                      SlotParams sl)
 {
     const int row = blockIdx.x / gx, bx = blockIdx.x - row * gx;
     const int x = bx * 256 + (int)threadIdx.x;
     const bool valid = x < g.nx;
+    int y, z;
+    if (L::D == 2) {
+        y = row;
+        z = 0;
+    } else {
+        z = row / g.ny;
+        y = row - z * g.ny;
+    }
     double tb = 0.0;
+    bool solid_node = false;
+    uint16_t own_node = FLUID;
+    T abn[3] = {0, 0, 0};
     if (valid) {
-        int y, z;
-        if (L::D == 2) {
-            y = row;
-            z = 0;
-        } else {
-            z = row / g.ny;
-            y = row - z * g.ny;
-        }
         const int N = (int)g.N;
         const int idx = row * g.nx + x;
         T f[L::Q];
-        pull<L, S, T>(fprev, idx, x, y, z, g, N, f);
+        const RowPull<L> rp(x, y, z, idx, bx > 0 && bx * 256 + 256 < g.nx, g);
+        pull_row<L, S, T>(fprev, rp, f);
         const uint16_t own = owner[idx];
         const bool solid = own != FLUID;
         T a[3] = {0, 0, 0};
@@ -174,13 +214,16 @@ __global__ __launch_bounds__(256) void k_adj_lattice(const typename S::raw *__re
         for (int q = 0; q < L::Q; ++q) {
             fbar[q] += T(L::cx[q]) * ub[0] + T(L::cy[q]) * ub[1] + T(L::cz[q]) * ub[2] + (q > 0 ? sb : T(0));
             // transpose of the pull: f_q(x) came from pull_offset(q, x)
-            lam_out[pull_offset<L>(q, idx, x, y, z, g, N)] = fbar[q];
+            lam_out[rp.at(q)] = fbar[q];
         }
-        if (solid) {
+        if (solid && asol) {
             asol[idx] = (double)ab[0];
             asol[N + idx] = (double)ab[1];
             if (L::D == 3) asol[2 * N + idx] = (double)ab[2];
         }
+        solid_node = solid;
+        own_node = own;
+        for (int k = 0; k < 3; ++k) abn[k] = ab[k];
         // dL/dtau through om = 1/tau, gamma = 1 - 1/(2 tau), and alpha = 1/tau
         const double om2 = sp.omega * sp.omega;
         tb = (double)omb * (-om2) + (double)gamb * (0.5 * om2);
@@ -190,6 +233,10 @@ __global__ __launch_bounds__(256) void k_adj_lattice(const typename S::raw *__re
     double s[1] = {tb};
     block_sum<1, 256>(s, part);
     if (threadIdx.x == 0) tau_part[blockIdx.x] += s[0];
+    if (sl.slots) { // uniform
+        const double abd[3] = {(double)abn[0], (double)abn[1], (double)abn[2]};
+        slot_abar<L::D>(solid_node, own_node, x, y, z, abd, sl);
+    }
 }
 
 // --------------------------------------------------------------- rigid adjoint
@@ -488,6 +535,139 @@ __global__ __launch_bounds__(256) void k_adj_particles(const uint16_t *__restric
     g_g[i] = gg0 + dg;
 }
 
+// Steps with slots: one workgroup per particle j closes the particle adjoint
+// of step n from j's records (A_bar^n_j and its density and |g| partials),
+// then, if rigid, runs the rigid adjoint of step n - 1 for j (A: the arrays of
+// that step).  The partners' A_bar^n, which the rigid adjoint needs through
+// their force adjoints, are summed from their records by the whole
+// workgroup, for the partners in reach only (|X_i - X_j| <= R_i + R_j +
+// delta + 0.6 at X^{n-1}: the prediction moves each body by at most 0.3), in
+// index order; thread 0 accumulates the pair terms.  Abar_n: A_bar^n out.
+template <int D, int BS>
+__global__ __launch_bounds__(BS) void k_adj_fused(AdjArrays A, PartDev P, RigidParams rp, Geom g, SlotParams sl,
+                                                  double *__restrict__ Abar_n, int rigid)
+{
+    constexpr int W1 = D + 1;
+    const int j = blockIdx.x, np = rp.np;
+    __shared__ double part[BS / WAVE][3];
+    __shared__ double s_Ab[3];
+    __shared__ int s_list[BS], s_cnt[BS / WAVE];
+    const double rho = P.rho_s[j], rg0 = A.rho_g[j], gg0 = A.g_g[j];
+    // what the rigid part needs, loaded up front so its latency overlaps the sums
+    const double *rj = A.rec + REC_STRIDE * j;
+    double Xbj[3], Upbj[3], Aj[3], Xj[3];
+    for (int k = 0; k < 3; ++k) {
+        Xbj[k] = A.Xbar[3 * j + k];
+        Upbj[k] = A.Upbar[3 * j + k];
+        Aj[k] = rj[10 + k];
+        Xj[k] = rj[k];
+    }
+    const double Nj = rj[13], Rj = P.a[j], V = particle_volume(P.shape[j], P.a[j], P.b[j]);
+    double Xc[3] = {0, 0, 0}, Rc = 0.0; // the first BS candidates of the partner search
+    if ((int)threadIdx.x < np) {
+        for (int k = 0; k < D; ++k) Xc[k] = A.rec[REC_STRIDE * threadIdx.x + k];
+        Rc = P.a[threadIdx.x];
+    }
+
+    // 1. A_bar^n_j from j's records
+    double t[3] = {0, 0, 0};
+    {
+        const double *sj = sl.slots + (size_t)j * sl.stride * W1;
+        for (int q = threadIdx.x; q < sl.stride; q += BS) {
+            double rv[W1];
+#pragma unroll
+            for (int m = 0; m < W1; ++m) rv[m] = sj[(size_t)q * W1 + m];
+            if (rv[0] == sl.stamp)
+#pragma unroll
+                for (int m = 0; m < D; ++m) t[m] += rv[1 + m];
+        }
+    }
+    block_sum<3, BS>(t, part);
+    double drho = 0.0, dg = 0.0;
+    if (threadIdx.x == 0) {
+        adj_particle_close(t, rho, rp, Abar_n + 3 * j, drho, dg);
+        for (int k = 0; k < 3; ++k) s_Ab[k] = t[k];
+        if (!rigid) {
+            A.rho_g[j] = rg0 + drho;
+            A.g_g[j] = gg0 + dg;
+        }
+    }
+    if (!rigid) return; // uniform
+    __syncthreads();
+
+    // 2. the rigid adjoint of step n - 1 for j
+    AdjBody bj;
+    adj_positions(rj, D, bj);
+    adj_force_bar(Xbj, s_Ab, Nj, rho, D, bj.F);
+    bj.R = Rj;
+    bj.C = P.Cc[j];
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int per[3] = {g.per_x, g.per_y, g.per_z};
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    double acc[2][3] = {{0, 0, 0}, {0, 0, 0}}, unit[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    for (int i0 = 0; i0 < np; i0 += BS) { // uniform
+        const int i = i0 + (int)threadIdx.x;
+        bool in = false;
+        if (i < np && i != j) {
+            if (i0 > 0) {
+                for (int k = 0; k < D; ++k) Xc[k] = A.rec[REC_STRIDE * i + k];
+                Rc = P.a[i];
+            }
+            double dv2 = 0.0;
+            for (int k = 0; k < D; ++k) {
+                double dk = Xj[k] - Xc[k];
+                if (per[k]) {
+                    const double h = 0.5 * n[k];
+                    if (dk > h) dk -= n[k];
+                    else if (dk < -h) dk += n[k];
+                }
+                dv2 += dk * dk;
+            }
+            const double reach = Rj + Rc + rp.delta + 0.6;
+            in = dv2 <= reach * reach;
+        }
+        const unsigned long long m = __ballot(in);
+        if (lane == 0) s_cnt[wv] = __popcll(m);
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int q = 0; q < BS / WAVE; ++q) {
+            off += q < wv ? s_cnt[q] : 0;
+            tot += s_cnt[q];
+        }
+        if (in) s_list[off + __popcll(m & ((1ull << lane) - 1ull))] = i;
+        __syncthreads();
+        for (int t2 = 0; t2 < tot; ++t2) { // uniform
+            const int ii = s_list[t2];
+            const double *si = sl.slots + (size_t)ii * sl.stride * W1;
+            double u[3] = {0, 0, 0};
+            for (int q = threadIdx.x; q < sl.stride; q += BS) {
+                double rv[W1];
+#pragma unroll
+                for (int mm = 0; mm < W1; ++mm) rv[mm] = si[(size_t)q * W1 + mm];
+                if (rv[0] == sl.stamp)
+#pragma unroll
+                    for (int mm = 0; mm < D; ++mm) u[mm] += rv[1 + mm];
+            }
+            block_sum<3, BS>(u, part);
+            if (threadIdx.x == 0) {
+                AdjBody bi;
+                const double *ri = A.rec + REC_STRIDE * ii;
+                adj_positions(ri, D, bi);
+                adj_force_bar(A.Xbar + 3 * ii, u, ri[13], P.rho_s[ii], D, bi.F);
+                bi.R = P.a[ii];
+                bi.C = P.Cc[ii];
+                adj_pair(bj, bi, rp, g, acc, unit);
+            }
+            __syncthreads(); // part is reused
+        }
+    }
+    if (threadIdx.x != 0) return;
+    double drho2, dg2;
+    adj_rigid_close(j, A, rp, g, bj, Nj, Aj, rho, V, Xbj, s_Ab, Upbj, acc, unit, drho2, dg2);
+    A.rho_g[j] = (rg0 + drho) + drho2;
+    A.g_g[j] = (gg0 + dg) + dg2;
+}
+
 // U^{-1} = U^0 was measured with a = b g on every node of the particle:
 // dU^{-1}/da = 1/2 gives the density and |g| partials of the initial state.
 __device__ __forceinline__ void adj_initial_terms(double rho, const double *Upb, const RigidParams &rp, double &drho,
@@ -519,7 +699,7 @@ __global__ void k_adj_initial(PartDev P, RigidParams rp, const double *__restric
 // ----------------------------------------------------------------- launchers
 hipError_t launch_adj_lattice(lbm_ctx *c, const void *fprev, const uint16_t *owner, const double *uext_d,
                               const float *uext_f, const double *acc_d, const float *acc_f, const void *lam_in,
-                              void *lam_out, double *asol, double *tau_part)
+                              void *lam_out, double *asol, double *tau_part, const SlotParams &sl)
 {
     const int gx = (c->geo.nx + 255) / 256;
     const unsigned blocks = (unsigned)gx * (unsigned)(c->geo.ny * c->geo.nz);
@@ -532,7 +712,7 @@ hipError_t launch_adj_lattice(lbm_ctx *c, const void *fprev, const uint16_t *own
         const Tt *uext = dbl ? (const Tt *)uext_d : (const Tt *)uext_f;
         hipLaunchKernelGGL((k_adj_lattice<Lt, St, Tt>), dim3(blocks), dim3(256), 0, c->stream,
                            (const typename St::raw *)fprev, owner, acc, uext, (const Tt *)lam_in, (Tt *)lam_out, asol,
-                           tau_part, c->geo, c->sp, gx);
+                           tau_part, c->geo, c->sp, gx, sl);
         return hipGetLastError();
     });
 }
@@ -564,6 +744,21 @@ hipError_t launch_adj_particles(lbm_ctx *c, const PartDev &P, const uint16_t *ow
     else
         hipLaunchKernelGGL(k_adj_particles<3>, dim3(c->np), dim3(256), 0, c->stream, owner, asol, rec, P, rp, c->geo,
                            Abar_out, rho_g, g_g);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_fused(lbm_ctx *c, const PartDev &P, const AdjArraysHost &h, const SlotParams &sl,
+                            double *Abar_n, int rigid)
+{
+    if (c->np == 0) return hipSuccess;
+    RigidParams rp = c->rp;
+    rp.np = c->np;
+    if (c->d == 2)
+        hipLaunchKernelGGL((k_adj_fused<2, 256>), dim3(c->np), dim3(256), 0, c->stream, adj_arrays(h), P, rp, c->geo, sl,
+                           Abar_n, rigid);
+    else
+        hipLaunchKernelGGL((k_adj_fused<3, 256>), dim3(c->np), dim3(256), 0, c->stream, adj_arrays(h), P, rp, c->geo, sl,
+                           Abar_n, rigid);
     return hipGetLastError();
 }
 

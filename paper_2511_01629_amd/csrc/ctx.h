@@ -166,9 +166,12 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 // adjoint.hip
 hipError_t launch_adj_lattice(lbm_ctx *c, const void *fprev, const uint16_t *owner, const double *uext_d,
                               const float *uext_f, const double *acc_d, const float *acc_f, const void *lam_in,
-                              void *lam_out, double *asol, double *tau_part);
+                              void *lam_out, double *asol, double *tau_part, const SlotParams &sl);
 // The particle adjoints read only the constants rho_s, a, b, Cc and shape of P.
 hipError_t launch_adj_rigid(lbm_ctx *c, const PartDev &P, const AdjArraysHost &h);
+// particle adjoint of step n from the slots (A_bar^n), then, if rigid, the rigid adjoint of step n - 1
+hipError_t launch_adj_fused(lbm_ctx *c, const PartDev &P, const AdjArraysHost &h, const SlotParams &sl,
+                            double *Abar_n, int rigid);
 hipError_t launch_adj_particles(lbm_ctx *c, const PartDev &P, const uint16_t *owner, const double *asol,
                                 const double *rec, double *Abar_out, double *rho_g, double *g_g);
 hipError_t launch_adj_initial(lbm_ctx *c, const PartDev &P, const double *Upbar, double *rho_g, double *g_g);

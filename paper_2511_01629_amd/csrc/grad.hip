@@ -223,10 +223,26 @@ int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau
     // segment frames: every + 1 population buffers, then every + 1 indicators
     const size_t segsize = all ? 1 : (size_t)(G->every + 1) * (G->fbytes + G->obytes);
     int rc = LBM_OK;
+    // per-(particle, slot) records of the lattice adjoint's a_bar sums, where
+    // the forward step has a slot layout (else a_bar goes to asol per node)
+    double *aslots = nullptr;
+    int64_t astamp = 0;
+    if (c->fused && c->slots && np > 0) {
+        const size_t nrec = (size_t)np * (size_t)c->slot_stride * (size_t)(c->d + 1);
+        if ((rc = dev_alloc(c, &aslots, nrec, owned))) {
+            cleanup();
+            return rc;
+        }
+        // NaN stamps: no record counts until a step writes it
+        if (hipMemsetAsync(aslots, 0xFF, nrec * sizeof(double), c->stream) != hipSuccess) {
+            cleanup();
+            return c->err = "slot initialisation failed", LBM_EDEVICE;
+        }
+    }
     if ((rc = dev_alloc(c, &seg, segsize, owned)) || (overlap && (rc = dev_alloc(c, &seg2, segsize, owned))) ||
         (rc = dev_alloc(c, &cst, 4 * (size_t)np, owned)) || (rc = dev_alloc(c, &cshape, (size_t)np, owned)) ||
         (rc = dev_alloc(c, &lam, 2 * Q * N * lam_elt, owned)) ||
-        (rc = dev_alloc(c, &asol, (size_t)c->d * N, owned)) || (rc = dev_alloc(c, &taup, nblocks, owned)) ||
+        (rc = dev_alloc(c, &asol, aslots ? 1 : (size_t)c->d * N, owned)) || (rc = dev_alloc(c, &taup, nblocks, owned)) ||
         (rc = dev_alloc(c, &Xbar, 6 * (size_t)np, owned)) || (rc = dev_alloc(c, &Abar, 3 * (size_t)np, owned)) ||
         (rc = dev_alloc(c, &Upbar, 6 * (size_t)np, owned)) || (rc = dev_alloc(c, &rho_g, np, owned)) ||
         (rc = dev_alloc(c, &g_g, np, owned)) || (rc = dev_alloc(c, &uext_d, 3 * (size_t)np, owned)) ||
@@ -321,16 +337,37 @@ int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau
             const char *fprev = fr + (size_t)(n - s0) * G->fbytes;
             const uint16_t *own_n = (const uint16_t *)(ow + (size_t)(n - s0) * G->obytes);
             const double *rec_n = G->rec + (size_t)n * np * REC_STRIDE;
-            if (launch_adj_rigid(c, Pc, rigid_arrays(n)) != hipSuccess) rc = LBM_EDEVICE;
-            cx ^= 1;
-            cu ^= 1;
+            // with slots the rigid adjoint of step n ran with the particle adjoint of step n + 1
+            if (!aslots || n == G->T - 1) {
+                if (launch_adj_rigid(c, Pc, rigid_arrays(n)) != hipSuccess) rc = LBM_EDEVICE;
+                cx ^= 1;
+                cu ^= 1;
+            }
             char *lin = lam + (size_t)cl * Q * N * lam_elt, *lout = lam + (size_t)(cl ^ 1) * Q * N * lam_elt;
-            if (rc == LBM_OK &&
-                launch_adj_lattice(c, fprev, own_n, uext_d, uext_f, acc_d, acc_f, lin, lout, asol, taup) != hipSuccess)
+            SlotParams asl{};
+            if (aslots) {
+                asl = slot_params(c, true);
+                asl.slots = aslots;
+                asl.stamp = (double)(++astamp);
+                asl.clear = nullptr;
+            }
+            if (rc == LBM_OK && launch_adj_lattice(c, fprev, own_n, uext_d, uext_f, acc_d, acc_f, lin, lout,
+                                                   aslots ? nullptr : asol, taup, asl) != hipSuccess)
                 rc = LBM_EDEVICE;
             cl ^= 1;
-            if (rc == LBM_OK && launch_adj_particles(c, Pc, own_n, asol, rec_n, Abar, rho_g, g_g) != hipSuccess)
+            if (aslots) {
+                // A_bar^n from the records, then the rigid adjoint of step n - 1
+                const int rigid = n > 0;
+                if (rc == LBM_OK &&
+                    launch_adj_fused(c, Pc, rigid_arrays(rigid ? n - 1 : 0), asl, Abar, rigid) != hipSuccess)
+                    rc = LBM_EDEVICE;
+                if (rigid) {
+                    cx ^= 1;
+                    cu ^= 1;
+                }
+            } else if (rc == LBM_OK && launch_adj_particles(c, Pc, own_n, asol, rec_n, Abar, rho_g, g_g) != hipSuccess) {
                 rc = LBM_EDEVICE;
+            }
         }
         if (overlap && rc == LBM_OK) {
             // this segment's buffer may be recomputed into once its sweep is done

@@ -3,6 +3,7 @@
 // the macroscopic moments (eq. 15a-b), the equilibrium (eq. 13) and the
 // collision with Guo forcing (eq. 14) and penalization (eq. 17).
 #pragma once
+#include <type_traits>
 #include "ctx.h"
 #include "lattice.h"
 
@@ -53,6 +54,114 @@ __device__ __forceinline__ int pull_offset(int q, int idx, int x, int y, int z, 
         }
     }
     return wall ? L::opp[q] * N + idx : q * N + (sx + g.nx * (sy + g.ny * sz));
+}
+
+// The same offsets for a node of a row-segment kernel (one workgroup per
+// segment of a lattice row): the source rows (y - c_y, z - c_z) are uniform
+// across the workgroup, so their wrap and wall tests are made once, in scalar
+// registers.  A segment that holds neither end of its row and whose source
+// rows all exist (`interior`) needs no test per lane: population q of node x
+// comes from (source row base + q N - c_x) + x, a uniform pointer plus the
+// lane's column.  Other segments test x - 1 and x + 1 per lane and select.
+template <class L>
+struct RowPull {
+    int rb[3][3]; // [c_y + 1][c_z + 1]: (sy + ny sz) nx of the source row; -1 behind a wall
+    int xs[3];    // [c_x + 1]: the source column x - c_x; -1 behind a wall
+    int x, idx, N;
+    bool interior;
+
+    __device__ __forceinline__ RowPull(int x_, int y, int z, int idx_, bool inner_segment, const Geom &g)
+        : x(x_), idx(idx_), N((int)g.N)
+    {
+        bool walls = false;
+#pragma unroll
+        for (int cy = -1; cy <= 1; ++cy)
+#pragma unroll
+            for (int cz = -1; cz <= 1; ++cz) {
+                int sy = y - cy, sz = z - cz;
+                bool wall = false;
+                if (sy < 0) {
+                    if (g.per_y) sy += g.ny; else wall = true;
+                } else if (sy >= g.ny) {
+                    if (g.per_y) sy -= g.ny; else wall = true;
+                }
+                if (L::D == 3) {
+                    if (sz < 0) {
+                        if (g.per_z) sz += g.nz; else wall = true;
+                    } else if (sz >= g.nz) {
+                        if (g.per_z) sz -= g.nz; else wall = true;
+                    }
+                } else if (cz != 0) {
+                    wall = false; // unused in 2D
+                }
+                walls = walls || (wall && (L::D == 3 || cz == 0));
+                rb[cy + 1][cz + 1] = wall ? -1 : (sy + g.ny * sz) * g.nx;
+            }
+        interior = inner_segment && !walls;
+#pragma unroll
+        for (int cx = -1; cx <= 1; ++cx) {
+            int sx = x - cx;
+            bool wall = false;
+            if (sx < 0) {
+                if (g.per_x) sx += g.nx; else wall = true;
+            } else if (sx >= g.nx) {
+                if (g.per_x) sx -= g.nx; else wall = true;
+            }
+            xs[cx + 1] = wall ? -1 : sx;
+        }
+    }
+    // offset on any segment
+    __device__ __forceinline__ int at(int q) const
+    {
+        return interior ? q * N + rb[L::cy[q] + 1][L::cz[q] + 1] - L::cx[q] + x : offset(q);
+    }
+    // general offset (any segment)
+    __device__ __forceinline__ int offset(int q) const
+    {
+        const int r = rb[L::cy[q] + 1][L::cz[q] + 1], s = xs[L::cx[q] + 1];
+        const int a = q * N + r + s, b = L::opp[q] * N + idx;
+        const int m = -(int)(r >= 0 && s >= 0); // branch-free select
+        return (a & m) | (b & ~m);
+    }
+};
+
+// A stored population loaded into a register of its own (2-byte types
+// zero-extended to 32 bits, so the compiler does not pack two of them into
+// one register, which would need a wait per pair), converted later.
+template <class S>
+__device__ __forceinline__ auto ld_reg(const typename S::raw *p)
+{
+    if constexpr (sizeof(typename S::raw) == 2)
+        return (uint32_t)__builtin_nontemporal_load(reinterpret_cast<const uint16_t *>(p));
+    else
+        return __builtin_nontemporal_load(p);
+}
+template <class S, class T, class R>
+__device__ __forceinline__ T from_reg(R r)
+{
+    if constexpr (std::is_same<S, StF16>::value) return (T)__builtin_bit_cast(_Float16, (uint16_t)r);
+    else if constexpr (std::is_same<S, StBF16>::value) return __uint_as_float(r << 16);
+    else return r;
+}
+
+// Loads in both branches and the conversion after them, so that no wait for
+// the loads is placed at the branch join.
+template <class L, class S, class T>
+__device__ __forceinline__ void pull_row(const typename S::raw *__restrict__ fin, const RowPull<L> &rp, T *f)
+{
+    decltype(ld_reg<S>(fin)) r[L::Q];
+    if (rp.interior) { // uniform
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            const typename S::raw *src = fin + (q * rp.N + rp.rb[L::cy[q] + 1][L::cz[q] + 1] - L::cx[q]);
+            r[q] = ld_reg<S>(src + (unsigned)rp.x);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) r[q] = ld_reg<S>(fin + rp.offset(q));
+    }
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) f[q] = from_reg<S, T>(r[q]);
 }
 
 template <class L, class S, class T>

@@ -5,6 +5,10 @@ written by the script beside it, which calls only the oracle).
   velocity U(t) every 10 steps and the final fluid velocity on sampled nodes,
   for FP32 and FP16 storage (bounds: twice the errors measured on MI355X,
   frozen).
+* Many-body sedimentation, 2048x4096, 500 bodies, 4000 steps: the error-growth
+  curve max_i |X_gpu - X_oracle| every 100 steps for FP32, FP16 and BF16
+  storage (bounds: twice the measured maxima); the horizon where the curve
+  reaches 0.1 R, none within 4000 steps so far, is reported.
 * Adjoint workload, 512x1024, 16 disks, 5000 steps, checkpoints every 100:
   the gradient of the mean final height with respect to every rho_s, tau and
   |g| against the oracle's complex-step derivative (indicator sequence frozen,
@@ -55,6 +59,37 @@ def test_disk_settling_20000_steps(storage):
           f"u err {eu:.3e} rel, terminal U {Uo[-1, 1]:.4e}", flush=True)
     bX, bU, bu = SETTLING_BOUNDS[storage]
     assert eX <= bX and eU <= bU and eu <= bu
+
+
+# max over the 40 records of max_i |X - X_oracle| (l.u.): twice the measured curves' maxima
+# (FP32 4.82e-4, FP16 3.56e-3, BF16 8.01e-3 at 4000 steps; the curves grow steadily, no
+# divergence within 4000 steps)
+SED_BOUNDS = {"f32": 9.6e-4, "f16": 7.1e-3, "bf16": 1.6e-2}
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_sedimentation_error_growth(storage):
+    gold = _load("sedimentation_2048x4096")
+    cfg, parts, _, _ = workload("sedimentation_2048x4096")
+    banner(f"sedimentation 2048x4096 {storage} {gold['steps']} steps")
+    sim = lbm.Simulation(cfg, parts, storage=storage, device=0)
+    R = np.array([p["a"] for p in parts])
+    curve = []
+    done = 0
+    for s, Xo in zip(gold["record_steps"], gold["X"]):
+        sim.step(s - done)
+        done = s
+        X = sim.particles()["X"][:, :2]
+        curve.append(float(np.abs(X - np.asarray(Xo)).max()))
+    curve = np.array(curve)
+    steps = np.asarray(gold["record_steps"])
+    over = np.flatnonzero(curve > 0.1 * R.min())
+    horizon = int(steps[over[0]]) if over.size else None
+    print(f"[measured] {storage}: max_i |X - X_oracle| every {gold['every']} steps: "
+          + " ".join(f"{v:.2e}" for v in curve), flush=True)
+    print(f"[measured] {storage}: horizon of 0.1 R: {horizon}", flush=True)
+    assert np.all(np.isfinite(curve))
+    assert curve.max() <= SED_BOUNDS[storage]
 
 
 # FP64: measured 1.3e-13; FP32: measured 2.7e-5 (tau), the stated 1e-4 target
