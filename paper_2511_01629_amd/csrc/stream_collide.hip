@@ -19,10 +19,12 @@
 
 namespace lbm {
 
-// The lattice update, one node per lane.  Each workgroup covers 256
+// The lattice update, one node per lane.  Each workgroup covers BS
 // consecutive nodes of one row (fixed y, z), so the row and the wall tests of
 // y and z are uniform and no index division is needed.  Every population is
-// read once (pull) and written once: 2 Q s bytes per node.
+// read once (pull) and written once: 2 Q s bytes per node.  BS = 256, or 512
+// for D2Q9 in FP64 (measured 3 % faster there; 512 and 1024 were slower in
+// FP32 and FP16).
 //
 // Measured alternatives that did not pay on MI355X: two adjacent nodes per
 // lane (element-aligned 2-wide loads, or aligned loads with a DPP lane shift
@@ -32,15 +34,15 @@ namespace lbm {
 // With slots (the fused-sums step), the solid nodes also add their momentum
 // sums to their particle's slots (keyed wavefront sums, no table lookups) and,
 // on in-place steps, reset their owner entry, which no other lane reads.
-template <class L, class S, class T>
-__global__ __launch_bounds__(256) void k_stream_collide(const typename S::raw *__restrict__ fin,
+template <class L, class S, class T, int BS>
+__global__ __launch_bounds__(BS) void k_stream_collide(const typename S::raw *__restrict__ fin,
                                                          typename S::raw *__restrict__ fout, const uint16_t *owner,
                                                          const T *__restrict__ acc_tab, double *__restrict__ usol,
                                                          int32_t *__restrict__ flags, Geom g, StepParams sp, int gx,
                                                          SlotParams sl)
 {
     const int row = blockIdx.x / gx, bx = blockIdx.x - row * gx; // uniform
-    const int x = bx * 256 + (int)threadIdx.x;
+    const int x = bx * BS + (int)threadIdx.x;
     const bool valid = x < g.nx;
     int y, z;
     if (L::D == 2) {
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(const typename S::raw *_
             // 2-byte storage: the row-uniform offsets (the instruction count
             // limits these kernels; measured 4 % faster in FP16, 8 % in BF16)
             own = owner[idx];
-            const RowPull<L> rp(x, y, z, idx, bx > 0 && bx * 256 + 256 < g.nx, g);
+            const RowPull<L> rp(x, y, z, idx, bx > 0 && bx * BS + BS < g.nx, g);
             pull_row<L, S, T>(fin, rp, f);
         } else {
             // 4- and 8-byte storage, bound by HBM: the per-lane offsets measured
@@ -351,8 +353,6 @@ hipError_t launch_stream_collide(lbm_ctx *c, const void *fin, void *fout)
 {
     const SlotParams sl = slot_params(c, c->fused != 0);
     double *usol = sl.slots ? nullptr : c->usol; // the slots replace the velocity field of the sums
-    const int gx = (c->geo.nx + 255) / 256;
-    const unsigned blocks = (unsigned)gx * (unsigned)(c->geo.ny * c->geo.nz);
     return dispatch(c, [&](auto L, auto S, auto T) {
         using Lt = decltype(L);
         using St = decltype(S);
@@ -376,7 +376,10 @@ hipError_t launch_stream_collide(lbm_ctx *c, const void *fin, void *fout)
                 return staged(std::integral_constant<int, 64>{});
             }
         }
-        return launch(c, k_stream_collide<Lt, St, Tt>, dim3(blocks), dim3(256), (const typename St::raw *)fin,
+        constexpr int BS = (Lt::D == 2 && sizeof(Tt) == 8) ? 512 : 256;
+        const int gx = (c->geo.nx + BS - 1) / BS;
+        const unsigned blocks = (unsigned)gx * (unsigned)(c->geo.ny * c->geo.nz);
+        return launch(c, k_stream_collide<Lt, St, Tt, BS>, dim3(blocks), dim3(BS), (const typename St::raw *)fin,
                       (typename St::raw *)fout, (const uint16_t *)c->owner, acc, usol, c->flags, c->geo, c->sp, gx,
                       sl);
     });
