@@ -480,8 +480,9 @@ int lbm_set_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
         bool ok = axis_ok(g.per_y, g.ny, My) && (d == 2 || axis_ok(g.per_z, g.nz, Mz));
         ok = ok && (!g.per_x || (ext + 63 <= g.nx && (wn % Mx == 0 || Mx >= wn)));
         const int64_t stride = (int64_t)Mx * My * Mz;
-        const size_t need = (size_t)cap * (size_t)stride * ((d == 2 ? 3 : 5) + 2) * sizeof(double);
-        if (ok && stride <= 65536 && need <= ((size_t)1 << 30)) {
+        const size_t need = (size_t)cap * (size_t)stride * slot_width(d) * sizeof(double);
+        const bool coords = g.nx < (1 << 21) && g.ny < (1 << 21) && g.nz < (1 << 21); // packed first nodes
+        if (ok && coords && stride <= 65536 && need <= ((size_t)1 << 30)) {
             if (need > c->slots_bytes) {
                 if (c->slots) HIPCHK(c, hipFree(c->slots));
                 c->slots = nullptr;

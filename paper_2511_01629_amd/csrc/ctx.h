@@ -34,11 +34,16 @@ struct PartDev {
 
 // Per-particle partial momentum sums written by the lattice kernel (the
 // fused-sums step, K = 1): one slot per (particle, lattice row key, wavefront
-// key), each [stamp, lane mask, sums...]; a slot counts for the step whose
-// stamp it carries, so nothing is ever cleared.  Slot s of particle i starts
+// key), each [stamp, lane mask, first node, sums...]; a slot counts for the
+// step whose stamp it carries, so nothing is ever cleared.  Slot s of particle i starts
 // at slots + (i * stride + s) * width.
+// Width of a momentum-sum record in doubles: stamp, lane mask, the packed
+// wrapped coordinates of the wavefront's first node (x0 | y << 21 | z << 42),
+// then the sums (2D 3, 3D 5).
+constexpr int slot_width(int d) { return (d == 2 ? 3 : 5) + 3; }
+
 struct SlotParams {
-    double *slots;      // [np][stride][NV + 2] records: stamp, lane mask, sums
+    double *slots;      // [np][stride][slot_width(d)] records
     int stride;         // slots per particle
     int mx, my, mz;     // wavefront, y and z keys: masks of powers of two
     int sy, sz;         // shifts of the y and z keys

@@ -490,11 +490,11 @@ __global__ __launch_bounds__(BS) void k_rigid_raster(uint16_t *__restrict__ owne
 // ------------------------------------- fused-sums step: Algorithm 1 from slots
 // K = 1 with the momentum sums taken by the lattice kernel (slot_sums): one
 // workgroup per particle i
-//  1. sums its own slots of this step: thread t takes the scan-box rows t,
-//     t + BS, ... and, along each, the wavefronts the box touches; a record
-//     with this step's stamp is shifted to moments about X_i^n (its row and
-//     first node are known), and the workgroup sum (fixed order) gives N_i,
-//     U_i^n, omega_i^n, the record, U_bar_i and dtheta_i;
+//  1. sums its own records of this step: thread t takes the records t,
+//     t + BS, ... of i's table; one with this step's stamp is shifted to
+//     moments about X_i^n by the first node it carries, and the workgroup sum
+//     (fixed order) gives N_i, U_i^n, omega_i^n, the record, U_bar_i and
+//     dtheta_i;
 //  2. lists, in index order, the particles j close enough to interact at X^n
 //     or at the prediction (|X_i - X_j| <= R_i + R_j + delta + 0.6: the
 //     lattice sentinel bounds every node speed by 0.3, hence |U_bar| <= 0.3);
@@ -506,6 +506,24 @@ __global__ __launch_bounds__(BS) void k_rigid_raster(uint16_t *__restrict__ owne
 //  3. closes Algorithm 1 and rasterises the new indicator, as k_rigid_raster.
 // U^{n-1} of every particle is read from P.U, which nothing writes during the
 // launch: U^n goes to P.Unext, and the host swaps the two afterwards.
+
+// Offsets from the centre X of a record's first node (unwrapped: on a
+// periodic axis the image nearest to X, which is the scan box's, since a box
+// reaches at most ceil(R) + 3 nodes from the centre and the set-up keeps that
+// under half a period; in x the wavefront's middle is used, as a wavefront
+// reaches 63 nodes further).
+__device__ __forceinline__ void slot_offsets(double first, const double *X, const Geom &g, double &dx, double &dy,
+                                             double &dz)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(first);
+    int x0 = (int)(b & 0x1FFFFFu), y = (int)((b >> 21) & 0x1FFFFFu), z = (int)(b >> 42);
+    if (g.per_x) x0 -= g.nx * (int)rint(((double)x0 + 31.5 - X[0]) / g.nx);
+    if (g.per_y) y -= g.ny * (int)rint(((double)y - X[1]) / g.ny);
+    if (g.per_z) z -= g.nz * (int)rint(((double)z - X[2]) / g.nz);
+    dx = (double)x0 - X[0];
+    dy = (double)y - X[1];
+    dz = (double)z - X[2];
+}
 
 // Adds the moments about the particle centre of one slot record (see
 // slot_sums) whose first node sits at (X_0 + dx, X_1 + dy, X_2 + dz): 2D
@@ -519,14 +537,14 @@ __device__ __forceinline__ void add_slot(const double *v, double dx, double dy, 
     mask_moments((unsigned long long)__double_as_longlong(v[1]), n, s1, s2);
     const double sxx = s2 + 2.0 * dx * s1 + n * dx * dx; // sum of r_x^2
     if constexpr (D == 2) {
-        const double vx = v[2], vy = v[3], vs = v[4];
+        const double vx = v[3], vy = v[4], vs = v[5];
         c[0] += n;
         c[1] += vx;
         c[2] += vy;
         c[3] += vs + dx * vy - dy * vx;
         c[4] += sxx + n * dy * dy;
     } else {
-        const double vx = v[2], vy = v[3], vz = v[4], vsy = v[5], vsz = v[6];
+        const double vx = v[3], vy = v[4], vz = v[5], vsy = v[6], vsz = v[7];
         const double syy = n * dy * dy, szz = n * dz * dz, sx = s1 + n * dx; // sum of r_x
         c[0] += n;
         c[1] += vx;
@@ -548,7 +566,7 @@ template <int D, int BS>
 __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner, PartDev P, RigidParams rp, Geom g,
                                                     SlotParams sl, double *__restrict__ rec, int32_t *__restrict__ flags)
 {
-    constexpr int NS = NSums<D>::value, W1 = (D == 2 ? 3 : 5) + 2;
+    constexpr int NS = NSums<D>::value, W1 = slot_width(D);
     const int i = blockIdx.x, np = rp.np;
     __shared__ double part[BS / WAVE][NS];
     __shared__ double s_X[3], s_cs, s_sn, s_Ub[3], s_dth;
@@ -568,38 +586,23 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
         Rc = P.a[threadIdx.x];
     }
 
-    // 1. own sums over the scan box the indicator was rasterised with: item t
-    // is the k-th wavefront (k = t mod Mx) of box row t / Mx; every record is
-    // loaded whole, then kept if it carries this step's stamp
+    // 1. own sums: every record of i's table (no dependence on the scan box:
+    // the loads issue with the particle's own), kept if it carries this step's
+    // stamp and shifted to moments about X_i^n by its first node
     double s[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) s[k] = 0.0;
     {
         const double *si = sl.slots + (size_t)i * sl.stride * W1;
-        const int lo0 = P.lo[3 * i], hi0 = P.hi[3 * i], lo1 = P.lo[3 * i + 1], lo2 = P.lo[3 * i + 2];
-        const int e1 = P.hi[3 * i + 1] - lo1 + 1, e2 = P.hi[3 * i + 2] - lo2 + 1;
-        const int rows = e1 > 0 && e2 > 0 ? e1 * e2 : 0;
-        const int lk = __ffs(sl.mx + 1) - 1; // Mx = 2^lk wavefront keys
-        for (int t = threadIdx.x; t < (rows << lk); t += BS) {
-            const int r = t >> lk, k = t & sl.mx;
-            int xu = lo0, w = 0, base = 0;
-            bool found = false;
-            for (int q = 0; q <= k && xu <= hi0; ++q) { // walk to the k-th wavefront
-                const int wx = wrap(xu, g.nx);
-                w = wx >> 6;
-                base = xu - (wx & (WAVE - 1));
-                found = q == k;
-                xu = base + min(WAVE, g.nx - (w << 6));
-            }
-            if (!found) continue; // the box touches fewer than k + 1 wavefronts
-            const int yu = lo1 + r % e1, zu = lo2 + r / e1;
-            const int rkey = ((wrap(zu, g.nz) & sl.mz) << sl.sz) | ((wrap(yu, g.ny) & sl.my) << sl.sy);
-            const double *v = si + (size_t)(rkey | (w & sl.mx)) * W1;
+        for (int t = threadIdx.x; t < sl.stride; t += BS) {
             double rv[W1];
 #pragma unroll
-            for (int m = 0; m < W1; ++m) rv[m] = v[m];
-            if (rv[0] == sl.stamp)
-                add_slot<D>(rv, (double)base - Xi[0], (double)yu - Xi[1], D == 3 ? (double)zu - Xi[2] : 0.0, s);
+            for (int m = 0; m < W1; ++m) rv[m] = si[(size_t)t * W1 + m];
+            if (rv[0] == sl.stamp) {
+                double dx, dy, dz;
+                slot_offsets(rv[2], Xi, g, dx, dy, dz);
+                add_slot<D>(rv, dx, dy, D == 3 ? dz : 0.0, s);
+            }
         }
     }
     block_sum<NS, BS>(s, part);
@@ -698,9 +701,9 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
                 const double *v = sj + (size_t)q * W1;
                 if (v[0] != sl.stamp) continue;
                 u[0] += (double)__popcll((unsigned long long)__double_as_longlong(v[1]));
-                u[1] += v[2];
-                u[2] += v[3];
-                if (D == 3) u[3] += v[4];
+                u[1] += v[3];
+                u[2] += v[4];
+                if (D == 3) u[3] += v[5];
             }
             block_sum<4, BS>(u, reinterpret_cast<double(*)[4]>(&part[0][0]));
             if (threadIdx.x == 0) {

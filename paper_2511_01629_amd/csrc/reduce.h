@@ -196,11 +196,12 @@ __device__ __forceinline__ void mask_moments(unsigned long long m, double &n, do
 // the lattice kernel.  Called by every lane of the wavefront with uniform
 // control flow; `active` lanes hold a solid node (x, y, z) of particle own
 // with velocity u.  For each distinct (particle, slot) key among the lanes,
-// its lowest lane writes the record [stamp, lane mask, sums]: the mask gives
-// the count and the lane offsets s = x mod 64 of the nodes, and the sums are
-// 2D [u_x, u_y, s u_y], 3D [u_x, u_y, u_z, s u_y, s u_z], each a fixed-order
-// wavefront sum.  The particle kernel shifts these to moments about the
-// particle centre, knowing the slot's row and first node.
+// its lowest lane writes the record [stamp, lane mask, first node, sums]: the
+// mask gives the count and the lane offsets s = x mod 64 of the nodes, the
+// first node is the wavefront's (x0 = x - s, y, z) packed into 64 bits, and
+// the sums are 2D [u_x, u_y, s u_y], 3D [u_x, u_y, u_z, s u_y, s u_z], each a
+// fixed-order wavefront sum.  The particle kernel shifts these to moments
+// about the particle centre.
 template <int D>
 __device__ void slot_sums(bool active, uint16_t own, int x, int y, int z, double ux, double uy, double uz,
                           const SlotParams &sl)
@@ -229,11 +230,14 @@ __device__ void slot_sums(bool active, uint16_t own, int x, int y, int z, double
 #pragma unroll
         for (int m = 0; m < NV; ++m) v[m] = wave_sum(v[m]);
         if (lane == leader) {
-            double *out = sl.slots + ((size_t)(k >> 16) * sl.stride + (k & 0xFFFFu)) * (NV + 2);
+            double *out = sl.slots + ((size_t)(k >> 16) * sl.stride + (k & 0xFFFFu)) * slot_width(D);
+            const unsigned long long first =
+                (unsigned long long)(x & ~(WAVE - 1)) | ((unsigned long long)y << 21) | ((unsigned long long)z << 42);
             out[0] = sl.stamp;
             out[1] = __longlong_as_double((long long)mask);
+            out[2] = __longlong_as_double((long long)first);
 #pragma unroll
-            for (int m = 0; m < NV; ++m) out[2 + m] = v[m];
+            for (int m = 0; m < NV; ++m) out[3 + m] = v[m];
         }
         pending &= ~mask;
     }
