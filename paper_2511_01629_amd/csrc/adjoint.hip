@@ -493,13 +493,13 @@ __device__ __forceinline__ void cell_abar(const uint16_t *__restrict__ owner, co
 // Closing for particle i from the totals t: A_bar^n into Abar_out, and the
 // density and |g| partials through a = b_i g + A_i.
 __device__ __forceinline__ void adj_particle_close(const double *t, double rho, const RigidParams &rp, double *Abar_out,
-                                                   double &drho, double &dg)
+                                                   double &drho, double &dg, bool store = true)
 {
     const double bi = rp.gform == 0 ? 1.0 - rp.rho_f / rho : rho / rp.rho_f - 1.0;
     const double dbdrho = rp.gform == 0 ? rp.rho_f / (rho * rho) : 1.0 / rp.rho_f;
     double ag = 0.0, aghat = 0.0;
     for (int k = 0; k < 3; ++k) {
-        Abar_out[k] = t[k];
+        if (store) Abar_out[k] = t[k];
         ag += t[k] * rp.g[k];
         aghat += rp.gmag > 0 ? t[k] * rp.g[k] / rp.gmag : 0.0;
     }
@@ -538,42 +538,55 @@ __global__ __launch_bounds__(256) void k_adj_particles(const uint16_t *__restric
 // Steps with slots: one workgroup per particle j closes the particle adjoint
 // of step n from j's records (A_bar^n_j and its density and |g| partials),
 // then, if rigid, runs the rigid adjoint of step n - 1 for j (A: the arrays of
-// that step).  The partners' A_bar^n, which the rigid adjoint needs through
-// their force adjoints, are summed from their records by the whole
-// workgroup, for the partners in reach only (|X_i - X_j| <= R_i + R_j +
-// delta + 0.6 at X^{n-1}: the prediction moves each body by at most 0.3), in
-// index order; thread 0 accumulates the pair terms.  Abar_n: A_bar^n out.
+// that step).  The partners in reach (|X_i - X_j| <= R_i + R_j + delta + 0.6
+// at X^{n-1}: the prediction moves each body by at most 0.3) are tested by
+// waves 1.., one bit per particle in LDS, while wave 0 sums j's records; after one barrier wave 0 sums each partner's records for its
+// A_bar^n, which the rigid adjoint needs through the partner's force
+// adjoint, in index order; every lane accumulates the same pair terms and
+// lane 0 writes.  Abar_n: A_bar^n out.
 template <int D, int BS>
 __global__ __launch_bounds__(BS) void k_adj_fused(AdjArrays A, PartDev P, RigidParams rp, Geom g, SlotParams sl,
                                                   double *__restrict__ Abar_n, int rigid)
 {
     constexpr int W1 = D + 1;
-    const int j = blockIdx.x, np = rp.np;
-    __shared__ double part[BS / WAVE][3];
-    __shared__ double s_Ab[3];
-    __shared__ int s_list[BS], s_cnt[BS / WAVE];
+    const int j = blockIdx.x, np = rp.np, lane = threadIdx.x & (WAVE - 1);
+    __shared__ unsigned long long s_reach[MAX_NP / WAVE]; // bit i: particle i is in reach
     const double rho = P.rho_s[j], rg0 = A.rho_g[j], gg0 = A.g_g[j];
-    // what the rigid part needs, loaded up front so its latency overlaps the sums
     const double *rj = A.rec + REC_STRIDE * j;
-    double Xbj[3], Upbj[3], Aj[3], Xj[3];
-    for (int k = 0; k < 3; ++k) {
-        Xbj[k] = A.Xbar[3 * j + k];
-        Upbj[k] = A.Upbar[3 * j + k];
-        Aj[k] = rj[10 + k];
-        Xj[k] = rj[k];
+    double Xj[3];
+    for (int k = 0; k < 3; ++k) Xj[k] = rj[k];
+    const double Rj = P.a[j];
+    // the partners in reach at step n - 1 (positions of its record), tested by
+    // waves 1.. while wave 0 sums j's records
+    if (rigid && threadIdx.x >= WAVE) {
+        const int n[3] = {g.nx, g.ny, g.nz};
+        const int per[3] = {g.per_x, g.per_y, g.per_z};
+        for (int i0 = 0; i0 < np; i0 += BS - WAVE) { // uniform
+            const int i = i0 + (int)threadIdx.x - WAVE;
+            bool in = false;
+            if (i < np && i != j) {
+                double dv2 = 0.0;
+                for (int k = 0; k < D; ++k) {
+                    double dk = Xj[k] - A.rec[REC_STRIDE * i + k];
+                    if (per[k]) {
+                        const double h = 0.5 * n[k];
+                        if (dk > h) dk -= n[k];
+                        else if (dk < -h) dk += n[k];
+                    }
+                    dv2 += dk * dk;
+                }
+                const double reach = Rj + P.a[i] + rp.delta + 0.6;
+                in = dv2 <= reach * reach;
+            }
+            const unsigned long long m = __ballot(in);
+            if (lane == 0 && i < np) s_reach[i / WAVE] = m;
+        }
     }
-    const double Nj = rj[13], Rj = P.a[j], V = particle_volume(P.shape[j], P.a[j], P.b[j]);
-    double Xc[3] = {0, 0, 0}, Rc = 0.0; // the first BS candidates of the partner search
-    if ((int)threadIdx.x < np) {
-        for (int k = 0; k < D; ++k) Xc[k] = A.rec[REC_STRIDE * threadIdx.x + k];
-        Rc = P.a[threadIdx.x];
-    }
-
-    // 1. A_bar^n_j from j's records
-    double t[3] = {0, 0, 0};
-    {
+    double t[3] = {0, 0, 0}, drho = 0.0, dg = 0.0;
+    if (threadIdx.x < WAVE) { // wave 0
+        // 1. A_bar^n_j from j's records (every lane ends with the totals)
         const double *sj = sl.slots + (size_t)j * sl.stride * W1;
-        for (int q = threadIdx.x; q < sl.stride; q += BS) {
+        for (int q = lane; q < sl.stride; q += WAVE) {
             double rv[W1];
 #pragma unroll
             for (int m = 0; m < W1; ++m) rv[m] = sj[(size_t)q * W1 + m];
@@ -581,66 +594,38 @@ __global__ __launch_bounds__(BS) void k_adj_fused(AdjArrays A, PartDev P, RigidP
 #pragma unroll
                 for (int m = 0; m < D; ++m) t[m] += rv[1 + m];
         }
-    }
-    block_sum<3, BS>(t, part);
-    double drho = 0.0, dg = 0.0;
-    if (threadIdx.x == 0) {
-        adj_particle_close(t, rho, rp, Abar_n + 3 * j, drho, dg);
-        for (int k = 0; k < 3; ++k) s_Ab[k] = t[k];
-        if (!rigid) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) t[m] = wave_sum(t[m]);
+        adj_particle_close(t, rho, rp, Abar_n + 3 * j, drho, dg, lane == 0);
+        if (!rigid && lane == 0) {
             A.rho_g[j] = rg0 + drho;
             A.g_g[j] = gg0 + dg;
         }
     }
     if (!rigid) return; // uniform
-    __syncthreads();
+    __syncthreads();    // the reach masks are complete
+    if (threadIdx.x >= WAVE) return;
 
-    // 2. the rigid adjoint of step n - 1 for j
+    // 2. the rigid adjoint of step n - 1 for j, by wave 0
+    double Xbj[3], Upbj[3], Aj[3];
+    for (int k = 0; k < 3; ++k) {
+        Xbj[k] = A.Xbar[3 * j + k];
+        Upbj[k] = A.Upbar[3 * j + k];
+        Aj[k] = rj[10 + k];
+    }
+    const double Nj = rj[13], V = particle_volume(P.shape[j], P.a[j], P.b[j]);
     AdjBody bj;
     adj_positions(rj, D, bj);
-    adj_force_bar(Xbj, s_Ab, Nj, rho, D, bj.F);
+    adj_force_bar(Xbj, t, Nj, rho, D, bj.F);
     bj.R = Rj;
     bj.C = P.Cc[j];
-    const int n[3] = {g.nx, g.ny, g.nz};
-    const int per[3] = {g.per_x, g.per_y, g.per_z};
-    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     double acc[2][3] = {{0, 0, 0}, {0, 0, 0}}, unit[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    for (int i0 = 0; i0 < np; i0 += BS) { // uniform
-        const int i = i0 + (int)threadIdx.x;
-        bool in = false;
-        if (i < np && i != j) {
-            if (i0 > 0) {
-                for (int k = 0; k < D; ++k) Xc[k] = A.rec[REC_STRIDE * i + k];
-                Rc = P.a[i];
-            }
-            double dv2 = 0.0;
-            for (int k = 0; k < D; ++k) {
-                double dk = Xj[k] - Xc[k];
-                if (per[k]) {
-                    const double h = 0.5 * n[k];
-                    if (dk > h) dk -= n[k];
-                    else if (dk < -h) dk += n[k];
-                }
-                dv2 += dk * dk;
-            }
-            const double reach = Rj + Rc + rp.delta + 0.6;
-            in = dv2 <= reach * reach;
-        }
-        const unsigned long long m = __ballot(in);
-        if (lane == 0) s_cnt[wv] = __popcll(m);
-        __syncthreads();
-        int off = 0, tot = 0;
-        for (int q = 0; q < BS / WAVE; ++q) {
-            off += q < wv ? s_cnt[q] : 0;
-            tot += s_cnt[q];
-        }
-        if (in) s_list[off + __popcll(m & ((1ull << lane) - 1ull))] = i;
-        __syncthreads();
-        for (int t2 = 0; t2 < tot; ++t2) { // uniform
-            const int ii = s_list[t2];
+    for (int i0 = 0; i0 < np; i0 += WAVE) { // uniform
+        for (unsigned long long m = s_reach[i0 / WAVE]; m; m &= m - 1ull) { // uniform
+            const int ii = i0 + __ffsll((long long)m) - 1;
             const double *si = sl.slots + (size_t)ii * sl.stride * W1;
             double u[3] = {0, 0, 0};
-            for (int q = threadIdx.x; q < sl.stride; q += BS) {
+            for (int q = lane; q < sl.stride; q += WAVE) {
                 double rv[W1];
 #pragma unroll
                 for (int mm = 0; mm < W1; ++mm) rv[mm] = si[(size_t)q * W1 + mm];
@@ -648,22 +633,20 @@ __global__ __launch_bounds__(BS) void k_adj_fused(AdjArrays A, PartDev P, RigidP
 #pragma unroll
                     for (int mm = 0; mm < D; ++mm) u[mm] += rv[1 + mm];
             }
-            block_sum<3, BS>(u, part);
-            if (threadIdx.x == 0) {
-                AdjBody bi;
-                const double *ri = A.rec + REC_STRIDE * ii;
-                adj_positions(ri, D, bi);
-                adj_force_bar(A.Xbar + 3 * ii, u, ri[13], P.rho_s[ii], D, bi.F);
-                bi.R = P.a[ii];
-                bi.C = P.Cc[ii];
-                adj_pair(bj, bi, rp, g, acc, unit);
-            }
-            __syncthreads(); // part is reused
+#pragma unroll
+            for (int mm = 0; mm < 3; ++mm) u[mm] = wave_sum(u[mm]);
+            AdjBody bi;
+            const double *ri = A.rec + REC_STRIDE * ii;
+            adj_positions(ri, D, bi);
+            adj_force_bar(A.Xbar + 3 * ii, u, ri[13], P.rho_s[ii], D, bi.F);
+            bi.R = P.a[ii];
+            bi.C = P.Cc[ii];
+            adj_pair(bj, bi, rp, g, acc, unit);
         }
     }
-    if (threadIdx.x != 0) return;
+    if (lane != 0) return;
     double drho2, dg2;
-    adj_rigid_close(j, A, rp, g, bj, Nj, Aj, rho, V, Xbj, s_Ab, Upbj, acc, unit, drho2, dg2);
+    adj_rigid_close(j, A, rp, g, bj, Nj, Aj, rho, V, Xbj, t, Upbj, acc, unit, drho2, dg2);
     A.rho_g[j] = (rg0 + drho) + drho2;
     A.g_g[j] = (gg0 + dg) + dg2;
 }

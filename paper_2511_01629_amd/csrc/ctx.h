@@ -37,6 +37,10 @@ struct PartDev {
 // key), each [stamp, lane mask, first node, sums...]; a slot counts for the
 // step whose stamp it carries, so nothing is ever cleared.  Slot s of particle i starts
 // at slots + (i * stride + s) * width.
+// Bound on the particle count (the owner map is 16-bit, FLUID reserved); the
+// fused particle kernels keep one reach bit per particle in LDS.
+constexpr int MAX_NP = 65536;
+
 // Width of a momentum-sum record in doubles: stamp, lane mask, the packed
 // wrapped coordinates of the wavefront's first node (x0 | y << 21 | z << 42),
 // then the sums (2D 3, 3D 5).

@@ -490,20 +490,22 @@ __global__ __launch_bounds__(BS) void k_rigid_raster(uint16_t *__restrict__ owne
 // ------------------------------------- fused-sums step: Algorithm 1 from slots
 // K = 1 with the momentum sums taken by the lattice kernel (slot_sums): one
 // workgroup per particle i
-//  1. sums its own records of this step: thread t takes the records t,
-//     t + BS, ... of i's table; one with this step's stamp is shifted to
-//     moments about X_i^n by the first node it carries, and the workgroup sum
-//     (fixed order) gives N_i, U_i^n, omega_i^n, the record, U_bar_i and
-//     dtheta_i;
-//  2. lists, in index order, the particles j close enough to interact at X^n
-//     or at the prediction (|X_i - X_j| <= R_i + R_j + delta + 0.6: the
-//     lattice sentinel bounds every node speed by 0.3, hence |U_bar| <= 0.3);
-//     for each, the workgroup sums the count and velocity of all of j's
-//     records with this step's stamp (j's box is not needed, which is as well:
-//     j's own workgroup is replacing it) to get U_j^n and
-//     U_bar_j = (U_j^n + U_j^{n-1})/2, and thread 0 adds the pair forces at X^n
-//     and at the prediction;
-//  3. closes Algorithm 1 and rasterises the new indicator, as k_rigid_raster.
+//  0. waves 1.. test which particles j are close enough to
+//     interact at X^n or at the prediction (|X_i - X_j| <= R_i + R_j +
+//     delta + 0.6: the lattice sentinel bounds every node speed by 0.3, hence
+//     |U_bar| <= 0.3), one bit per j in LDS;
+//  1. meanwhile its first wavefront sums i's records of this step: lane l
+//     takes the records l, l + 64, ... of i's table; one with this step's
+//     stamp is shifted to moments about X_i^n by the first node it carries,
+//     and the wavefront sum (fixed order) gives N_i, U_i^n, omega_i^n, the
+//     record, U_bar_i and dtheta_i on every lane;
+//  2. after a barrier the same wavefront visits the particles in reach in
+//     index order, sums the count and velocity of j's records of this step
+//     (j's box is not needed, which is as well: j's own workgroup is replacing
+//     it) for U_j^n and U_bar_j = (U_j^n + U_j^{n-1})/2, and adds the pair
+//     forces at X^n and at the prediction;
+//  3. lane 0 closes Algorithm 1; after a second barrier the whole workgroup
+//     rasterises the new indicator, as k_rigid_raster.
 // U^{n-1} of every particle is read from P.U, which nothing writes during the
 // launch: U^n goes to P.Unext, and the host swaps the two afterwards.
 
@@ -568,33 +570,60 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
 {
     constexpr int NS = NSums<D>::value, W1 = slot_width(D);
     const int i = blockIdx.x, np = rp.np;
-    __shared__ double part[BS / WAVE][NS];
-    __shared__ double s_X[3], s_cs, s_sn, s_Ub[3], s_dth;
-    __shared__ int s_lo[3], s_hi[3], s_N;
-    __shared__ int s_list[BS], s_cnt[BS / WAVE];
-    const double Ri = P.a[i], Ci = P.Cc[i], rho = P.rho_s[i], theta = P.theta[i], bi = P.b[i];
+    __shared__ double s_X[3], s_cs, s_sn;
+    __shared__ int s_lo[3], s_hi[3];
+    __shared__ unsigned long long s_reach[MAX_NP / WAVE]; // bit j: particle j is in reach
+    const double Ri = P.a[i], bi = P.b[i];
     const int shape = P.shape[i];
+    // the particles close enough to interact with i at X^n or at the
+    // prediction (|X_i - X_j| <= R_i + R_j + delta + 0.6: the lattice sentinel
+    // bounds every node speed by 0.3, hence |U_bar| <= 0.3), tested by waves
+    // 1.. while wave 0 sums i's records
+    if (threadIdx.x >= WAVE) {
+        const int n[3] = {g.nx, g.ny, g.nz};
+        const int per[3] = {g.per_x, g.per_y, g.per_z};
+        double Xo[3];
+        for (int k = 0; k < 3; ++k) Xo[k] = P.X[3 * i + k];
+        for (int j0 = 0; j0 < np; j0 += BS - WAVE) { // uniform
+            const int j = j0 + (int)threadIdx.x - WAVE;
+            bool in = false;
+            if (j < np && j != i) {
+                double dv2 = 0.0;
+                for (int k = 0; k < D; ++k) {
+                    double dk = Xo[k] - P.X[3 * j + k];
+                    if (per[k]) {
+                        const double h = 0.5 * n[k];
+                        if (dk > h) dk -= n[k];
+                        else if (dk < -h) dk += n[k];
+                    }
+                    dv2 += dk * dk;
+                }
+                const double reach = Ri + P.a[j] + rp.delta + 0.6;
+                in = dv2 <= reach * reach;
+            }
+            const unsigned long long m = __ballot(in);
+            if ((threadIdx.x & (WAVE - 1)) == 0 && j < np) s_reach[j / WAVE] = m;
+        }
+    }
+    const int lane = threadIdx.x & (WAVE - 1);
+    const double Ci = P.Cc[i], rho = P.rho_s[i], theta = P.theta[i];
     double Xi[3];
     for (int k = 0; k < 3; ++k) Xi[k] = P.X[3 * i + k];
     PrevState ps = load_prev(P, i);
     for (int k = 0; k < 3; ++k) ps.Uprev[k] = P.U[3 * i + k]; // U^{n-1}
+    int cnt = 0;
+    double dth = 0.0, Ub[3] = {0, 0, 0};
+    if (threadIdx.x < WAVE) { // wave 0
 
-    // the first BS candidates of step 2, loaded now rather than after the sums
-    double Xc[3] = {0, 0, 0}, Rc = 0.0;
-    if ((int)threadIdx.x < np) {
-        for (int k = 0; k < D; ++k) Xc[k] = P.X[3 * threadIdx.x + k];
-        Rc = P.a[threadIdx.x];
-    }
-
-    // 1. own sums: every record of i's table (no dependence on the scan box:
-    // the loads issue with the particle's own), kept if it carries this step's
-    // stamp and shifted to moments about X_i^n by its first node
-    double s[NS];
+        // 1. own sums: every record of i's table (no dependence on the scan
+        // box: the loads issue with the particle's own), kept if it carries
+        // this step's stamp and shifted to moments about X_i^n by its first
+        // node; every lane ends with the same totals
+        double s[NS];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) s[k] = 0.0;
-    {
+        for (int k = 0; k < NS; ++k) s[k] = 0.0;
         const double *si = sl.slots + (size_t)i * sl.stride * W1;
-        for (int t = threadIdx.x; t < sl.stride; t += BS) {
+        for (int t = lane; t < sl.stride; t += WAVE) {
             double rv[W1];
 #pragma unroll
             for (int m = 0; m < W1; ++m) rv[m] = si[(size_t)t * W1 + m];
@@ -604,11 +633,9 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
                 add_slot<D>(rv, dx, dy, D == 3 ? dz : 0.0, s);
             }
         }
-    }
-    block_sum<NS, BS>(s, part);
-    if (threadIdx.x == 0) {
-        const int cnt = (int)s[0];
-        P.N[i] = cnt;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) s[k] = wave_sum(s[k]);
+        cnt = (int)s[0];
         double U[3] = {0, 0, 0}, W[3] = {0, 0, 0};
         if (cnt > 0) {
             if constexpr (D == 2) {
@@ -629,84 +656,58 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
                 W[2] = (A02 * L0 + A12 * L1 + A22 * L2) / det;
             }
         }
-        if (rec) {
-            double *r = rec + REC_STRIDE * i;
-            for (int k = 0; k < 3; ++k) {
-                r[k] = ps.X[k];
-                r[4 + k] = U[k];
-                r[7 + k] = W[k];
-                r[10 + k] = ps.A[k];
-                r[14 + k] = ps.Uprev[k];
-            }
-            r[3] = ps.theta;
-            r[13] = (double)cnt;
-        }
-        s_dth = 0.5 * (W[2] + ps.Wprev[2]);
-        P.dth[i] = s_dth;
-        for (int k = 0; k < 3; ++k) {
-            s_Ub[k] = 0.5 * (U[k] + ps.Uprev[k]);
-            P.Ub[3 * i + k] = s_Ub[k];
-            P.Unext[3 * i + k] = U[k];
-            P.W[3 * i + k] = W[k];
-            P.Wprev[3 * i + k] = W[k];
-        }
-        s_N = cnt;
-    }
-    __syncthreads();
-
-    // 2. pair forces with the particles in reach (thread 0 accumulates, in
-    // index order)
-    double Yi[3];
-    for (int k = 0; k < 3; ++k) Yi[k] = Xi[k] + (k < D ? s_Ub[k] : 0.0);
-    const int n[3] = {g.nx, g.ny, g.nz};
-    const int per[3] = {g.per_x, g.per_y, g.per_z};
-    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-    double F[6] = {0, 0, 0, 0, 0, 0};
-    for (int j0 = 0; j0 < np; j0 += BS) { // uniform
-        const int j = j0 + (int)threadIdx.x;
-        bool in = false;
-        if (j < np && j != i) {
-            if (j0 > 0) {
-                for (int k = 0; k < D; ++k) Xc[k] = P.X[3 * j + k];
-                Rc = P.a[j];
-            }
-            double dv2 = 0.0;
-            for (int k = 0; k < D; ++k) {
-                double dk = Xi[k] - Xc[k];
-                if (per[k]) {
-                    const double h = 0.5 * n[k];
-                    if (dk > h) dk -= n[k];
-                    else if (dk < -h) dk += n[k];
+        dth = 0.5 * (W[2] + ps.Wprev[2]);
+        for (int k = 0; k < 3; ++k) Ub[k] = 0.5 * (U[k] + ps.Uprev[k]);
+        if (lane == 0) {
+            P.N[i] = cnt;
+            if (rec) {
+                double *r = rec + REC_STRIDE * i;
+                for (int k = 0; k < 3; ++k) {
+                    r[k] = ps.X[k];
+                    r[4 + k] = U[k];
+                    r[7 + k] = W[k];
+                    r[10 + k] = ps.A[k];
+                    r[14 + k] = ps.Uprev[k];
                 }
-                dv2 += dk * dk;
+                r[3] = ps.theta;
+                r[13] = (double)cnt;
             }
-            const double reach = Ri + Rc + rp.delta + 0.6;
-            in = dv2 <= reach * reach;
-        }
-        const unsigned long long m = __ballot(in);
-        if (lane == 0) s_cnt[wv] = __popcll(m);
-        __syncthreads();
-        int off = 0, tot = 0;
-        for (int q = 0; q < BS / WAVE; ++q) {
-            off += q < wv ? s_cnt[q] : 0;
-            tot += s_cnt[q];
-        }
-        if (in) s_list[off + __popcll(m & ((1ull << lane) - 1ull))] = j;
-        __syncthreads();
-        for (int t = 0; t < tot; ++t) { // uniform
-            const int jj = s_list[t];
-            const double *sj = sl.slots + (size_t)jj * sl.stride * W1;
-            double u[4] = {0, 0, 0, 0};
-            for (int q = threadIdx.x; q < sl.stride; q += BS) {
-                const double *v = sj + (size_t)q * W1;
-                if (v[0] != sl.stamp) continue;
-                u[0] += (double)__popcll((unsigned long long)__double_as_longlong(v[1]));
-                u[1] += v[3];
-                u[2] += v[4];
-                if (D == 3) u[3] += v[5];
+            P.dth[i] = dth;
+            for (int k = 0; k < 3; ++k) {
+                P.Ub[3 * i + k] = Ub[k];
+                P.Unext[3 * i + k] = U[k];
+                P.W[3 * i + k] = W[k];
+                P.Wprev[3 * i + k] = W[k];
             }
-            block_sum<4, BS>(u, reinterpret_cast<double(*)[4]>(&part[0][0]));
-            if (threadIdx.x == 0) {
+        }
+
+    }
+    __syncthreads(); // the reach masks are complete
+    if (threadIdx.x < WAVE) { // wave 0
+        // 2. pair forces with the particles in reach, in index order; the
+        // wavefront sums each partner's records for U_j^n, every lane adds
+        // the same forces
+        double Yi[3];
+        for (int k = 0; k < 3; ++k) Yi[k] = Xi[k] + (k < D ? Ub[k] : 0.0);
+        double F[6] = {0, 0, 0, 0, 0, 0};
+        for (int j0 = 0; j0 < np; j0 += WAVE) { // uniform
+            for (unsigned long long m = s_reach[j0 / WAVE]; m; m &= m - 1ull) { // uniform
+                const int jj = j0 + __ffsll((long long)m) - 1;
+                const double *sj = sl.slots + (size_t)jj * sl.stride * W1;
+                double u[4] = {0, 0, 0, 0};
+                for (int t = lane; t < sl.stride; t += WAVE) {
+                    double rv[W1];
+#pragma unroll
+                    for (int mm = 0; mm < W1; ++mm) rv[mm] = sj[(size_t)t * W1 + mm];
+                    if (rv[0] == sl.stamp) {
+                        u[0] += (double)__popcll((unsigned long long)__double_as_longlong(rv[1]));
+                        u[1] += rv[3];
+                        u[2] += rv[4];
+                        if (D == 3) u[3] += rv[5];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) u[k] = wave_sum(u[k]);
                 double Xj[3], Yj[3];
                 for (int k = 0; k < 3; ++k) {
                     Xj[k] = P.X[3 * jj + k];
@@ -717,32 +718,31 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
                 pair_force(Xi, Xj, Ri, Rj, Ci, rp, g, F);
                 pair_force(Yi, Yj, Ri, Rj, Ci, rp, g, F + 3);
             }
-            __syncthreads(); // part is reused
         }
-    }
 
-    // 3. close Algorithm 1, then the new indicator
-    if (threadIdx.x == 0) {
-        wall_force(Xi, Ri, Ci, rp, g, F);
-        wall_force(Yi, Ri, Ci, rp, g, F + 3);
-        const int cnt = s_N;
-        const double M = rho * (double)cnt;
-        const double c = M > 0.0 ? 1.0 / (2.0 * M) : 0.0;
-        double Y[3], Dc[3];
-        for (int k = 0; k < 3; ++k) {
-            Dc[k] = k < D ? c * (F[k] + F[3 + k]) / 2.0 : 0.0;
-            Y[k] = Yi[k] + Dc[k];
-        }
-        const double th = close_rigid(P, rp, g, i, Y, Dc, cnt, rho, theta, s_dth, flags, s_X);
-        s_cs = shape == LBM_ELLIPSE ? cos(th) : 1.0;
-        s_sn = shape == LBM_ELLIPSE ? sin(th) : 0.0;
-        centre_box(s_X, Ri, g, D, s_lo, s_hi);
-        for (int k = 0; k < 3; ++k) {
-            P.lo[3 * i + k] = s_lo[k];
-            P.hi[3 * i + k] = s_hi[k];
+        // 3. close Algorithm 1
+        if (lane == 0) {
+            wall_force(Xi, Ri, Ci, rp, g, F);
+            wall_force(Yi, Ri, Ci, rp, g, F + 3);
+            const double M = rho * (double)cnt;
+            const double c = M > 0.0 ? 1.0 / (2.0 * M) : 0.0;
+            double Y[3], Dc[3];
+            for (int k = 0; k < 3; ++k) {
+                Dc[k] = k < D ? c * (F[k] + F[3 + k]) / 2.0 : 0.0;
+                Y[k] = Yi[k] + Dc[k];
+            }
+            const double th = close_rigid(P, rp, g, i, Y, Dc, cnt, rho, theta, dth, flags, s_X);
+            s_cs = shape == LBM_ELLIPSE ? cos(th) : 1.0;
+            s_sn = shape == LBM_ELLIPSE ? sin(th) : 0.0;
+            centre_box(s_X, Ri, g, D, s_lo, s_hi);
+            for (int k = 0; k < 3; ++k) {
+                P.lo[3 * i + k] = s_lo[k];
+                P.hi[3 * i + k] = s_hi[k];
+            }
         }
     }
     __syncthreads();
+    // then the new indicator, by the whole workgroup
     raster_items<UNR>(owner, g, D, i, s_X, shape, Ri, bi, s_cs, s_sn, s_lo, s_hi, threadIdx.x, BS);
 }
 
