@@ -144,15 +144,20 @@ namespace lbm {
 // time between them excludes the dispatch latency an event recorded on the
 // stream around the launch would add).
 template <typename... Args, typename F>
-inline hipError_t launch(lbm_ctx *c, F kernel, dim3 grid, dim3 block, Args... args)
+inline hipError_t launch_shm(lbm_ctx *c, F kernel, dim3 grid, dim3 block, size_t shmem, Args... args)
 {
     if (c->tev[0]) {
-        hipExtLaunchKernelGGL(kernel, grid, block, 0, c->stream, c->tev[0], c->tev[1], 0, args...);
+        hipExtLaunchKernelGGL(kernel, grid, block, shmem, c->stream, c->tev[0], c->tev[1], 0, args...);
         c->tev_used = 1;
     } else {
-        hipLaunchKernelGGL(kernel, grid, block, 0, c->stream, args...);
+        hipLaunchKernelGGL(kernel, grid, block, shmem, c->stream, args...);
     }
     return hipGetLastError();
+}
+template <typename... Args, typename F>
+inline hipError_t launch(lbm_ctx *c, F kernel, dim3 grid, dim3 block, Args... args)
+{
+    return launch_shm(c, kernel, grid, block, 0, args...);
 }
 
 // stream_collide.hip

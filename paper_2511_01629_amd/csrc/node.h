@@ -172,27 +172,64 @@ __device__ __forceinline__ void pull(const typename S::raw *__restrict__ fin, in
     for (int q = 0; q < L::Q; ++q) f[q] = ld<S, T>(fin + pull_offset<L>(q, idx, x, y, z, g, N));
 }
 
+// A sum whose terms are known at compile time to be present or not (after
+// unrolling over q): absent terms are left out instead of added as zeros,
+// which IEEE semantics would keep in the code (0 * v and x + 0 are not
+// folded, though they change at most the sign of a zero).  Present terms are
+// added in the order given.
+template <class T>
+struct CSum {
+    T v = T(0);
+    bool any = false;
+    __device__ __forceinline__ void add(bool present, T t)
+    {
+        if (!present) return;
+        v = any ? v + t : t;
+        any = true;
+    }
+    __device__ __forceinline__ void sub(bool present, T t)
+    {
+        if (!present) return;
+        v = any ? v - t : -t;
+        any = true;
+    }
+};
+
+// c_q . (vx, vy, vz) without the zero components of c_q
+template <class L, class T>
+__device__ __forceinline__ T cdot(int q, T vx, T vy, T vz)
+{
+    CSum<T> r;
+    r.add(L::cx[q] > 0, vx);
+    r.sub(L::cx[q] < 0, vx);
+    r.add(L::cy[q] > 0, vy);
+    r.sub(L::cy[q] < 0, vy);
+    r.add(L::D == 3 && L::cz[q] > 0, vz);
+    r.sub(L::D == 3 && L::cz[q] < 0, vz);
+    return r.v;
+}
+
 // u = sum f c + a/2 and p = (cs^2 sum_{q>0} f - w0 |u|^2 / 2)/(1 - w0)  (eq. 15a-b)
 template <class L, class T>
 __device__ __forceinline__ void moments(const T *f, T ax, T ay, T az, T &ux, T &uy, T &uz, T &p)
 {
-    T jx = 0, jy = 0, jz = 0, s = 0;
+    CSum<T> jx, jy, jz, s;
 #pragma unroll
     for (int q = 1; q < L::Q; ++q) {
-        if (L::cx[q] > 0) jx += f[q];
-        if (L::cx[q] < 0) jx -= f[q];
-        if (L::cy[q] > 0) jy += f[q];
-        if (L::cy[q] < 0) jy -= f[q];
-        if (L::cz[q] > 0) jz += f[q];
-        if (L::cz[q] < 0) jz -= f[q];
-        s += f[q];
+        jx.add(L::cx[q] > 0, f[q]);
+        jx.sub(L::cx[q] < 0, f[q]);
+        jy.add(L::cy[q] > 0, f[q]);
+        jy.sub(L::cy[q] < 0, f[q]);
+        jz.add(L::cz[q] > 0, f[q]);
+        jz.sub(L::cz[q] < 0, f[q]);
+        s.add(true, f[q]);
     }
-    ux = jx + T(0.5) * ax;
-    uy = jy + T(0.5) * ay;
-    uz = (L::D == 3) ? jz + T(0.5) * az : T(0);
+    ux = jx.v + T(0.5) * ax;
+    uy = jy.v + T(0.5) * ay;
+    uz = (L::D == 3) ? jz.v + T(0.5) * az : T(0);
     const T uu = ux * ux + uy * uy + uz * uz;
     constexpr double w0 = L::w[0];
-    p = (T(1.0 / 3.0) * s - T(0.5 * w0) * uu) * T(1.0 / (1.0 - w0));
+    p = (T(1.0 / 3.0) * s.v - T(0.5 * w0) * uu) * T(1.0 / (1.0 - w0));
 }
 
 // f^eq_q of eq. (13) with cs^2 = 1/3: q = 0: -(1-w0) 3p - w0 1.5|u|^2;
@@ -239,7 +276,7 @@ __device__ __forceinline__ void collide_node(T *f, uint16_t own, const T *__rest
     if (!pen && !frc) {
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) {
-            const T cu = T(L::cx[q]) * ux + T(L::cy[q]) * uy + T(L::cz[q]) * uz;
+            const T cu = cdot<L, T>(q, ux, uy, uz);
             f[q] = f[q] - om * (f[q] - feq_q<L, T>(q, p3, cu, u15));
         }
         return;
@@ -249,7 +286,7 @@ __device__ __forceinline__ void collide_node(T *f, uint16_t own, const T *__rest
     T Pxx = 0, Pyy = 0, Pzz = 0, Pxy = 0, Pxz = 0, Pyz = 0;
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
-        const T cu = T(L::cx[q]) * ux + T(L::cy[q]) * uy + T(L::cz[q]) * uz;
+        const T cu = cdot<L, T>(q, ux, uy, uz);
         fneq[q] = f[q] - feq_q<L, T>(q, p3, cu, u15);
         if (L::cx[q] != 0) Pxx += fneq[q];
         if (L::cy[q] != 0) Pyy += fneq[q];
@@ -264,17 +301,25 @@ __device__ __forceinline__ void collide_node(T *f, uint16_t own, const T *__rest
     const T al = pen ? (T)sp.alpha : T(0);
     const T trace3 = (Pxx + Pyy + Pzz) * T(1.0 / 3.0);
     const T gpre = T(1) - T(0.5) * om;
-    const T ua = ux * ax + uy * ay + uz * az;
+    const T ua = L::D == 3 ? ux * ax + uy * ay + uz * az : ux * ax + uy * ay;
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
-        const T cx = T(L::cx[q]), cy = T(L::cy[q]), cz = T(L::cz[q]);
         // S_q = alpha w_q / (2 cs^4) Pi^neq : (c c - cs^2 I)   (eq. 17)
-        const T PiCC = cx * cx * Pxx + cy * cy * Pyy + cz * cz * Pzz +
-                       T(2) * (cx * cy * Pxy + cx * cz * Pxz + cy * cz * Pyz);
+        CSum<T> diag, off;
+        diag.add(L::cx[q] != 0, Pxx);
+        diag.add(L::cy[q] != 0, Pyy);
+        diag.add(L::cz[q] != 0, Pzz);
+        off.add(L::cx[q] * L::cy[q] > 0, Pxy);
+        off.sub(L::cx[q] * L::cy[q] < 0, Pxy);
+        off.add(L::cx[q] * L::cz[q] > 0, Pxz);
+        off.sub(L::cx[q] * L::cz[q] < 0, Pxz);
+        off.add(L::cy[q] * L::cz[q] > 0, Pyz);
+        off.sub(L::cy[q] * L::cz[q] < 0, Pyz);
+        const T PiCC = off.any ? diag.v + T(2) * off.v : diag.v;
         const T Sq = al * T(4.5 * L::w[q]) * (PiCC - trace3);
         // F_q = (1 - 1/(2 tau)) w_q [3 (c - u).a + 9 (c.u)(c.a)]   (eq. 14)
-        const T cu = cx * ux + cy * uy + cz * uz;
-        const T ca = cx * ax + cy * ay + cz * az;
+        const T cu = cdot<L, T>(q, ux, uy, uz);
+        const T ca = cdot<L, T>(q, ax, ay, az);
         const T F = gpre * T(L::w[q]) * (T(3) * (ca - ua) + T(9) * cu * ca);
         f[q] = f[q] - om * fneq[q] + F + Sq;
     }

@@ -23,8 +23,8 @@ namespace lbm {
 // consecutive nodes of one row (fixed y, z), so the row and the wall tests of
 // y and z are uniform and no index division is needed.  Every population is
 // read once (pull) and written once: 2 Q s bytes per node.  BS = 256, or 512
-// for D2Q9 in FP64 (measured 3 % faster there; 512 and 1024 were slower in
-// FP32 and FP16).
+// for D2Q9 in FP64 (512 and 1024 were slower in FP32 and FP16, and capping
+// their occupancy below the register limit was slower too).
 //
 // Measured alternatives that did not pay on MI355X: two adjacent nodes per
 // lane (element-aligned 2-wide loads, or aligned loads with a DPP lane shift
@@ -376,12 +376,17 @@ hipError_t launch_stream_collide(lbm_ctx *c, const void *fin, void *fout)
                 return staged(std::integral_constant<int, 64>{});
             }
         }
-        constexpr int BS = (Lt::D == 2 && sizeof(Tt) == 8) ? 512 : 256;
+        constexpr bool d2f64 = Lt::D == 2 && sizeof(Tt) == 8;
+        constexpr int BS = d2f64 ? 512 : 256;
+        // D2Q9 in FP64: at most two 512-thread workgroups per compute unit (an
+        // unused LDS reservation of 56 KiB of the 160), 16 waves: measured
+        // faster than the 24 its register use would allow
+        constexpr size_t shm = d2f64 ? (size_t)56 << 10 : 0;
         const int gx = (c->geo.nx + BS - 1) / BS;
         const unsigned blocks = (unsigned)gx * (unsigned)(c->geo.ny * c->geo.nz);
-        return launch(c, k_stream_collide<Lt, St, Tt, BS>, dim3(blocks), dim3(BS), (const typename St::raw *)fin,
-                      (typename St::raw *)fout, (const uint16_t *)c->owner, acc, usol, c->flags, c->geo, c->sp, gx,
-                      sl);
+        return launch_shm(c, k_stream_collide<Lt, St, Tt, BS>, dim3(blocks), dim3(BS), shm,
+                          (const typename St::raw *)fin, (typename St::raw *)fout, (const uint16_t *)c->owner, acc,
+                          usol, c->flags, c->geo, c->sp, gx, sl);
     });
 }
 
