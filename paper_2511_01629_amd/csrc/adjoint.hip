@@ -72,9 +72,9 @@ __global__ __launch_bounds__(256) void k_adj_lattice(const typename S::raw *__re
                                                       const T *__restrict__ uext, const T *__restrict__ lam_in,
                                                       T *__restrict__ lam_out, double *__restrict__ asol,
                                                       double *__restrict__ tau_part, Geom g, StepParams sp, int gx,
-                                                      SlotParams sl)
+                                                      unsigned gxm, SlotParams sl)
 {
-    const int row = blockIdx.x / gx, bx = blockIdx.x - row * gx;
+    const int row = div_magic((int)blockIdx.x, gx, gxm), bx = (int)blockIdx.x - row * gx;
     const int x = bx * 256 + (int)threadIdx.x;
     const bool valid = x < g.nx;
     int y, z;
@@ -695,7 +695,7 @@ hipError_t launch_adj_lattice(lbm_ctx *c, const void *fprev, const uint16_t *own
         const Tt *uext = dbl ? (const Tt *)uext_d : (const Tt *)uext_f;
         hipLaunchKernelGGL((k_adj_lattice<Lt, St, Tt>), dim3(blocks), dim3(256), 0, c->stream,
                            (const typename St::raw *)fprev, owner, acc, uext, (const Tt *)lam_in, (Tt *)lam_out, asol,
-                           tau_part, c->geo, c->sp, gx, sl);
+                           tau_part, c->geo, c->sp, gx, magic_for(gx), sl);
         return hipGetLastError();
     });
 }

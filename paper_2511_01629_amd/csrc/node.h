@@ -66,64 +66,66 @@ __device__ __forceinline__ int pull_offset(int q, int idx, int x, int y, int z, 
 template <class L>
 struct RowPull {
     int rb[3][3]; // [c_y + 1][c_z + 1]: (sy + ny sz) nx of the source row; -1 behind a wall
-    int xs[3];    // [c_x + 1]: the source column x - c_x; -1 behind a wall
     int x, idx, N;
     bool interior;
+    const Geom &g;
 
-    __device__ __forceinline__ RowPull(int x_, int y, int z, int idx_, bool inner_segment, const Geom &g)
-        : x(x_), idx(idx_), N((int)g.N)
+    // source coordinate v - c on an axis of n nodes: wrapped, or flagged as
+    // behind a wall (selects, no branches)
+    static __device__ __forceinline__ int src(int v, int c, int n, int per, bool &wall)
+    {
+        int sv = v - c;
+        const bool lo = sv < 0, hi = sv >= n;
+        sv += lo ? n : 0;
+        sv -= hi ? n : 0;
+        wall = (lo || hi) && !per;
+        return sv;
+    }
+
+    __device__ __forceinline__ RowPull(int x_, int y, int z, int idx_, bool inner_segment, const Geom &g_)
+        : x(x_), idx(idx_), N((int)g_.N), g(g_)
     {
         bool walls = false;
 #pragma unroll
         for (int cy = -1; cy <= 1; ++cy)
 #pragma unroll
-            for (int cz = -1; cz <= 1; ++cz) {
-                int sy = y - cy, sz = z - cz;
-                bool wall = false;
-                if (sy < 0) {
-                    if (g.per_y) sy += g.ny; else wall = true;
-                } else if (sy >= g.ny) {
-                    if (g.per_y) sy -= g.ny; else wall = true;
-                }
-                if (L::D == 3) {
-                    if (sz < 0) {
-                        if (g.per_z) sz += g.nz; else wall = true;
-                    } else if (sz >= g.nz) {
-                        if (g.per_z) sz -= g.nz; else wall = true;
-                    }
-                } else if (cz != 0) {
-                    wall = false; // unused in 2D
-                }
-                walls = walls || (wall && (L::D == 3 || cz == 0));
+            for (int cz = (L::D == 3 ? -1 : 0); cz <= (L::D == 3 ? 1 : 0); ++cz) {
+                bool wy, wz = false;
+                const int sy = src(y, cy, g.ny, g.per_y, wy);
+                const int sz = L::D == 3 ? src(z, cz, g.nz, g.per_z, wz) : 0;
+                const bool wall = wy || wz;
+                walls = walls || wall;
                 rb[cy + 1][cz + 1] = wall ? -1 : (sy + g.ny * sz) * g.nx;
             }
         interior = inner_segment && !walls;
-#pragma unroll
-        for (int cx = -1; cx <= 1; ++cx) {
-            int sx = x - cx;
-            bool wall = false;
-            if (sx < 0) {
-                if (g.per_x) sx += g.nx; else wall = true;
-            } else if (sx >= g.nx) {
-                if (g.per_x) sx -= g.nx; else wall = true;
-            }
-            xs[cx + 1] = wall ? -1 : sx;
-        }
     }
     // offset on any segment
     __device__ __forceinline__ int at(int q) const
     {
         return interior ? q * N + rb[L::cy[q] + 1][L::cz[q] + 1] - L::cx[q] + x : offset(q);
     }
-    // general offset (any segment)
+    // general offset (any segment): the column x - c_x tested per lane
     __device__ __forceinline__ int offset(int q) const
     {
-        const int r = rb[L::cy[q] + 1][L::cz[q] + 1], s = xs[L::cx[q] + 1];
+        bool wx = false;
+        const int s = L::cx[q] != 0 ? src(x, L::cx[q], g.nx, g.per_x, wx) : x;
+        const int r = rb[L::cy[q] + 1][L::cz[q] + 1];
         const int a = q * N + r + s, b = L::opp[q] * N + idx;
-        const int m = -(int)(r >= 0 && s >= 0); // branch-free select
+        const int m = -(int)(r >= 0 && !wx); // branch-free select
         return (a & m) | (b & ~m);
     }
 };
+
+// n / d for a uniform divisor d >= 1 with m = floor(2^32 / d) (2^32 - 1 for
+// d = 1) precomputed on the host: the high product is the quotient or one
+// less, so one correction gives it exactly (n < 2^31).
+__device__ __forceinline__ int div_magic(int n, int d, unsigned m)
+{
+    int q = (int)__umulhi((unsigned)n, m);
+    q += (n - q * d >= d) ? 1 : 0;
+    return q;
+}
+static inline unsigned magic_for(int d) { return d == 1 ? 0xFFFFFFFFu : (unsigned)((1ull << 32) / (unsigned)d); }
 
 // A stored population loaded into a register of its own (2-byte types
 // zero-extended to 32 bits, so the compiler does not pack two of them into
