@@ -67,6 +67,68 @@ def test_fluid_step_random_state_f32_3d(n, periodic):
         assert e < 5e-6, e
 
 
+def _round_storage(f, storage):
+    """The values 2-byte storage holds (round to nearest even)."""
+    if storage == "f16":
+        return f.astype(np.float16).astype(np.float64)
+    u = f.astype(np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _half_quantum(o, storage):
+    a = np.abs(o)
+    if storage == "f16":
+        return 0.5 * np.spacing(a.astype(np.float16)).astype(np.float64)
+    return 0.5 * 2.0 ** (np.floor(np.log2(np.maximum(a, 1e-38))) - 7)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("periodic,with_parts", [((1, 0, 0), False), ((0, 1, 0), False), ((1, 0, 0), True)])
+def test_two_byte_step_wide_rows(storage, periodic, with_parts):
+    """D2Q9 in 2-byte storage on a lattice of several row segments (interior
+    segments, whose sources come from uniform row pointers, and row-end and
+    wall-row segments, which take per-node offsets).  One step from a random
+    state against the FP64 oracle started from the same rounded populations:
+    every population within half a storage quantum of the oracle's, plus
+    FP32 arithmetic.  With bodies: some inside interior segments, one across
+    a wavefront edge there, one wrapping the periodic x axis."""
+    banner(f"two-byte wide rows {storage} {periodic} parts={with_parts}")
+    n = (1600, 24, 1)
+    cfg = dict(lattice="D2Q9", n=n, periodic=periodic, tau=0.7)
+    parts = []
+    if with_parts:
+        cfg["g"] = (0.0, -3e-4, 0.0)
+        parts = [dict(shape="disk", rho_s=1.5, a=5.0, x=(700.3, 12.2, 0.0)),
+                 dict(shape="disk", rho_s=1.3, a=4.5, x=(1023.6, 10.7, 0.0)),
+                 dict(shape="ellipse", rho_s=1.4, a=6.0, b=3.0, x=(1540.2, 12.5, 0.0), theta=0.7),
+                 dict(shape="disk", rho_s=1.6, a=4.0, x=(2.1, 11.4, 0.0))]
+    else:
+        cfg["fluid_accel"] = (2e-5, -1e-5, 0.0)
+    scale = 5e-3
+    f0 = _round_storage(random_state((1, n[1], n[0]), 9, scale, seed=31), storage)
+    sim, ora = pair(cfg, parts, storage=storage, f0=f0)
+    assert np.array_equal(sim.populations(), f0)
+    rg = sim.step_record(1) if with_parts else None
+    ro = ora.step(1, record=True) if with_parts else None
+    if not with_parts:
+        sim.step(1)
+        ora.step(1)
+    g, o = sim.populations(), ora.f()
+    bound = _half_quantum(o, storage) * (1 + 1e-3) + 2e-6 * np.abs(o).max()
+    excess = np.abs(g - o) - bound
+    print(f"[measured] {storage} {periodic} parts={with_parts}: max |g - o| {np.abs(g - o).max():.3e}, "
+          f"worst excess over the bound {excess.max():.3e}", flush=True)
+    assert excess.max() <= 0.0
+    if with_parts:
+        assert np.array_equal(rg[:, :, 13], ro[:, :, 13])  # node counts
+        Usc = np.abs(ro[:, :, 4:6]).max()
+        assert np.abs(rg[:, :, 4:6] - ro[:, :, 4:6]).max() <= 1e-4 * Usc
+        _, _, og = sim.fields()
+        _, _, oo = ora.fields()
+        check_owner(og, oo, parts, ora.particles(), periodic)
+
+
 def test_penalize_all_random_state():
     banner("penalize_all random")
     cfg = dict(lattice="D2Q9", n=(31, 27, 1), periodic=(1, 1, 0), tau=0.8, alpha=0.6, penalize_all=1)
