@@ -109,21 +109,26 @@ __global__ __launch_bounds__(256) void k_adj_lattice(const typename S::raw *__re
         const T om = (T)sp.omega, p3 = T(3) * p, u15 = T(1.5) * uu;
         const bool pen = solid || sp.penalize_all;
         const bool frc = solid || sp.has_fluid_acc;
+        // Sums over the velocity set leave out the components of c_q that are
+        // zero at compile time (CSum, cdot): 0 * v and x + 0 would stay in the
+        // code otherwise, though they change at most the sign of a zero.
         T fneq[L::Q], lam[L::Q], fbar[L::Q];
-        T Pxx = 0, Pyy = 0, Pzz = 0, Pxy = 0, Pxz = 0, Pyz = 0;
+        CSum<T> Pxx, Pyy, Pzz, Pxy, Pxz, Pyz;
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) {
-            const T cu = T(L::cx[q]) * u[0] + T(L::cy[q]) * u[1] + T(L::cz[q]) * u[2];
+            const T cu = cdot<L, T>(q, u[0], u[1], u[2]);
             fneq[q] = f[q] - feq_q<L, T>(q, p3, cu, u15);
             lam[q] = lam_in[q * N + idx];
             if (pen) {
-                const T cx = T(L::cx[q]), cy = T(L::cy[q]), cz = T(L::cz[q]);
-                Pxx += fneq[q] * cx * cx;
-                Pyy += fneq[q] * cy * cy;
-                Pzz += fneq[q] * cz * cz;
-                Pxy += fneq[q] * cx * cy;
-                Pxz += fneq[q] * cx * cz;
-                Pyz += fneq[q] * cy * cz;
+                Pxx.add(L::cx[q] != 0, fneq[q]);
+                Pyy.add(L::cy[q] != 0, fneq[q]);
+                Pzz.add(L::cz[q] != 0, fneq[q]);
+                Pxy.add(L::cx[q] * L::cy[q] > 0, fneq[q]);
+                Pxy.sub(L::cx[q] * L::cy[q] < 0, fneq[q]);
+                Pxz.add(L::cx[q] * L::cz[q] > 0, fneq[q]);
+                Pxz.sub(L::cx[q] * L::cz[q] < 0, fneq[q]);
+                Pyz.add(L::cy[q] * L::cz[q] > 0, fneq[q]);
+                Pyz.sub(L::cy[q] * L::cz[q] < 0, fneq[q]);
             }
         }
         // f~ = f - om fneq + F + S:  f_bar = lam, fneq_bar = -om lam, F_bar = S_bar = lam
@@ -139,32 +144,53 @@ __global__ __launch_bounds__(256) void k_adj_lattice(const typename S::raw *__re
         if (pen) {
             // S_q = sigma 4.5 w_q (Pi : c c - tr Pi / 3): Pi_bar and sigma_bar
             const T sigma = (T)sp.alpha;
-            const T tr3 = (Pxx + Pyy + Pzz) * T(1.0 / 3.0);
-            T sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0, str = 0;
+            const T tr3 = (Pxx.v + Pyy.v + Pzz.v) * T(1.0 / 3.0);
+            CSum<T> sxx, syy, szz, sxy, sxz, syz;
+            T str = 0;
 #pragma unroll
             for (int q = 0; q < L::Q; ++q) {
-                const T cx = T(L::cx[q]), cy = T(L::cy[q]), cz = T(L::cz[q]);
                 const T wl = T(4.5 * L::w[q]) * lam[q];
-                sxx += wl * cx * cx;
-                syy += wl * cy * cy;
-                szz += wl * cz * cz;
-                sxy += wl * cx * cy;
-                sxz += wl * cx * cz;
-                syz += wl * cy * cz;
+                sxx.add(L::cx[q] != 0, wl);
+                syy.add(L::cy[q] != 0, wl);
+                szz.add(L::cz[q] != 0, wl);
+                sxy.add(L::cx[q] * L::cy[q] > 0, wl);
+                sxy.sub(L::cx[q] * L::cy[q] < 0, wl);
+                sxz.add(L::cx[q] * L::cz[q] > 0, wl);
+                sxz.sub(L::cx[q] * L::cz[q] < 0, wl);
+                syz.add(L::cy[q] * L::cz[q] > 0, wl);
+                syz.sub(L::cy[q] * L::cz[q] < 0, wl);
                 str += wl;
-                const T PiCC = cx * cx * Pxx + cy * cy * Pyy + cz * cz * Pzz +
-                               T(2) * (cx * cy * Pxy + cx * cz * Pxz + cy * cz * Pyz);
+                CSum<T> diag, off;
+                diag.add(L::cx[q] != 0, Pxx.v);
+                diag.add(L::cy[q] != 0, Pyy.v);
+                diag.add(L::cz[q] != 0, Pzz.v);
+                off.add(L::cx[q] * L::cy[q] > 0, Pxy.v);
+                off.sub(L::cx[q] * L::cy[q] < 0, Pxy.v);
+                off.add(L::cx[q] * L::cz[q] > 0, Pxz.v);
+                off.sub(L::cx[q] * L::cz[q] < 0, Pxz.v);
+                off.add(L::cy[q] * L::cz[q] > 0, Pyz.v);
+                off.sub(L::cy[q] * L::cz[q] < 0, Pyz.v);
+                const T PiCC = off.any ? diag.v + T(2) * off.v : diag.v;
                 sigb += wl * (PiCC - tr3);
             }
             // trace term acts on the lattice dimensions only (Pzz = 0 in 2D)
             const T t3 = str * T(1.0 / 3.0);
-            const T bxx = sigma * (sxx - t3), byy = sigma * (syy - t3), bzz = (L::D == 3) ? sigma * (szz - t3) : T(0);
-            const T bxy = sigma * sxy, bxz = sigma * sxz, byz = sigma * syz;
+            const T bxx = sigma * (sxx.v - t3), byy = sigma * (syy.v - t3),
+                    bzz = (L::D == 3) ? sigma * (szz.v - t3) : T(0);
+            const T bxy = sigma * sxy.v, bxz = sigma * sxz.v, byz = sigma * syz.v;
 #pragma unroll
             for (int q = 0; q < L::Q; ++q) {
-                const T cx = T(L::cx[q]), cy = T(L::cy[q]), cz = T(L::cz[q]);
-                fnb[q] += bxx * cx * cx + byy * cy * cy + bzz * cz * cz +
-                          T(2) * (bxy * cx * cy + bxz * cx * cz + byz * cy * cz);
+                CSum<T> diag, off;
+                diag.add(L::cx[q] != 0, bxx);
+                diag.add(L::cy[q] != 0, byy);
+                diag.add(L::cz[q] != 0, bzz);
+                off.add(L::cx[q] * L::cy[q] > 0, bxy);
+                off.sub(L::cx[q] * L::cy[q] < 0, bxy);
+                off.add(L::cx[q] * L::cz[q] > 0, bxz);
+                off.sub(L::cx[q] * L::cz[q] < 0, bxz);
+                off.add(L::cy[q] * L::cz[q] > 0, byz);
+                off.sub(L::cy[q] * L::cz[q] < 0, byz);
+                if (diag.any || off.any) fnb[q] += off.any ? diag.v + T(2) * off.v : diag.v;
             }
         }
         T ub[3] = {0, 0, 0}, ab[3] = {0, 0, 0};
@@ -172,16 +198,22 @@ __global__ __launch_bounds__(256) void k_adj_lattice(const typename S::raw *__re
         if (frc) {
             // F_q = gamma w_q [3 (c - u).a + 9 (c.u)(c.a)],  gamma = 1 - om/2
             const T gpre = T(1) - T(0.5) * om;
-            const T ua = u[0] * a[0] + u[1] * a[1] + u[2] * a[2];
+            const T ua = L::D == 3 ? u[0] * a[0] + u[1] * a[1] + u[2] * a[2] : u[0] * a[0] + u[1] * a[1];
 #pragma unroll
             for (int q = 0; q < L::Q; ++q) {
-                const T c[3] = {T(L::cx[q]), T(L::cy[q]), T(L::cz[q])};
-                const T ca = c[0] * a[0] + c[1] * a[1] + c[2] * a[2];
-                const T cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+                const int c[3] = {L::cx[q], L::cy[q], L::cz[q]};
+                const T ca = cdot<L, T>(q, a[0], a[1], a[2]);
+                const T cu = cdot<L, T>(q, u[0], u[1], u[2]);
                 const T gl = gpre * T(L::w[q]) * lam[q];
-                for (int k = 0; k < 3; ++k) {
-                    ub[k] += gl * (T(-3) * a[k] + T(9) * ca * c[k]);
-                    ab[k] += gl * (T(3) * (c[k] - u[k]) + T(9) * cu * c[k]);
+#pragma unroll
+                for (int k = 0; k < L::D; ++k) {
+                    if (c[k] != 0) {
+                        ub[k] += gl * (T(-3) * a[k] + T(9) * ca * T(c[k]));
+                        ab[k] += gl * (T(3) * (T(c[k]) - u[k]) + T(9) * cu * T(c[k]));
+                    } else {
+                        ub[k] += gl * (T(-3) * a[k]);
+                        ab[k] += gl * (T(3) * (-u[k]));
+                    }
                 }
                 gamb += T(L::w[q]) * lam[q] * (T(3) * (ca - ua) + T(9) * cu * ca);
             }
@@ -192,27 +224,33 @@ __global__ __launch_bounds__(256) void k_adj_lattice(const typename S::raw *__re
         for (int q = 0; q < L::Q; ++q) {
             fbar[q] += fnb[q];
             const T eb = -fnb[q]; // feq_bar
-            const T c[3] = {T(L::cx[q]), T(L::cy[q]), T(L::cz[q])};
+            const int c[3] = {L::cx[q], L::cy[q], L::cz[q]};
             if (q == 0) {
                 pb += eb * T(-3.0 * (1.0 - L::w[0]));
-                for (int k = 0; k < 3; ++k) ub[k] += eb * T(-3.0 * L::w[0]) * u[k];
+#pragma unroll
+                for (int k = 0; k < L::D; ++k) ub[k] += eb * T(-3.0 * L::w[0]) * u[k];
             } else {
-                const T cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+                const T cu = cdot<L, T>(q, u[0], u[1], u[2]);
                 pb += eb * T(3.0 * L::w[q]);
-                for (int k = 0; k < 3; ++k) ub[k] += eb * T(L::w[q]) * (T(3) * c[k] + T(9) * cu * c[k] - T(3) * u[k]);
+#pragma unroll
+                for (int k = 0; k < L::D; ++k)
+                    ub[k] += eb * T(L::w[q]) *
+                             (c[k] != 0 ? T(3) * T(c[k]) + T(9) * cu * T(c[k]) - T(3) * u[k] : -(T(3) * u[k]));
             }
         }
         // p = (s/3 - w0 |u|^2 / 2) / (1 - w0)
         const T sb = pb * T(1.0 / (3.0 * (1.0 - L::w[0])));
-        for (int k = 0; k < 3; ++k) ub[k] += pb * T(-L::w[0] / (1.0 - L::w[0])) * u[k];
+#pragma unroll
+        for (int k = 0; k < L::D; ++k) ub[k] += pb * T(-L::w[0] / (1.0 - L::w[0])) * u[k];
         if (solid)
             for (int k = 0; k < L::D; ++k) ub[k] += uext[3 * own + k];
         if (L::D == 2) ub[2] = 0;
         // u = j + a/2
-        for (int k = 0; k < 3; ++k) ab[k] += T(0.5) * ub[k];
+#pragma unroll
+        for (int k = 0; k < L::D; ++k) ab[k] += T(0.5) * ub[k];
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) {
-            fbar[q] += T(L::cx[q]) * ub[0] + T(L::cy[q]) * ub[1] + T(L::cz[q]) * ub[2] + (q > 0 ? sb : T(0));
+            if (q > 0) fbar[q] += cdot<L, T>(q, ub[0], ub[1], ub[2]) + sb;
             // transpose of the pull: f_q(x) came from pull_offset(q, x)
             lam_out[rp.at(q)] = fbar[q];
         }
