@@ -620,11 +620,13 @@ __global__ __launch_bounds__(BS) void k_adj_fused(AdjArrays A, PartDev P, RigidP
             if (lane == 0 && i < np) s_reach[i / WAVE] = m;
         }
     }
+    // 1. A_bar^n_j from j's records: wave 0 in 2D; the whole workgroup in 3D
+    // (thousands of records), its sum then handed to wave 0
     double t[3] = {0, 0, 0}, drho = 0.0, dg = 0.0;
-    if (threadIdx.x < WAVE) { // wave 0
-        // 1. A_bar^n_j from j's records (every lane ends with the totals)
+    if (D == 3 || threadIdx.x < WAVE) {
         const double *sj = sl.slots + (size_t)j * sl.stride * W1;
-        for (int q = lane; q < sl.stride; q += WAVE) {
+        const int t0 = D == 3 ? (int)threadIdx.x : lane, nt = D == 3 ? BS : WAVE;
+        for (int q = t0; q < sl.stride; q += nt) {
             double rv[W1];
 #pragma unroll
             for (int m = 0; m < W1; ++m) rv[m] = sj[(size_t)q * W1 + m];
@@ -632,8 +634,20 @@ __global__ __launch_bounds__(BS) void k_adj_fused(AdjArrays A, PartDev P, RigidP
 #pragma unroll
                 for (int m = 0; m < D; ++m) t[m] += rv[1 + m];
         }
+    }
+    if constexpr (D == 3) {
+        __shared__ double part[BS / WAVE][3];
+        __shared__ double s_tot[3];
+        block_sum<3, BS>(t, part);
+        if (threadIdx.x == 0)
+            for (int m = 0; m < 3; ++m) s_tot[m] = t[m];
+        __syncthreads();
+        for (int m = 0; m < 3; ++m) t[m] = s_tot[m];
+    } else if (threadIdx.x < WAVE) {
 #pragma unroll
         for (int m = 0; m < 3; ++m) t[m] = wave_sum(t[m]);
+    }
+    if (threadIdx.x < WAVE) { // wave 0
         adj_particle_close(t, rho, rp, Abar_n + 3 * j, drho, dg, lane == 0);
         if (!rigid && lane == 0) {
             A.rho_g[j] = rg0 + drho;

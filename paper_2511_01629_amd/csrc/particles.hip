@@ -494,11 +494,12 @@ __global__ __launch_bounds__(BS) void k_rigid_raster(uint16_t *__restrict__ owne
 //     interact at X^n or at the prediction (|X_i - X_j| <= R_i + R_j +
 //     delta + 0.6: the lattice sentinel bounds every node speed by 0.3, hence
 //     |U_bar| <= 0.3), one bit per j in LDS;
-//  1. meanwhile its first wavefront sums i's records of this step: lane l
-//     takes the records l, l + 64, ... of i's table; one with this step's
-//     stamp is shifted to moments about X_i^n by the first node it carries,
-//     and the wavefront sum (fixed order) gives N_i, U_i^n, omega_i^n, the
-//     record, U_bar_i and dtheta_i on every lane;
+//  1. meanwhile its first wavefront sums i's records of this step (in 3D,
+//     with thousands of records, the whole workgroup): lane l takes the
+//     records l, l + 64, ... of i's table; one with this step's stamp is
+//     shifted to moments about X_i^n by the first node it carries, and the
+//     fixed-order sum gives N_i, U_i^n, omega_i^n, the record, U_bar_i and
+//     dtheta_i on every lane of wave 0;
 //  2. after a barrier the same wavefront visits the particles in reach in
 //     index order, sums the count and velocity of j's records of this step
 //     (j's box is not needed, which is as well: j's own workgroup is replacing
@@ -613,17 +614,20 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
     for (int k = 0; k < 3; ++k) ps.Uprev[k] = P.U[3 * i + k]; // U^{n-1}
     int cnt = 0;
     double dth = 0.0, Ub[3] = {0, 0, 0};
-    if (threadIdx.x < WAVE) { // wave 0
 
-        // 1. own sums: every record of i's table (no dependence on the scan
-        // box: the loads issue with the particle's own), kept if it carries
-        // this step's stamp and shifted to moments about X_i^n by its first
-        // node; every lane ends with the same totals
-        double s[NS];
+    // 1. own sums: every record of i's table (no dependence on the scan box:
+    // the loads issue with the particle's own), kept if it carries this
+    // step's stamp and shifted to moments about X_i^n by its first node.
+    // 2D: wave 0 alone (64 records); 3D (thousands of records): the whole
+    // workgroup, then its sum is handed to wave 0.  Either way every lane of
+    // wave 0 ends with the same totals.
+    double s[NS];
 #pragma unroll
-        for (int k = 0; k < NS; ++k) s[k] = 0.0;
+    for (int k = 0; k < NS; ++k) s[k] = 0.0;
+    if (D == 3 || threadIdx.x < WAVE) {
         const double *si = sl.slots + (size_t)i * sl.stride * W1;
-        for (int t = lane; t < sl.stride; t += WAVE) {
+        const int t0 = D == 3 ? (int)threadIdx.x : lane, nt = D == 3 ? BS : WAVE;
+        for (int t = t0; t < sl.stride; t += nt) {
             double rv[W1];
 #pragma unroll
             for (int m = 0; m < W1; ++m) rv[m] = si[(size_t)t * W1 + m];
@@ -633,8 +637,22 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
                 add_slot<D>(rv, dx, dy, D == 3 ? dz : 0.0, s);
             }
         }
+    }
+    if constexpr (D == 3) {
+        __shared__ double part[BS / WAVE][NS];
+        __shared__ double s_tot[NS];
+        block_sum<NS, BS>(s, part);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < NS; ++k) s_tot[k] = s[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NS; ++k) s[k] = s_tot[k];
+    } else if (threadIdx.x < WAVE) {
 #pragma unroll
         for (int k = 0; k < NS; ++k) s[k] = wave_sum(s[k]);
+    }
+    if (threadIdx.x < WAVE) { // wave 0
         cnt = (int)s[0];
         double U[3] = {0, 0, 0}, W[3] = {0, 0, 0};
         if (cnt > 0) {
