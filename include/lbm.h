@@ -184,10 +184,12 @@ int lbm_backward(lbm_ctx *ctx, const double *dL_dX, double *g_rho_s, double *g_t
  * for the stream before returning.  lbm_profile_read returns, per kernel
  * class, the summed duration in milliseconds and the launch count since the
  * last reset (reset = 1 clears them afterwards).  Classes, in order:
- * 0 stream-collide-penalize, 1 momentum sums (with the indicator clear),
- * 2 Algorithm 1 with the new indicator (K = 1) or the sub-step integration
- * (K > 1), 3 the indicator after sub-steps (K > 1 only).  host_ms and
- * host_count are host arrays of LBM_NKERNELS. */
+ * 0 stream-collide-penalize, 1 momentum sums (with the indicator clear; no
+ * launches where the lattice kernel takes the sums, which it does with K = 1
+ * whenever the set-up found a slot layout), 2 Algorithm 1 with the new
+ * indicator (K = 1) or the sub-step integration (K > 1), 3 the indicator
+ * after sub-steps (K > 1 only).  host_ms and host_count are host arrays of
+ * LBM_NKERNELS. */
 #define LBM_NKERNELS 4
 int lbm_profile(lbm_ctx *ctx, int32_t enable);
 int lbm_profile_read(lbm_ctx *ctx, double *host_ms, int64_t *host_count, int32_t reset);
