@@ -252,8 +252,9 @@ def main():
         record_traffic(args.record_traffic, ("f32", "f16"), args.workload, COPY_BYTES)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path shards as "
-              f"slabs with halo exchange, which this build does not run)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the library runs on "
+              f"one GPU; a multi-GPU run would shard the lattice in slabs with a halo exchange, not implemented)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
