@@ -302,6 +302,10 @@ def main():
 
     key = f"{args.workload}/{args.storage}"
     traffic = measured_traffic(key)
+    from paper_2511_01629_amd.workloads import workload
+
+    wcfg = workload(args.workload)[0]
+    dims = list(wcfg["n"][:2] if wcfg["lattice"] == "D2Q9" else wcfg["n"])
     line = {
         "metric": "MLUPS & % HBM roofline: FP64 vs FP32 vs FP16-store; fwd+adjoint MLUPS",
         "value": head["mlups"],
@@ -315,7 +319,7 @@ def main():
         "vs_baseline": None,
         "dtype": MATH[args.storage],
         "data": "synthetic (seeded placement, no dataset)",
-        "config": {"workload": args.workload, "lattice": "D2Q9", "n": [2048, 4096], "bodies": head["particles"],
+        "config": {"workload": args.workload, "lattice": wcfg["lattice"], "n": dims, "bodies": head["particles"],
                    "storage": args.storage, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": head["kernel_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": head["kernel_frac"], "traffic": traffic,
