@@ -205,6 +205,9 @@ typedef struct {
      * the penalization source applied on every node */
     double fluid_accel[3];
     int penalize_all;
+    /* tangential velocity of the halfway walls, [axis][low, high side][component];
+     * moving walls only on the y or z axis, every other axis periodic */
+    double wall_u[3][2][3];
 } ora_cfg;
 
 typedef struct {
@@ -235,6 +238,8 @@ typedef struct {
     int K, cform, gform;
     double fluid_accel[3];
     int penalize_all;
+    int wall_axis; /* 0: no moving wall; else the axis of the moving walls */
+    double wall_u[2][3];
     int np;
     particle_t *p;
     real *f, *ft, *u, *pr;
@@ -460,9 +465,19 @@ static void collide_stream(ora_ctx *c)
                         wall = 1;
                 }
             }
-            if (wall)
+            if (wall) {
                 c->f[i * Q + a] = c->ft[i * Q + c->L.opp[a]];
-            else
+                if (c->wall_axis) {
+                    /* bounce-back off a moving wall (its other axes are periodic, so
+                     * this is the wall crossed): the reflected population gains the
+                     * difference of the two equilibria at the wall velocity,
+                     * f^eq_a(u_w) - f^eq_opp(u_w) = 2 w_a (c_a . u_w) / cs2 (eq. 13) */
+                    const int k = c->wall_axis, side = src[k] < 0 ? 0 : 1;
+                    double cu = 0.0;
+                    for (int j = 0; j < d; j++) cu += c->L.c[a][j] * c->wall_u[side][j];
+                    c->f[i * Q + a] += 2.0 * c->L.w[a] * cu / CS2;
+                }
+            } else
                 c->f[i * Q + a] = c->ft[node_index(c, (int)src[0], (int)src[1], (int)src[2]) * Q + a];
         }
     }
@@ -626,6 +641,26 @@ int ora_create(const ora_cfg *cfg, ora_ctx **out)
     c->gform = cfg->gravity_form;
     for (int k = 0; k < 3; k++) c->fluid_accel[k] = (k < c->L.d) ? cfg->fluid_accel[k] : 0.0;
     c->penalize_all = cfg->penalize_all;
+    /* moving walls: one axis (y or z), tangential velocities, others periodic */
+    for (int k = 0; k < 3; k++)
+        for (int sd = 0; sd < 2; sd++)
+            for (int j = 0; j < 3; j++) {
+                if (cfg->wall_u[k][sd][j] == 0.0) continue;
+                if (k == 0 || k >= c->L.d || c->periodic[k] || j == k || (c->wall_axis && c->wall_axis != k)) {
+                    free(c);
+                    return -1;
+                }
+                c->wall_axis = k;
+            }
+    if (c->wall_axis) {
+        for (int k = 0; k < c->L.d; k++)
+            if (k != c->wall_axis && !c->periodic[k]) {
+                free(c);
+                return -1;
+            }
+        for (int sd = 0; sd < 2; sd++)
+            for (int j = 0; j < 3; j++) c->wall_u[sd][j] = j < c->L.d ? cfg->wall_u[c->wall_axis][sd][j] : 0.0;
+    }
     const int Q = c->L.Q;
     c->f = calloc((size_t)c->N * Q, sizeof(real));
     c->ft = calloc((size_t)c->N * Q, sizeof(real));

@@ -34,6 +34,7 @@ class _Cfg(C.Structure):
         ("eps_p", C.c_double), ("eps_w", C.c_double), ("delta", C.c_double),
         ("K", C.c_int), ("collision_form", C.c_int), ("gravity_form", C.c_int),
         ("fluid_accel", C.c_double * 3), ("penalize_all", C.c_int),
+        ("wall_u", C.c_double * 18),
     ]
 
 
@@ -112,6 +113,12 @@ def _make_cfg(cfg):
     c.gravity_form = int(cfg.get("gravity_form", 0))
     c.fluid_accel = _vec3(cfg.get("fluid_accel", (0, 0, 0)))
     c.penalize_all = int(bool(cfg.get("penalize_all", 0)))
+    # wall_velocity: [axis][low, high][component] tangential wall velocities
+    wv = np.zeros((3, 2, 3))
+    if cfg.get("wall_velocity") is not None:
+        w = np.asarray(cfg["wall_velocity"], dtype=np.float64)
+        wv[: w.shape[0], : w.shape[1], : w.shape[2]] = w
+    c.wall_u = (C.c_double * 18)(*wv.ravel())
     return c
 
 

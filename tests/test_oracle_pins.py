@@ -457,6 +457,78 @@ def test_rigidity_grows_with_penalization():
     assert max(Us) / min(Us) - 1 < 0.03, Us
 
 
+def couette_walls(U, axis=1, direction=(1.0, 0.0, 0.0)):
+    """wall_velocity of a plane Couette flow: the walls normal to `axis` move at
+    -U/2 and +U/2 along `direction`."""
+    w = np.zeros((3, 2, 3))
+    w[axis, 0] = -0.5 * U * np.asarray(direction)
+    w[axis, 1] = 0.5 * U * np.asarray(direction)
+    return w.tolist()
+
+
+@pytest.mark.parametrize("tau", [0.6, 1.0, 1.7])
+def test_couette_exact_2d(tau):
+    """Halfway bounce-back off walls moving at -U/2 and +U/2 (the Couette
+    benchmark of sec. 3.1): the steady profile is the linear one of the walls
+    at y = -1/2 and H - 1/2, to round-off, with no normal velocity and a
+    uniform pressure (a linear shear is an exact steady state of BGK, and the
+    halfway wall adds no slip to it)."""
+    H, U = 16, 0.02
+    cfg = dict(lattice="D2Q9", n=(3, H), periodic=(1, 0, 0), tau=tau, wall_velocity=couette_walls(U))
+    o = O.Oracle(cfg, [])
+    o.step(int(40 * H * H / (CS2 * (tau - 0.5))))
+    u, p, _ = o.fields()
+    exact = -U / 2 + U * (np.arange(H) + 0.5) / H
+    assert np.abs(u[0, :, :, 0] - exact[:, None]).max() < 1e-13 * U
+    assert np.abs(u[..., 1]).max() < 1e-15 and np.ptp(p) < 1e-15
+
+
+def test_couette_exact_3d():
+    """The same in D3Q19 with the walls normal to z moving along (1, 2, 0)/sqrt 5."""
+    H, U, tau = 12, 0.02, 0.9
+    d = np.array([1.0, 2.0, 0.0]) / math.sqrt(5.0)
+    cfg = dict(lattice="D3Q19", n=(3, 3, H), periodic=(1, 1, 0), tau=tau, wall_velocity=couette_walls(U, 2, d))
+    o = O.Oracle(cfg, [])
+    o.step(int(40 * H * H / (CS2 * (tau - 0.5))))
+    u, _, _ = o.fields()
+    prof = -U / 2 + U * (np.arange(H) + 0.5) / H
+    for k in range(2):
+        assert np.abs(u[..., k] - (prof * d[k])[:, None, None]).max() < 1e-13 * U
+    assert np.abs(u[..., 2]).max() < 1e-15
+
+
+def test_couette_start_keeps_zero_momentum():
+    """Impulsively started Couette flow between walls at -U/2 and +U/2: the
+    flow is odd about the mid-plane at every step, so the total momentum stays
+    zero to round-off while the profile builds up (a wrong sign or side of
+    either wall term breaks it)."""
+    H, U = 20, 0.04
+    cfg = dict(lattice="D2Q9", n=(5, H), periodic=(1, 0, 0), tau=0.7, wall_velocity=couette_walls(U))
+    o = O.Oracle(cfg, [])
+    for _ in range(5):
+        o.step(37)
+        u, _, _ = o.fields()
+        assert abs(u[..., 0].sum()) < 1e-15 * u[..., 0].size
+        assert np.abs(u[0, :, :, 0] + u[0, ::-1, :, 0]).max() < 1e-16
+        assert u[0, -1, 0, 0] > 0.1 * U
+
+
+@pytest.mark.parametrize("bad", [
+    dict(periodic=(1, 1, 0)),                                    # moving wall on a periodic axis
+    dict(wall_velocity=[[(0, 0, 0)] * 2, [(0, 0.01, 0), (0, 0, 0)], [(0, 0, 0)] * 2]),  # normal motion
+    dict(periodic=(0, 1, 0), wall_velocity=[[(0, 0.01, 0), (0, 0, 0)], [(0, 0, 0)] * 2, [(0, 0, 0)] * 2]),  # x walls
+    dict(periodic=(0, 0, 0)),                                    # another axis with walls
+])
+def test_moving_wall_limits(bad):
+    """Moving walls are accepted on the y (or z) axis only, tangential, with
+    every other axis periodic (a population crossing two walls would have no
+    single wall velocity)."""
+    cfg = dict(lattice="D2Q9", n=(6, 8), periodic=(1, 0, 0), tau=0.8, wall_velocity=couette_walls(0.01))
+    cfg.update(bad)
+    with pytest.raises(Exception):
+        O.Oracle(cfg, [])
+
+
 def _poiseuille(tau, H, a=1e-6, steps=None):
     cfg = dict(lattice="D2Q9", n=(3, H), periodic=(1, 0, 0), tau=tau, fluid_accel=(a, 0.0))
     o = O.Oracle(cfg, [])
