@@ -86,6 +86,13 @@ typedef struct {
                                bytes (e.g. from torch); NULL: the library allocates         */
     size_t workspace_bytes; /* size of `workspace`                                          */
     int32_t max_particles;  /* capacity for lbm_set_particles (sizes the workspace)         */
+    double wall_velocity[3][2][3]; /* [axis][low, high wall][component]: velocity of the
+                               halfway walls (the plane Couette benchmark of sec. 3.1).  A
+                               population bounced off a moving wall gains
+                               2 w_q (c_q . u_w)/cs^2 (the difference of the equilibria of
+                               eq. 13 at the wall velocity).  Nonzero only on the y axis, or
+                               the y or z axis in 3D, tangential (no normal component), with
+                               every other axis periodic; all zero: fixed walls.            */
 } lbm_config;
 
 typedef struct {

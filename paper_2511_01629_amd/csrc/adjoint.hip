@@ -95,6 +95,7 @@ __global__ __launch_bounds__(256) void k_adj_lattice(const typename S::raw *__re
         T f[L::Q];
         const RowPull<L> rp(x, y, z, idx, bx > 0 && bx * 256 + 256 < g.nx, g);
         pull_row<L, S, T>(fprev, rp, f);
+        wall_motion<L, T>(f, y, z, g, sp); // the pre-collision populations, moving walls included
         const uint16_t own = owner[idx];
         const bool solid = own != FLUID;
         T a[3] = {0, 0, 0};

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "ctx.h"
+#include "lattice.h"
 
 using namespace lbm;
 
@@ -97,7 +98,46 @@ int validate_cfg(const lbm_config *cfg, std::string &why, int &Q, int &d, int64_
     if (cfg->K < 1) return why = "K must be >= 1", LBM_EINVAL;
     if (!(cfg->rho_f > 0)) return why = "rho_f must be positive", LBM_EINVAL;
     if (cfg->eps_p <= 0 || cfg->eps_w <= 0 || cfg->delta <= 0) return why = "eps_p, eps_w, delta must be positive", LBM_EINVAL;
+    // moving walls: one axis (y, or z in 3D), tangential, every other axis periodic
+    int wall_axis = 0;
+    for (int k = 0; k < 3; ++k)
+        for (int s = 0; s < 2; ++s)
+            for (int j = 0; j < 3; ++j) {
+                const double v = cfg->wall_velocity[k][s][j];
+                if (v == 0.0) continue;
+                if (!isfinite(v)) return why = "wall velocities must be finite", LBM_EINVAL;
+                if (k == 0 || k >= d) return why = "moving walls only on the y axis (or the z axis in 3D)", LBM_EINVAL;
+                if (cfg->periodic[k]) return why = "a moving wall needs a wall axis, not a periodic one", LBM_EINVAL;
+                if (j == k) return why = "wall velocities must be tangential to the wall", LBM_EINVAL;
+                if (wall_axis && wall_axis != k) return why = "moving walls on one axis only", LBM_EINVAL;
+                wall_axis = k;
+            }
+    for (int k = 0; wall_axis && k < d; ++k)
+        if (k != wall_axis && !cfg->periodic[k])
+            return why = "with moving walls every other axis must be periodic", LBM_EINVAL;
     return LBM_OK;
+}
+
+// Per side and population, what a population pulled from behind a moving
+// wall gains: 2 w_q (c_q . u_w)/cs^2 (the difference of the equilibria of
+// eq. 13 at the wall velocity).
+template <class L> void wall_terms(const lbm_config *cfg, StepParams &sp)
+{
+    sp.wall_axis = 0;
+    for (int k = 1; k < L::D; ++k)
+        for (int s = 0; s < 2; ++s)
+            for (int j = 0; j < 3; ++j)
+                if (cfg->wall_velocity[k][s][j] != 0.0) sp.wall_axis = k;
+    for (int s = 0; s < 2; ++s)
+        for (int q = 0; q < 19; ++q) sp.wall_corr[s][q] = 0.0;
+    if (!sp.wall_axis) return;
+    for (int s = 0; s < 2; ++s)
+        for (int q = 0; q < L::Q; ++q) {
+            const int c[3] = {L::cx[q], L::cy[q], L::cz[q]};
+            double cu = 0.0;
+            for (int j = 0; j < L::D; ++j) cu += c[j] * cfg->wall_velocity[sp.wall_axis][s][j];
+            sp.wall_corr[s][q] = 2.0 * L::w[q] * cu / CS2;
+        }
 }
 
 void feq_host(int lattice, double p, const double u[3], double *out)
@@ -305,6 +345,8 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
     }
     c->sp.penalize_all = cfg->penalize_all != 0;
     c->sp.alpha_tracks_tau = !(cfg->alpha > 0);
+    if (d == 2) wall_terms<D2Q9>(cfg, c->sp);
+    else wall_terms<D3Q19>(cfg, c->sp);
     c->grad = nullptr;
     c->fresh = 0;
     c->rp.rho_f = cfg->rho_f;

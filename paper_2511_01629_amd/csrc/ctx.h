@@ -68,6 +68,11 @@ struct StepParams {
     int has_fluid_acc;
     int penalize_all;
     int alpha_tracks_tau; // alpha = 1/tau (the default) rather than a fixed value
+    // moving walls: their axis (1 y, 2 z; 0 none) and, per side (low, high) and
+    // population, the term 2 w_q (c_q . u_w)/cs^2 a population pulled from
+    // behind that wall gains
+    int wall_axis;
+    double wall_corr[2][19];
 };
 
 // Device pointers of one backward step of Algorithm 1 (see adjoint.hip).

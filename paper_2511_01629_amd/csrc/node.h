@@ -116,6 +116,27 @@ struct RowPull {
     }
 };
 
+// Bounce-back off a moving wall (sec. 3.1 Couette benchmark): a population
+// pulled from behind a halfway wall moving with u_w gains the difference of
+// the equilibria of eq. (13) at u_w, f^eq_q - f^eq_opp(q) = 2 w_q (c_q . u_w)
+// / cs^2.  Moving walls lie on one axis (y or z) and every other axis is
+// periodic, so the term depends on the row (y, z) only; rows not next to a
+// moving wall skip it.  sign = -1 removes it (the inverse of the pull).
+template <class L, class T>
+__device__ __forceinline__ void wall_motion(T *f, int y, int z, const Geom &g, const StepParams &sp, double sign = 1.0)
+{
+    if (sp.wall_axis == 0) return; // uniform
+    const int v = sp.wall_axis == 1 ? y : z, n = sp.wall_axis == 1 ? g.ny : g.nz;
+    if (v != 0 && v != n - 1) return; // uniform
+#pragma unroll
+    for (int q = 1; q < L::Q; ++q) {
+        const int c = sp.wall_axis == 1 ? L::cy[q] : L::cz[q];
+        const int s = v - c; // source coordinate on the wall axis
+        if (c != 0 && s < 0) f[q] += (T)(sign * sp.wall_corr[0][q]);
+        else if (c != 0 && s >= n) f[q] += (T)(sign * sp.wall_corr[1][q]);
+    }
+}
+
 // n / d for a uniform divisor d >= 1 with m = floor(2^32 / d) (2^32 - 1 for
 // d = 1) precomputed on the host: the high product is the quotient or one
 // less, so one correction gives it exactly (n < 2^31).

@@ -74,6 +74,7 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename S::raw *__
             pull<L, S, T>(fin, idx, x, y, z, g, N, f);
             own = owner[idx];
         }
+        wall_motion<L, T>(f, y, z, g, sp);
         collide_node<L, T>(f, own, acc_tab, sp, flags, usol, idx, N, ux, uy, uz);
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) st<S, T>(fout + q * N + idx, f[q]);
@@ -206,6 +207,7 @@ __global__ __launch_bounds__(TPB) void k_stream_collide_lds(const typename S::ra
                 j = j < 0 ? W : (j >= Wv ? W + 1 : j);
                 f[q] = from_raw<S, T>(buf[q * RL + j]);
             }
+            wall_motion<L, T>(f, y, z, g, sp);
             own = own_s[i];
             collide_node<L, T>(f, own, acc_tab, sp, flags, usol, rbase + x0 + i, N, ux, uy, uz);
 #pragma unroll
@@ -256,6 +258,7 @@ __global__ __launch_bounds__(256) void k_fields(const typename S::raw *__restric
     coords<L>(idx, g, x, y, z);
     T f[L::Q];
     pull<L, S, T>(fin, idx, x, y, z, g, N, f);
+    wall_motion<L, T>(f, y, z, g, sp);
     T ax = 0, ay = 0, az = 0;
     if (solid) {
         ax = acc_tab[3 * own + 0];
@@ -283,7 +286,7 @@ __global__ __launch_bounds__(256) void k_fields(const typename S::raw *__restric
 // Pulled populations f^n (FP64) of directions [q0, q0+nq) into out[q-q0][N].
 template <class L, class S, class T>
 __global__ __launch_bounds__(256) void k_populations(const typename S::raw *__restrict__ fin, double *__restrict__ out,
-                                                      int q0, int nq, Geom g)
+                                                      int q0, int nq, Geom g, StepParams sp)
 {
     const int N = (int)g.N;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -292,6 +295,7 @@ __global__ __launch_bounds__(256) void k_populations(const typename S::raw *__re
     coords<L>(idx, g, x, y, z);
     T f[L::Q];
     pull<L, S, T>(fin, idx, x, y, z, g, N, f);
+    wall_motion<L, T>(f, y, z, g, sp);
 #pragma unroll
     for (int q = 0; q < L::Q; ++q)
         if (q >= q0 && q < q0 + nq) out[(size_t)(q - q0) * N + idx] = (double)f[q];
@@ -299,11 +303,12 @@ __global__ __launch_bounds__(256) void k_populations(const typename S::raw *__re
 
 // Inverse of the pull: store f~ so that the next pull yields fn.  For node
 // x and direction q: f~_q(x) = fn_q(x + c_q) if x + c_q is a node (wrapped),
-// else f~_q(x) = fn_opp(q)(x) (the population bounced back into x).
+// else f~_q(x) = fn_opp(q)(x) (the population bounced back into x), less
+// what a moving wall adds to it.
 // fn holds directions q and opp(q) at fn[0][N] and fn[1][N].
 template <class L, class S, class T>
 __global__ __launch_bounds__(256) void k_set_populations(const double *__restrict__ fn, typename S::raw *__restrict__ fout,
-                                                          int q, Geom g)
+                                                          int q, Geom g, StepParams sp)
 {
     const int N = (int)g.N;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -322,6 +327,10 @@ __global__ __launch_bounds__(256) void k_set_populations(const double *__restric
         }
     }
     double v = out ? fn[(size_t)N + idx] : fn[d[0] + g.nx * (d[1] + g.ny * d[2])];
+    if (out && sp.wall_axis) { // every other axis is periodic: x + c_q lies behind the moving wall
+        const int s = sp.wall_axis == 1 ? y + cq[1] : z + cq[2]; // below 0: the low wall; else the high one
+        v -= sp.wall_corr[s < 0 ? 0 : 1][L::opp[q]];
+    }
     st<S, T>(fout + (size_t)q * N + idx, (T)v);
 }
 
@@ -330,7 +339,8 @@ struct FeqTab {
     double v[19];
 };
 template <class L, class S, class T>
-__global__ __launch_bounds__(256) void k_init_uniform(typename S::raw *__restrict__ fout, FeqTab fe, Geom g)
+__global__ __launch_bounds__(256) void k_init_uniform(typename S::raw *__restrict__ fout, FeqTab fe, Geom g,
+                                                       StepParams sp)
 {
     const int N = (int)g.N;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -348,7 +358,12 @@ __global__ __launch_bounds__(256) void k_init_uniform(typename S::raw *__restric
             int t = xs[k] + cq[k];
             if ((t < 0 || t >= n[k]) && !per[k]) out = true;
         }
-        st<S, T>(fout + (size_t)q * N + idx, (T)(out ? fe.v[L::opp[q]] : fe.v[q]));
+        double v = out ? fe.v[L::opp[q]] : fe.v[q];
+        if (out && sp.wall_axis) { // less what the moving wall adds to the bounced population
+            const int s = xs[sp.wall_axis] + cq[sp.wall_axis];
+            v -= sp.wall_corr[s < 0 ? 0 : 1][L::opp[q]];
+        }
+        st<S, T>(fout + (size_t)q * N + idx, (T)v);
     }
 }
 
@@ -415,7 +430,7 @@ hipError_t launch_populations(lbm_ctx *c, const void *fin, double *out, int q0, 
         using St = decltype(S);
         using Tt = decltype(T);
         hipLaunchKernelGGL((k_populations<Lt, St, Tt>), dim3(blocks_for(c->geo.N)), dim3(256), 0, c->stream,
-                           (const typename St::raw *)fin, out, q0, nq, c->geo);
+                           (const typename St::raw *)fin, out, q0, nq, c->geo, c->sp);
         return hipGetLastError();
     });
 }
@@ -427,7 +442,7 @@ hipError_t launch_set_populations(lbm_ctx *c, const double *fn, void *fout, int 
         using St = decltype(S);
         using Tt = decltype(T);
         hipLaunchKernelGGL((k_set_populations<Lt, St, Tt>), dim3(blocks_for(c->geo.N)), dim3(256), 0, c->stream, fn,
-                           (typename St::raw *)fout, q, c->geo);
+                           (typename St::raw *)fout, q, c->geo, c->sp);
         return hipGetLastError();
     });
 }
@@ -441,7 +456,7 @@ hipError_t launch_init_uniform(lbm_ctx *c, void *fout, const double *feq)
         using St = decltype(S);
         using Tt = decltype(T);
         hipLaunchKernelGGL((k_init_uniform<Lt, St, Tt>), dim3(blocks_for(c->geo.N)), dim3(256), 0, c->stream,
-                           (typename St::raw *)fout, t, c->geo);
+                           (typename St::raw *)fout, t, c->geo, c->sp);
         return hipGetLastError();
     });
 }

@@ -46,7 +46,7 @@ class Config(C.Structure):
         ("delta", C.c_double), ("K", C.c_int32), ("collision_form", C.c_int32), ("gravity_form", C.c_int32),
         ("fluid_accel", C.c_double * 3), ("penalize_all", C.c_int32), ("device", C.c_int32),
         ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
-        ("max_particles", C.c_int32),
+        ("max_particles", C.c_int32), ("wall_velocity", C.c_double * 18),
     ]
 
 
@@ -127,6 +127,12 @@ def make_config(cfg, storage=None, device=0, max_particles=0):
     c.penalize_all = int(bool(cfg.get("penalize_all", 0)))
     c.device = int(device)
     c.max_particles = int(max_particles)
+    # wall_velocity: [axis][low, high wall][component], tangential velocities of moving walls
+    wv = np.zeros((3, 2, 3))
+    if cfg.get("wall_velocity") is not None:
+        w = np.asarray(cfg["wall_velocity"], dtype=np.float64)
+        wv[: w.shape[0], : w.shape[1], : w.shape[2]] = w
+    c.wall_velocity = (C.c_double * 18)(*wv.ravel())
     return c
 
 

@@ -94,10 +94,22 @@ def workload(name):
         kinds = [("disk", 10.0, 10.0)] * 16
         parts = place((512, 1024), kinds, 1631, (1.2, 1.6), upper_axis=1)
         return cfg, parts, 5000, dict(desc="16 disks R=10 in 512x1024; loss = mean final height", checkpoint=100)
+    if name == "couette_migration_5000x200":
+        # plane Couette flow, H = 4D, L = 100D, walls at -U_w/2 and +U_w/2 with
+        # U_w = 1/60, tau = 1; a neutrally buoyant disk of diameter D = 50
+        # released at (15D, D)
+        H, D, Uw = 200, 50.0, 1.0 / 60.0
+        cfg = _cfg(lattice="D2Q9", n=(100 * int(D), H, 1), periodic=(1, 0, 0), tau=1.0, g=(0.0, 0.0, 0.0),
+                   storage="f64",
+                   wall_velocity=[[(0.0, 0.0, 0.0)] * 2, [(-Uw / 2, 0.0, 0.0), (Uw / 2, 0.0, 0.0)], [(0.0, 0.0, 0.0)] * 2])
+        parts = [dict(shape="disk", rho_s=1.0, a=D / 2, b=D / 2, x=(15 * D, D, 0.0), theta=0.0)]
+        return cfg, parts, 700000, dict(desc="lateral migration of a neutrally buoyant disk in plane Couette flow",
+                                        shear_rate=Uw / H)
     raise KeyError(name)
 
 
 NAMES = ["floating_disk_200x400", "disk_settling_400x1600", "sedimentation_2048x4096", "spheres_256x256x512",
+         "couette_migration_5000x200",
          "adjoint_512x1024"]
 
 

@@ -45,6 +45,30 @@ def test_invalid_configs_rejected_on_host(bad):
     assert not ctx.value
 
 
+def _walls(axis, lo, hi):
+    w = [[(0.0, 0.0, 0.0), (0.0, 0.0, 0.0)] for _ in range(3)]
+    w[axis] = [lo, hi]
+    return w
+
+
+@pytest.mark.parametrize("bad", [
+    dict(wall_velocity=_walls(1, (0.0, 0.01, 0.0), (0.0, 0.0, 0.0))),                     # normal motion
+    dict(periodic=(0, 1, 0), wall_velocity=_walls(0, (0.0, 0.01, 0.0), (0.0, 0.0, 0.0))),  # x walls
+    dict(periodic=(1, 1, 0), wall_velocity=_walls(1, (0.01, 0.0, 0.0), (0.0, 0.0, 0.0))),  # periodic axis
+    dict(periodic=(0, 0, 0), wall_velocity=_walls(1, (0.01, 0.0, 0.0), (0.0, 0.0, 0.0))),  # x walls fixed
+    dict(wall_velocity=_walls(1, (float("nan"), 0.0, 0.0), (0.0, 0.0, 0.0))),
+])
+def test_moving_walls_rejected_on_host(bad):
+    """Moving walls: one axis (y, or z in 3D), tangential, every other axis
+    periodic; anything else is EINVAL before any device work."""
+    lib = lbm.load()
+    c = lbm.make_config(dict(_base(), **bad), max_particles=4)
+    size = C.c_size_t()
+    assert lib.lbm_workspace_size(C.byref(c), C.byref(size)) == lbm.LBM_EINVAL
+    good = lbm.make_config(dict(_base(), wall_velocity=_walls(1, (-0.01, 0.0, 0.0), (0.01, 0.0, 0.0))))
+    assert lib.lbm_workspace_size(C.byref(good), C.byref(size)) == 0
+
+
 def test_invalid_storage_and_particle_cap():
     lib = lbm.load()
     c = lbm.make_config(_base(), max_particles=70000)
