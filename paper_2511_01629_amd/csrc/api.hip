@@ -32,7 +32,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 int storage_bytes(int s) { return s == LBM_F64 ? 8 : s == LBM_F32 ? 4 : 2; }
 
 struct Layout {
-    size_t f0, f1, owner, usol, staging, flags, pd, pf, pi, total;
+    size_t f0, f1, owner, usol, staging, flags, wall, pd, pf, pi, total;
 };
 
 Layout layout_for(const lbm_config *cfg, int Q, int d, int64_t N)
@@ -53,6 +53,8 @@ Layout layout_for(const lbm_config *cfg, int Q, int d, int64_t N)
     off += align_up((size_t)4 * N * sizeof(double));
     L.flags = off;
     off += ALIGN;
+    L.wall = off;
+    off += align_up(2 * 19 * sizeof(double));
     L.pd = off;
     off += align_up((size_t)cap * PART_DOUBLES * sizeof(double));
     L.pf = off;
@@ -118,10 +120,11 @@ int validate_cfg(const lbm_config *cfg, std::string &why, int &Q, int &d, int64_
     return LBM_OK;
 }
 
-// Per side and population, what a population pulled from behind a moving
-// wall gains: 2 w_q (c_q . u_w)/cs^2 (the difference of the equilibria of
-// eq. 13 at the wall velocity).
-template <class L> void wall_terms(const lbm_config *cfg, StepParams &sp)
+// The axis of the moving walls (validated above) and, per side and
+// population, what a population pulled from behind that wall gains:
+// 2 w_q (c_q . u_w)/cs^2, the difference of the equilibria of eq. (13) at
+// the wall velocity.
+template <class L> void wall_terms(const lbm_config *cfg, StepParams &sp, double tab[2][19])
 {
     sp.wall_axis = 0;
     for (int k = 1; k < L::D; ++k)
@@ -129,14 +132,13 @@ template <class L> void wall_terms(const lbm_config *cfg, StepParams &sp)
             for (int j = 0; j < 3; ++j)
                 if (cfg->wall_velocity[k][s][j] != 0.0) sp.wall_axis = k;
     for (int s = 0; s < 2; ++s)
-        for (int q = 0; q < 19; ++q) sp.wall_corr[s][q] = 0.0;
-    if (!sp.wall_axis) return;
-    for (int s = 0; s < 2; ++s)
-        for (int q = 0; q < L::Q; ++q) {
+        for (int q = 0; q < 19; ++q) {
+            tab[s][q] = 0.0;
+            if (!sp.wall_axis || q >= L::Q) continue;
             const int c[3] = {L::cx[q], L::cy[q], L::cz[q]};
             double cu = 0.0;
             for (int j = 0; j < L::D; ++j) cu += c[j] * cfg->wall_velocity[sp.wall_axis][s][j];
-            sp.wall_corr[s][q] = 2.0 * L::w[q] * cu / CS2;
+            tab[s][q] = 2.0 * L::w[q] * cu / CS2;
         }
 }
 
@@ -180,6 +182,8 @@ void carve(lbm_ctx *c, const Layout &L)
     c->owner = (uint16_t *)(base + L.owner);
     c->usol = (double *)(base + L.usol);
     c->staging = (double *)(base + L.staging);
+    c->wall_tab = (double *)(base + L.wall);
+    c->sp.wall_tab = c->wall_tab;
     c->flags = (int32_t *)(base + L.flags);
     const int cap = c->cap;
     double *pd = (double *)(base + L.pd);
@@ -345,8 +349,9 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
     }
     c->sp.penalize_all = cfg->penalize_all != 0;
     c->sp.alpha_tracks_tau = !(cfg->alpha > 0);
-    if (d == 2) wall_terms<D2Q9>(cfg, c->sp);
-    else wall_terms<D3Q19>(cfg, c->sp);
+    double wall_tab[2][19];
+    if (d == 2) wall_terms<D2Q9>(cfg, c->sp, wall_tab);
+    else wall_terms<D3Q19>(cfg, c->sp, wall_tab);
     c->grad = nullptr;
     c->fresh = 0;
     c->rp.rho_f = cfg->rho_f;
@@ -409,7 +414,8 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
     carve(c, L);
     double u0[3] = {cfg->u0[0], cfg->u0[1], d == 3 ? cfg->u0[2] : 0.0}, fe[19];
     feq_host(cfg->lattice, cfg->p0, u0, fe);
-    if ((e = launch_init_uniform(c, c->f[0], fe)) != hipSuccess ||
+    if ((e = hipMemcpy(c->wall_tab, wall_tab, sizeof(wall_tab), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = launch_init_uniform(c, c->f[0], fe)) != hipSuccess ||
         (e = hipMemsetAsync(c->owner, 0xFF, (size_t)((N + 1) / 2 * 2) * sizeof(uint16_t), c->stream)) != hipSuccess ||
         (e = hipMemsetAsync(c->flags, 0, ALIGN, c->stream)) != hipSuccess ||
         (e = hipMemsetAsync(c->P.lo, 0, (size_t)c->cap * 6 * sizeof(int32_t), c->stream)) != hipSuccess ||

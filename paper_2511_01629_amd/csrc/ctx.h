@@ -68,11 +68,11 @@ struct StepParams {
     int has_fluid_acc;
     int penalize_all;
     int alpha_tracks_tau; // alpha = 1/tau (the default) rather than a fixed value
-    // moving walls: their axis (1 y, 2 z; 0 none) and, per side (low, high) and
-    // population, the term 2 w_q (c_q . u_w)/cs^2 a population pulled from
-    // behind that wall gains
+    // moving walls: their axis (1 y, 2 z; 0 none) and, in device memory, per
+    // side (low, high) and population, the term 2 w_q (c_q . u_w)/cs^2 that a
+    // population pulled from behind that wall gains ([2][19] doubles)
     int wall_axis;
-    double wall_corr[2][19];
+    const double *wall_tab;
 };
 
 // Device pointers of one backward step of Algorithm 1 (see adjoint.hip).
@@ -116,6 +116,7 @@ struct lbm_ctx {
                           // buffer the next step's indicator goes to (differentiated runs)
     double *usol;    // [d][N] velocity on solid nodes (written by the lattice kernel unless it takes the sums)
     double *staging; // [4][N] doubles for field/population transfers
+    double *wall_tab; // [2][19] moving-wall terms (StepParams::wall_tab)
     int32_t *flags;  // [0] unstable, [1] domain
     lbm::PartDev P;
     int np, cap;

@@ -121,20 +121,43 @@ struct RowPull {
 // the equilibria of eq. (13) at u_w, f^eq_q - f^eq_opp(q) = 2 w_q (c_q . u_w)
 // / cs^2.  Moving walls lie on one axis (y or z) and every other axis is
 // periodic, so the term depends on the row (y, z) only; rows not next to a
-// moving wall skip it.  sign = -1 removes it (the inverse of the pull).
+// moving wall skip it.
+// The term for population q and the low (side 0) or high wall, in FP64
+// (a uniform load, made only on the rows next to a moving wall).
+template <class L>
+__device__ __forceinline__ double wall_term(int q, int side, const StepParams &sp)
+{
+    return sp.wall_tab[side * 19 + q];
+}
+
+template <class L, class T, int AX>
+__device__ __forceinline__ void wall_motion_on(T *f, int v, int n, const StepParams &sp)
+{
+#pragma unroll
+    for (int q = 1; q < L::Q; ++q) {
+        const int c = AX == 1 ? L::cy[q] : L::cz[q];
+        if (c == 0) continue;
+        const int s = v - c; // source coordinate on the wall axis
+        if (s < 0 || s >= n) f[q] += (T)wall_term<L>(q, s < 0 ? 0 : 1, sp);
+    }
+}
+
+// Whether row (y, z) lies next to a moving wall (uniform).
+__device__ __forceinline__ bool wall_row(int y, int z, const Geom &g, const StepParams &sp)
+{
+    if (sp.wall_axis == 1) return y == 0 || y == g.ny - 1;
+    if (sp.wall_axis == 2) return z == 0 || z == g.nz - 1;
+    return false;
+}
+
 template <class L, class T>
-__device__ __forceinline__ void wall_motion(T *f, int y, int z, const Geom &g, const StepParams &sp, double sign = 1.0)
+__device__ __forceinline__ void wall_motion(T *f, int y, int z, const Geom &g, const StepParams &sp)
 {
     if (sp.wall_axis == 0) return; // uniform
     const int v = sp.wall_axis == 1 ? y : z, n = sp.wall_axis == 1 ? g.ny : g.nz;
     if (v != 0 && v != n - 1) return; // uniform
-#pragma unroll
-    for (int q = 1; q < L::Q; ++q) {
-        const int c = sp.wall_axis == 1 ? L::cy[q] : L::cz[q];
-        const int s = v - c; // source coordinate on the wall axis
-        if (c != 0 && s < 0) f[q] += (T)(sign * sp.wall_corr[0][q]);
-        else if (c != 0 && s >= n) f[q] += (T)(sign * sp.wall_corr[1][q]);
-    }
+    if (L::D == 2 || sp.wall_axis == 1) wall_motion_on<L, T, 1>(f, v, n, sp);
+    else wall_motion_on<L, T, 2>(f, v, n, sp);
 }
 
 // n / d for a uniform divisor d >= 1 with m = floor(2^32 / d) (2^32 - 1 for
