@@ -81,6 +81,49 @@ def test_couette_fluid_3d(storage, tol):
     assert e < tol
 
 
+@pytest.mark.parametrize("storage,tol", [("f64", TOL), ("f32", 5e-6), ("f16", None)])
+def test_couette_fluid_3d_y_walls(storage, tol):
+    """D3Q19 with the moving walls normal to y (x and z periodic): the rows
+    next to them are whole (y, z) rows, in every storage type (FP32 staged
+    through LDS; FP16 one step within half a storage quantum)."""
+    banner(f"couette fluid 3d y walls {storage}")
+    n = (12, 7, 6)
+    w = [[(0.0, 0.0, 0.0)] * 2, [(0.02, 0.0, -0.01), (-0.015, 0.0, 0.02)], [(0.0, 0.0, 0.0)] * 2]
+    cfg = dict(lattice="D3Q19", n=n, periodic=(1, 0, 1), tau=0.7, wall_velocity=w)
+    f0 = random_state((n[2], n[1], n[0]), 19, 2e-3, seed=46)
+    if storage == "f32":
+        f0 = f0.astype(np.float32).astype(np.float64)
+    if storage == "f16":
+        f0 = _round_storage(f0, "f16")
+    sim, ora = pair(cfg, [], storage=storage, f0=f0)
+    if storage == "f16":
+        ora.set_f(sim.populations())
+        sim.step(1)
+        ora.step(1)
+        g, o = sim.populations(), ora.f()
+        mag = np.abs(o)
+        mag[:, [0, -1]] += 2.0 / 18.0 * 0.025 * 3.0
+        excess = np.abs(g - o) - (_half_quantum(mag, "f16") * (1 + 1e-3) + 2e-6 * np.abs(o).max())
+        assert excess.max() <= 0.0, excess.max()
+        return
+    sim.step(10)
+    ora.step(10)
+    e = rel(sim.populations(), ora.f())
+    print(f"[measured] couette 3d y walls {storage}: populations rel err {e:.2e}", flush=True)
+    assert e < tol
+
+
+def test_couette_sphere_3d_f64():
+    """A sphere sheared between walls normal to z (D3Q19, FP64), with
+    gravity along the walls' normal: the whole step within 1e-12."""
+    banner("couette sphere 3d f64")
+    w = [[(0.0, 0.0, 0.0)] * 2, [(0.0, 0.0, 0.0)] * 2, [(-0.02, 0.01, 0.0), (0.03, 0.0, 0.0)]]
+    cfg = dict(lattice="D3Q19", n=(18, 16, 20), periodic=(1, 1, 0), tau=0.7, g=(0.0, 0.0, -3e-4), wall_velocity=w)
+    parts = [dict(shape="sphere", rho_s=1.4, a=4.0, x=(8.3, 7.6, 9.2))]
+    f0 = random_state((20, 16, 18), 19, 1e-3, seed=47)
+    _compare_run(cfg, parts, 15, f0=f0)
+
+
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 def test_couette_two_byte_step(storage):
     """One step in 2-byte storage on rows of several segments with moving y
