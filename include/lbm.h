@@ -113,9 +113,12 @@ typedef struct {
 int lbm_workspace_size(const lbm_config *cfg, size_t *bytes);
 
 /* Validate cfg, allocate (or carve the workspace), and initialise every node
- * to f^eq(p0, u0) (eq. 13).  EINVAL: tau <= 1/2, alpha > 1/tau, n <= 0,
- * unknown lattice/storage, max_particles outside [0, 65534].  *out receives
- * the context; it is freed by lbm_destroy. */
+ * to f^eq(p0, u0) (eq. 13), also next to moving walls.  EINVAL: tau <= 1/2,
+ * alpha > 1/tau, n <= 0, Q*N >= 2^31, unknown lattice/storage, max_particles
+ * outside [0, 65534], K < 1, non-positive rho_f, eps_p, eps_w or delta, and
+ * moving walls outside their limits (on x, on a periodic axis, on two axes,
+ * with a normal component or a non-finite value, or with another axis not
+ * periodic).  *out receives the context; it is freed by lbm_destroy. */
 int lbm_create(const lbm_config *cfg, lbm_ctx **out);
 
 /* Free the context and everything it allocated (never the caller's workspace). */
