@@ -13,12 +13,16 @@ kernels take their own code path: there the bound is the storage's rounding
 (velocities on the nodes both sides give the same owner, relative to the
 largest velocity; body centres in lattice units), far below the O(1) error of
 a wrong index or a missed tail.
+
+The first 24 draws also run through the hand-written adjoint (K = 1, from a
+uniform flow along the first periodic axis), against the complex-step oracle.
 """
 import numpy as np
 import pytest
 
 from gpu_common import banner, pair
 from paper_2511_01629_amd.workloads import place, random_state
+from test_gpu_adjoint import _check, gpu_gradient, oracle_gradient
 from test_gpu_parity import _compare_run
 
 pytestmark = pytest.mark.gpu
@@ -117,3 +121,28 @@ def test_random_config_storage(seed, storage):
     print(f"[measured] seed={seed} storage={storage} u_rel={eu:.3e} X_abs={ex:.3e} flips={flips}", flush=True)
     bu, bx, bf = STORAGE_BOUNDS[storage]
     assert eu < bu and ex < bx and flips <= bf
+
+
+@pytest.mark.parametrize("seed", SEEDS[:24])
+def test_random_config_adjoint(seed):
+    """The gradient of a seeded weighting of the final centres with respect to
+    every rho_s, tau and |g|, checkpoints every 1, 4 or 15 steps: within 1e-8
+    of the complex-step oracle (FP64 storage, as the other adjoint tests)."""
+    cfg, parts = draw(seed)
+    cfg["K"] = 1
+    per = cfg["periodic"]
+    if any(per):
+        u0 = [0.0] * 3
+        u0[per.index(1)] = 0.01
+        cfg["u0"] = tuple(u0)
+    d = 2 if cfg["lattice"] == "D2Q9" else 3
+    rng = np.random.default_rng(4000 + seed)
+    w = rng.normal(size=(len(parts), 3))
+    w[:, d:] = 0.0
+    every = int(rng.choice([1, 4, STEPS]))
+    banner(f"random config {seed} adjoint every={every}: {cfg['lattice']} n={cfg['n']} periodic={per} "
+           f"alpha={cfg.get('alpha', 'default')} walls={'moving' if 'wall_velocity' in cfg else 'fixed'} "
+           f"bodies={len(parts)}")
+    go = oracle_gradient(cfg, parts, STEPS, w)
+    ga = gpu_gradient(cfg, parts, STEPS, every, w)
+    _check(ga, go, 1e-8)
