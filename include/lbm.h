@@ -206,8 +206,10 @@ int lbm_profile_read(lbm_ctx *ctx, double *host_ms, int64_t *host_count, int32_t
 
 /* Plain device-to-device copy of `bytes` bytes with a streaming kernel of the
  * library (16-byte vector loads/stores), queued on `stream` (hipStream_t or
- * NULL).  dst and src are device pointers, 16-byte aligned, not overlapping.
- * Used as the achievable-bandwidth reference of the measurements. */
+ * NULL).  dst and src are device pointers, 16-byte aligned, not overlapping;
+ * bytes is a multiple of 16 (EINVAL otherwise, and for a NULL pointer with
+ * bytes > 0; EDEVICE if the launch fails).  Used as the achievable-bandwidth
+ * reference of the measurements. */
 int lbm_copy(void *dst, const void *src, size_t bytes, void *stream);
 
 /* Number of completed steps. */

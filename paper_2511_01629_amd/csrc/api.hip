@@ -737,7 +737,7 @@ int lbm_profile_read(lbm_ctx *c, double *ms, int64_t *cnt, int32_t reset)
 int lbm_copy(void *dst, const void *src, size_t bytes, void *stream)
 {
     if ((!dst || !src) && bytes) return LBM_EINVAL;
-    if (((uintptr_t)dst | (uintptr_t)src) % 16) return LBM_EINVAL;
+    if (((uintptr_t)dst | (uintptr_t)src | bytes) % 16) return LBM_EINVAL; // the kernel moves whole 16-byte words
     return launch_copy(dst, src, bytes, (hipStream_t)stream) == hipSuccess ? LBM_OK : LBM_EDEVICE;
 }
 

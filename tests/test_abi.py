@@ -98,6 +98,22 @@ def test_null_arguments():
     assert lib.lbm_create(None, None) == lbm.LBM_EINVAL
     assert lib.lbm_destroy(None) == lbm.LBM_EINVAL
     assert lib.lbm_step(None, 1) == lbm.LBM_EINVAL
+    # every call taking a context rejects NULL before any device work
+    size = C.c_size_t()
+    step = C.c_int64()
+    for rc in (lib.lbm_workspace_size(None, C.byref(size)), lib.lbm_set_particles(None, None, 0),
+               lib.lbm_step_record(None, 0, None), lib.lbm_sync(None), lib.lbm_get_fields(None, None, None, None),
+               lib.lbm_get_populations(None, None), lib.lbm_set_populations(None, None),
+               lib.lbm_get_particles(None, None, 0), lib.lbm_forward_checkpointed(None, 1, 1),
+               lib.lbm_backward(None, None, None, None, None), lib.lbm_profile(None, 1),
+               lib.lbm_profile_read(None, None, None, 0), lib.lbm_get_step(None, C.byref(step))):
+        assert rc == lbm.LBM_EINVAL
+    assert lib.lbm_workspace_size(C.byref(lbm.make_config(_base())), None) == lbm.LBM_EINVAL
+    # lbm_copy: NULL with bytes > 0, misaligned pointers, sizes that are not whole 16-byte words
+    assert lib.lbm_copy(None, None, 16, None) == lbm.LBM_EINVAL
+    assert lib.lbm_copy(C.c_void_p(0x1008), C.c_void_p(0x2000), 16, None) == lbm.LBM_EINVAL
+    assert lib.lbm_copy(C.c_void_p(0x1000), C.c_void_p(0x2000), 24, None) == lbm.LBM_EINVAL
+    assert lib.lbm_copy(None, None, 0, None) == lbm.LBM_OK
     # a rejected configuration leaves its reason for lbm_last_error(NULL)
     bad = lbm.make_config(_base(), storage="f32", max_particles=8)
     bad.tau = 0.4
