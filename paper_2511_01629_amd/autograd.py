@@ -2,9 +2,11 @@
 
 LbmTrajectory.apply(rho_s, tau, gmag, run) runs `run.steps` steps of the
 penalized LBM on the GPU with checkpoints every `run.every` steps and returns
-the final particle centres (n x 3, float64).  Its backward calls the library's
+the final particle centres (n x 3, float64, on the device of rho_s).  Its
+backward calls the library's
 hand-written adjoint (lbm_backward), so gradients of any loss of the final
-centres flow to the solid densities, tau and |g|.  Every step runs in the HIP
+centres flow to the solid densities, tau and |g|, each on its input's device
+and dtype (a plain number for tau or |g| gets no gradient).  Every step runs in the HIP
 library; this module only marshals tensors.
 """
 from dataclasses import dataclass, field
@@ -26,30 +28,44 @@ class Run:
     last: dict = field(default_factory=dict)
 
 
+def _number(x):
+    return float(x.detach()) if torch.is_tensor(x) else float(x)
+
+
 class LbmTrajectory(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rho_s, tau, gmag, run):
         rho = rho_s.detach().cpu().double().numpy()
         cfg = dict(run.cfg)
-        cfg["tau"] = float(tau)
+        cfg["tau"] = _number(tau)
         g = np.asarray(cfg.get("g", (0.0, 0.0, 0.0)), dtype=np.float64)
         g0 = np.linalg.norm(g)
         if g0 == 0.0:
             raise ValueError("the gravity direction is taken from cfg['g'], which is zero")
-        cfg["g"] = tuple(g / g0 * float(gmag))
+        cfg["g"] = tuple(g / g0 * _number(gmag))
         parts = [dict(p, rho_s=float(r)) for p, r in zip(run.particles, rho)]
         sim = lbm.Simulation(cfg, parts, storage=run.storage, device=run.device)
         sim.forward_checkpointed(run.steps, run.every)
         X = sim.particles()["X"]
         ctx.sim = sim
+        # each gradient goes back on its input's device and dtype (inputs may
+        # be CUDA tensors or plain numbers)
+        ctx.like = [(t.device, t.dtype) if torch.is_tensor(t) else None for t in (rho_s, tau, gmag)]
         run.last["sim"] = sim
-        return torch.from_numpy(np.ascontiguousarray(X)).to(torch.float64)
+        out = torch.from_numpy(np.ascontiguousarray(X)).to(torch.float64)
+        return out.to(rho_s.device) if torch.is_tensor(rho_s) else out
 
     @staticmethod
     def backward(ctx, gX):
         g_rho, g_tau, g_g = ctx.sim.backward(gX.detach().cpu().double().numpy())
-        return (torch.from_numpy(np.ascontiguousarray(g_rho)), torch.tensor(g_tau, dtype=torch.float64),
-                torch.tensor(g_g, dtype=torch.float64), None)
+        out = []
+        for k, g in enumerate((np.ascontiguousarray(g_rho), g_tau, g_g)):
+            like = ctx.like[k]
+            if not ctx.needs_input_grad[k] or like is None:
+                out.append(None)
+            else:
+                out.append(torch.as_tensor(g, dtype=torch.float64).to(device=like[0], dtype=like[1]))
+        return (*out, None)
 
 
 def final_centres(rho_s, tau, gmag, run):

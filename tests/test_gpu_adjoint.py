@@ -155,6 +155,33 @@ def test_autograd_wrapper_matches_oracle():
     assert abs(loss.item() - o.particles()["X"][:, 1].mean()) < 1e-10
 
 
+def test_autograd_devices_and_plain_numbers():
+    """rho_s on the GPU, tau a plain number, |g| a float32 CPU tensor: the
+    centres come back on the GPU, each gradient on its input's device and
+    dtype (none for the plain number), equal to the complex-step oracle."""
+    banner("autograd devices")
+    import torch
+
+    from paper_2511_01629_amd.autograd import Run, mean_height_loss
+
+    parts = place((40, 72), [("disk", 6.0, 6.0)] * 3, seed=32, rho_range=(1.2, 1.6), upper_axis=1, gap=0.5,
+                  margin=0.3)
+    gmag = torch.tensor(2e-4, dtype=torch.float32, requires_grad=True)
+    cfg = dict(lattice="D2Q9", n=(40, 72, 1), periodic=(1, 0, 0), tau=0.7, g=(0.0, -gmag.item(), 0.0))
+    run = Run(cfg=cfg, particles=parts, steps=50, every=8, storage="f64")
+    rho = torch.tensor([p["rho_s"] for p in parts], dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = mean_height_loss(rho, 0.7, gmag, run)
+    assert loss.device.type == "cuda"
+    loss.backward()
+    assert rho.grad.device.type == "cuda" and rho.grad.dtype == torch.float64
+    assert gmag.grad.device.type == "cpu" and gmag.grad.dtype == torch.float32
+    w = np.zeros((3, 3))
+    w[:, 1] = 1.0 / 3
+    go = oracle_gradient(cfg, parts, 50, w)
+    _check(rho.grad.cpu().numpy(), go[:3], 1e-8)
+    assert abs(gmag.grad.item() / go[4] - 1) < 1e-6
+
+
 def test_adjoint_many_bodies_f64():
     """70 bodies: the particle adjoints run one workgroup per particle."""
     banner("adjoint many bodies f64")
