@@ -8,7 +8,8 @@ Configurations and particles are plain dicts:
   cfg = dict(lattice="D2Q9"|"D3Q19", n=(nx, ny, nz), periodic=(px, py, pz),
              tau=..., alpha=0 (-> 1/tau), rho_f=1, g=(gx, gy, gz), u0=(...),
              p0=0, eps_p=2, eps_w=1, delta=1, K=1, collision_form=0,
-             gravity_form=0)
+             gravity_form=0, fluid_accel=(0, 0, 0), penalize_all=0,
+             wall_velocity=None or [axis][low, high wall][component])
   particle = dict(shape="disk"|"ellipse"|"sphere", rho_s=..., a=..., b=...,
                   x=(X, Y, Z), theta=...)
 Fields come back with shape (nz, ny, nx, ...) (x fastest).
