@@ -554,7 +554,10 @@ int lbm_set_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
     HIPCHK(c, launch_fields(c, c->f[c->cur], c->usol, nullptr, 1));
     HIPCHK(c, launch_reduce(c, 0, nullptr));
     // U^{-1} = U^0.  With fused sums U^{n-1} is read from U itself (U^n goes to
-    // Unext, swapped in after the step), so U_prev is an alias of U.
+    // Unext, swapped in after the step), so U_prev is an alias of U.  The alias
+    // may outlive a later set-up without fused sums; that is harmless because
+    // every path leaves U_prev equal to U between steps, and the sums kernel
+    // reads U_prev before it writes U.
     if (c->fused) c->P.Uprev = c->P.U;
     else if (c->P.Uprev != c->P.U) HIPCHK(c, hipMemcpyAsync(c->P.Uprev, c->P.U, b3, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->P.Wprev, c->P.W, b3, hipMemcpyDeviceToDevice, c->stream));
