@@ -10,6 +10,8 @@ import numpy as np
 import pytest
 
 from gpu_common import banner, check_owner, pair, rel
+from oracle import oracle as O
+from paper_2511_01629_amd import lbm
 from paper_2511_01629_amd.workloads import workload
 
 pytestmark = pytest.mark.gpu
@@ -72,3 +74,44 @@ def test_fullsize_adjoint_workload_f64():
 
 def test_fullsize_disk_settling_f64():
     _compare("disk_settling_400x1600", "f64", 100, 1e-12)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f16"])
+def test_largest_lattice_index_range(storage):
+    """The largest D2Q9 lattice the library accepts (Q N = 2,147,401,728, just
+    below 2^31): every population offset q N + node sits at the top of the
+    32-bit index range.  Uniform flow along the periodic x axis between walls
+    in y stays independent of x, so after three steps every sampled column
+    equals the column of a 4-node-wide lattice with the same rows: to the
+    oracle within 1e-12 in FP64, and bit for bit to the small GPU run in FP16
+    storage (the same node arithmetic)."""
+    import torch
+
+    nx, ny = 16384, 14563
+    assert 9 * nx * ny < 2 ** 31
+    banner(f"largest lattice {nx}x{ny} {storage}")
+    cfg = dict(lattice="D2Q9", n=(nx, ny, 1), periodic=(1, 0, 0), tau=0.8, u0=(0.02, 0.0, 0.0))
+    small_cfg = dict(cfg, n=(4, ny, 1))
+    big = lbm.Simulation(cfg, [], storage=storage)
+    big.step(3)
+    ub, pb, _ = big.fields()
+    big.close()
+    del big
+    torch.cuda.empty_cache()
+    cols = [0, 1, 2, 3, 4097, 8190, nx - 2, nx - 1]
+    ub, pb = ub[0][:, cols], pb[0][:, cols]
+    if storage == "f64":
+        ora = O.Oracle(small_cfg, [])
+        ora.step(3)
+        uo, po, _ = ora.fields()
+    else:
+        small = lbm.Simulation(small_cfg, [], storage=storage)
+        small.step(3)
+        uo, po, _ = small.fields()
+        small.close()
+    uo, po = uo[0][:, [c % 4 for c in cols]], po[0][:, [c % 4 for c in cols]]
+    if storage == "f64":
+        assert np.abs(ub - uo).max() / np.abs(uo).max() < 1e-12
+        assert np.abs(pb - po).max() / max(np.abs(po).max(), 1e-30) < 1e-11
+    else:
+        assert np.array_equal(ub, uo) and np.array_equal(pb, po)
