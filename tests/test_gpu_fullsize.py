@@ -76,40 +76,53 @@ def test_fullsize_disk_settling_f64():
     _compare("disk_settling_400x1600", "f64", 100, 1e-12)
 
 
-@pytest.mark.parametrize("storage", ["f64", "f16"])
-def test_largest_lattice_index_range(storage):
-    """The largest D2Q9 lattice the library accepts (Q N = 2,147,401,728, just
-    below 2^31): every population offset q N + node sits at the top of the
-    32-bit index range.  Uniform flow along the periodic x axis between walls
-    in y stays independent of x, so after three steps every sampled column
-    equals the column of a 4-node-wide lattice with the same rows: to the
-    oracle within 1e-12 in FP64, and bit for bit to the small GPU run in FP16
-    storage (the same node arithmetic)."""
+LARGEST = {
+    # lattice: (n, periodic, the small lattice with the same rows, sampled (x, y))
+    "D2Q9": ((16384, 14563, 1), (1, 0, 0), (4, 14563, 1), [(0, 0), (1, 0), (3, 0), (4097, 0), (16383, 0)]),
+    "D3Q19": ((512, 512, 431), (1, 1, 0), (4, 1, 431), [(0, 0), (3, 511), (257, 130), (511, 0), (511, 511)]),
+}
+
+
+@pytest.mark.parametrize("kind,storage", [("D2Q9", "f64"), ("D2Q9", "f16"), ("D3Q19", "f64"), ("D3Q19", "f32"),
+                                          ("D3Q19", "f16")])
+def test_largest_lattice_index_range(kind, storage):
+    """The largest lattices the library accepts (Q N just below 2^31: D2Q9
+    16384 x 14563, D3Q19 512 x 512 x 431): every population offset q N + node
+    sits at the top of the 32-bit index range.  Uniform flow along a periodic
+    x between walls (in y, or in z with y periodic) stays independent of the
+    periodic coordinates, so after three steps every sampled column equals the
+    column of a lattice four nodes wide (one deep) with the same wall-normal
+    rows: to the oracle within 1e-12 in FP64, and bit for bit to the small GPU
+    run in FP32 (the LDS-staged D3Q19 kernel) and FP16 storage (the same node
+    arithmetic)."""
     import torch
 
-    nx, ny = 16384, 14563
-    assert 9 * nx * ny < 2 ** 31
-    banner(f"largest lattice {nx}x{ny} {storage}")
-    cfg = dict(lattice="D2Q9", n=(nx, ny, 1), periodic=(1, 0, 0), tau=0.8, u0=(0.02, 0.0, 0.0))
-    small_cfg = dict(cfg, n=(4, ny, 1))
+    n, per, n_small, pts = LARGEST[kind]
+    Q = 9 if kind == "D2Q9" else 19
+    assert Q * n[0] * n[1] * n[2] < 2 ** 31
+    banner(f"largest lattice {kind} {n} {storage}")
+    cfg = dict(lattice=kind, n=n, periodic=per, tau=0.8, u0=(0.02, 0.0, 0.0))
+    small_cfg = dict(cfg, n=n_small)
     big = lbm.Simulation(cfg, [], storage=storage)
     big.step(3)
-    ub, pb, _ = big.fields()
+    u, p, _ = big.fields()
     big.close()
     del big
     torch.cuda.empty_cache()
-    cols = [0, 1, 2, 3, 4097, 8190, nx - 2, nx - 1]
-    ub, pb = ub[0][:, cols], pb[0][:, cols]
+    ub = np.stack([u[:, y, x] for x, y in pts])
+    pb = np.stack([p[:, y, x] for x, y in pts])
+    del u, p
     if storage == "f64":
         ora = O.Oracle(small_cfg, [])
         ora.step(3)
-        uo, po, _ = ora.fields()
+        us, ps, _ = ora.fields()
     else:
         small = lbm.Simulation(small_cfg, [], storage=storage)
         small.step(3)
-        uo, po, _ = small.fields()
+        us, ps, _ = small.fields()
         small.close()
-    uo, po = uo[0][:, [c % 4 for c in cols]], po[0][:, [c % 4 for c in cols]]
+    uo = np.stack([us[:, y % n_small[1], x % 4] for x, y in pts])
+    po = np.stack([ps[:, y % n_small[1], x % 4] for x, y in pts])
     if storage == "f64":
         assert np.abs(ub - uo).max() / np.abs(uo).max() < 1e-12
         assert np.abs(pb - po).max() / max(np.abs(po).max(), 1e-30) < 1e-11
