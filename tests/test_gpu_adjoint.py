@@ -110,6 +110,27 @@ def test_adjoint_2d_f32_storage():
     _check(ga, go, 1e-3)
 
 
+# 2-byte storage of the populations (FP32 arithmetic, FP64 particle adjoint):
+# relative bounds on the gradient, about twice the errors measured on MI355X
+TWO_BYTE_BOUNDS = {"f16": 1e-5, "bf16": 1e-4}  # measured 4.6e-6 and 4.8e-5
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_adjoint_2d_two_byte_storage(storage):
+    """The FP32-storage case in FP16 and BF16 storage: the gradient of the
+    mean final height against the FP64 complex-step oracle, to the rounding
+    of the stored populations."""
+    banner(f"adjoint 2d {storage}")
+    parts = place((40, 72), [("disk", 6.0, 6.0)] * 3, seed=32, rho_range=(1.2, 1.6), upper_axis=1, gap=0.5,
+                  margin=0.3)
+    cfg = dict(lattice="D2Q9", n=(40, 72, 1), periodic=(1, 0, 0), tau=0.7, g=(0.0, -2e-4, 0.0))
+    w = np.zeros((len(parts), 3))
+    w[:, 1] = 1.0 / len(parts)
+    go = oracle_gradient(cfg, parts, 50, w)
+    ga = gpu_gradient(cfg, parts, 50, 10, w, storage=storage)
+    _check(ga, go, TWO_BYTE_BOUNDS[storage])
+
+
 def test_adjoint_rejects_bad_use():
     banner("adjoint errors")
     parts = [dict(shape="disk", rho_s=1.5, a=5.0, x=(20.0, 30.0, 0.0))]
