@@ -11,14 +11,19 @@ one of the step map with the indicator frozen):
   * complex step, for every parameter: one run of the complex-valued oracle
     with an imaginary perturbation 1e-30 (exact to rounding);
   * central differences with h_k = 1e-6 |theta_k|, the indicator replayed from
-    the centres and orientations recorded in the base run, for a subset of the
-    parameters (--fd) as an independent check of the complex step.
+    the centres and orientations recorded in the base run, for every
+    parameter (--fd all, the default, or a comma-separated subset): two real
+    runs per parameter, an independent check of the complex step.
+
+--cs-from takes the complex-step values of an earlier output of this script
+instead of recomputing them (they do not depend on the central differences).
 
 Each parameter is one job, run in a child process, whose result is kept in
 --partial so that an interrupted run resumes where it stopped.
 
 Calls only oracle/; writes tests/golden/adjoint_512x1024_grad.json.
     python tests/golden/make_adjoint_golden.py --partial DIR [--jobs 3 --threads 2]
+        [--cs-from tests/golden/adjoint_512x1024_grad.json]
 """
 import argparse
 import json
@@ -34,7 +39,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 NAME = "adjoint_512x1024"
-FD_DEFAULT = "rho_s[0],rho_s[9],tau,gmag"
+FD_DEFAULT = "all"
 
 
 def _setup():
@@ -51,7 +56,7 @@ def _mean_height(o, imag=False):
     return float(o.particles(imag=imag)["X"][:, 1].mean())
 
 
-def run_one(k, steps, partial, do_fd):
+def run_one(k, steps, partial, do_fd, cs_from=None):
     """Complex-step (and optionally central-difference) derivative for parameter k."""
     from oracle import oracle as O
 
@@ -65,10 +70,15 @@ def run_one(k, steps, partial, do_fd):
     else:
         seed["d_gmag"] = 1.0
     t0 = time.time()
-    oc = O.Oracle(cfg, parts, complex_step=seed)
-    oc.step(steps)
-    cs = _mean_height(oc, imag=True) / seed["h"]
-    del oc
+    if cs_from:
+        prev = json.load(open(cs_from))
+        assert prev["steps"] == steps and prev["params"][k] == name
+        cs = prev["grad_complex_step"][k]
+    else:
+        oc = O.Oracle(cfg, parts, complex_step=seed)
+        oc.step(steps)
+        cs = _mean_height(oc, imag=True) / seed["h"]
+        del oc
     fd = None
     if do_fd:
         base = np.load(os.path.join(partial, "base.npz"))
@@ -103,16 +113,17 @@ def main():
     ap.add_argument("--partial", required=True, help="directory for per-parameter results")
     ap.add_argument("--jobs", type=int, default=3)
     ap.add_argument("--threads", type=int, default=2, help="OpenMP threads per job")
-    ap.add_argument("--fd", default=FD_DEFAULT, help="parameters that also get central differences")
+    ap.add_argument("--fd", default=FD_DEFAULT, help="'all' or the parameters that get central differences")
+    ap.add_argument("--cs-from", default=None, help="reuse the complex-step values of this earlier output")
     ap.add_argument("--one", type=int, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                   f"{NAME}_grad.json"))
     args = ap.parse_args()
     os.makedirs(args.partial, exist_ok=True)
-    fd_names = set(s for s in args.fd.split(",") if s)
     cfg, parts, gmag, names, values = _setup()
+    fd_names = set(names) if args.fd == "all" else set(s for s in args.fd.split(",") if s)
     if args.one is not None:
-        run_one(args.one, args.steps, args.partial, names[args.one] in fd_names)
+        run_one(args.one, args.steps, args.partial, names[args.one] in fd_names, args.cs_from)
         return
 
     from oracle import oracle as O
@@ -136,7 +147,7 @@ def main():
 
     def job(k):
         cmd = [sys.executable, os.path.abspath(__file__), "--one", str(k), "--steps", str(args.steps),
-               "--partial", args.partial, "--fd", args.fd]
+               "--partial", args.partial, "--fd", args.fd] + (["--cs-from", args.cs_from] if args.cs_from else [])
         r = subprocess.run(cmd, env=env)
         res = json.load(open(os.path.join(args.partial, f"p{k:02d}.json"))) if r.returncode == 0 else None
         print(f"{names[k]}: rc {r.returncode} {res} ({time.time() - t0:.0f} s)", flush=True)

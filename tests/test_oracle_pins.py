@@ -307,8 +307,8 @@ def test_collision_force_wall():
 
 # ---------------------------------------------------------- whole step vs brute force
 
-def _compare_with_brute(kind, n, periodic, parts, g, steps, seed):
-    cfg = dict(lattice=kind, n=n, periodic=periodic, tau=0.7, g=g, eps_p=2.0, eps_w=1.0, delta=1.0)
+def _compare_with_brute(kind, n, periodic, parts, g, steps, seed, K=1):
+    cfg = dict(lattice=kind, n=n, periodic=periodic, tau=0.7, g=g, eps_p=2.0, eps_w=1.0, delta=1.0, K=K)
     o = O.Oracle(cfg, parts)
     Q = 9 if kind == "D2Q9" else 19
     shp = (n[2] if kind == "D3Q19" else 1, n[1], n[0])
@@ -316,7 +316,7 @@ def _compare_with_brute(kind, n, periodic, parts, g, steps, seed):
     o.set_f(f0)
     o.reset_particles(parts)
     st = brute.initial_state(kind, n if len(n) == 3 else tuple(n) + (1,), periodic, 0.7, 0.0, 1.0, g, (0, 0, 0),
-                             parts)
+                             parts, K=K)
     for nd in st["f"]:
         x, y, z = nd
         st["f"][nd] = list(f0[z, y, x])
@@ -355,6 +355,83 @@ def test_oracle_vs_brute_d3q19():
     parts = [dict(shape="sphere", rho_s=1.6, a=1.6, x=(2.0, 2.1, 2.3)),
              dict(shape="sphere", rho_s=1.4, a=1.4, x=(3.4, 3.0, 3.9))]
     _compare_with_brute("D3Q19", (5, 5, 6), (0, 1, 0), parts, (0.0, 0.0, -1e-3), 2, 2)
+
+
+@pytest.mark.parametrize("K", [2, 3])
+def test_oracle_vs_brute_substeps_d2q9(K):
+    """Algorithm 1 with K sub-steps (sec. 2.4): the prediction by U_bar/K, the
+    correction with (1/K)^2 and the forces at Y^{k-1} and Y*, over three whole
+    steps against the brute-force transcription, bodies in contact."""
+    parts = [dict(shape="disk", rho_s=1.6, a=2.2, x=(3.1, 3.2)),
+             dict(shape="ellipse", rho_s=1.3, a=2.5, b=1.2, x=(7.6, 4.4), theta=0.4)]
+    st = _compare_with_brute("D2Q9", (9, 8, 1), (1, 0, 0), parts, (0.0, -1e-3, 0.0), 3, 1, K=K)
+    assert any(abs(a) > 1e-8 for q in st["parts"] for a in q["A"])
+
+
+@pytest.mark.parametrize("K", [2, 3])
+def test_oracle_vs_brute_substeps_d3q19(K):
+    parts = [dict(shape="sphere", rho_s=1.6, a=1.6, x=(2.0, 2.1, 2.3)),
+             dict(shape="sphere", rho_s=1.4, a=1.4, x=(3.4, 3.0, 3.9))]
+    st = _compare_with_brute("D3Q19", (5, 5, 6), (0, 1, 0), parts, (0.0, 0.0, -1e-3), 2, 2, K=K)
+    assert any(abs(a) > 1e-8 for q in st["parts"] for a in q["A"])
+
+
+@pytest.mark.parametrize("K", [1, 3])
+def test_algorithm1_literal_collision_acceleration(K):
+    """Algorithm 1 defines A^{n+1} = 2(X^{n+1} - X^n - U_bar) with
+    U_bar = (U^n + U^{n-1})/2.  The oracle takes the bracket as the summed
+    correction displacements; here the literal difference of the recorded
+    positions must give the same A to round-off of the positions, in a run
+    where the contact forces are strong."""
+    kinds = [("disk", 5.0, 5.0)] * 5 + [("ellipse", 6.0, 3.0)] * 3
+    from paper_2511_01629_amd.workloads import place
+
+    parts = place((64, 96), kinds, seed=7, rho_range=(1.2, 1.8), upper_axis=1, gap=0.3, margin=0.3)
+    cfg = dict(lattice="D2Q9", n=(64, 96, 1), periodic=(0, 0, 0), tau=0.6, g=(0.0, -2e-4, 0.0), K=K)
+    o = O.Oracle(cfg, parts)
+    U_init = o.particles()["U"].copy()  # U^{-1} = U^0
+    rec = o.step(60, record=True)  # per step n: X^n theta U^n omega A^n N
+    X, U, A = rec[:, :, 0:3], rec[:, :, 4:7], rec[:, :, 10:13]
+    Uprev = np.concatenate([U_init[None], U[:-1]])
+    Ubar = 0.5 * (U + Uprev)
+    A_lit = 2.0 * (X[1:] - X[:-1] - Ubar[:-1])
+    ulp = np.spacing(np.abs(X).max())
+    assert np.abs(A[1:] - A_lit).max() <= 8 * K * ulp
+    assert np.abs(A[1:]).max() > 1e4 * ulp  # contacts act: the pin is not trivially 0 = 0
+    assert np.all(A[0] == 0.0)
+
+
+def test_algorithm1_free_flight_substeps():
+    """With no contact, K = 3 sub-steps move by U_bar/3 three times:
+    X^{n+1} = X^n + U_bar to round-off, and A^{n+1} = 0 exactly (every
+    correction is zero)."""
+    cfg = dict(lattice="D2Q9", n=(60, 50), periodic=(1, 1, 0), tau=0.8, u0=(0.02, -0.01), K=3)
+    o = O.Oracle(cfg, [dict(shape="disk", rho_s=1.0, a=6.0, x=(30.25, 24.5))])
+    rec = o.step(4, record=True)
+    X, U, A = rec[:, 0, 0:3], rec[:, 0, 4:7], rec[:, 0, 10:13]
+    assert np.abs(U[:, :2] - [0.02, -0.01]).max() < 1e-16
+    assert np.abs(X[1:, :2] - X[:-1, :2] - U[:-1, :2]).max() <= 4 * np.spacing(30.0)
+    assert np.all(A == 0.0)
+
+
+@pytest.mark.parametrize("gravity_form,expect", [(0, 1.0 - 1.0 / 1.5), (1, 1.5 - 1.0)])
+def test_gravity_form_momentum(gravity_form, expect):
+    """The solid-node acceleration of sec. 2.1 (eq. 5-8): a = (1 - rho_f/rho_s) g
+    (the default reading) or (rho_s/rho_f - 1) g (gravity_form = 1).  The
+    collision with the Guo force leaves the momentum sum f~ c = sum f c + a at
+    every node (eq. 14-15; the penalization carries none), so from rest (f = 0)
+    in a fully periodic box, where streaming is a permutation, the lattice
+    momentum after one step is N_i b g with b the form's factor."""
+    g = (0.0, -3e-4, 0.0)
+    cfg = dict(lattice="D2Q9", n=(40, 36), periodic=(1, 1, 0), tau=0.7, g=g, gravity_form=gravity_form)
+    o = O.Oracle(cfg, [dict(shape="disk", rho_s=1.5, a=6.0, x=(20.0, 18.0))])
+    N = int(o.particles()["N"][0])
+    o.step(1)
+    c, _, _ = _lat("D2Q9")
+    P = np.einsum("zyxa,ak->k", o.f(), c)
+    assert N > 100
+    assert abs(P[1] - N * expect * g[1]) <= 1e-12 * abs(N * expect * g[1])
+    assert abs(P[0]) < 1e-17
 
 
 # ---------------------------------------------------------- conservation and textbook flows
