@@ -51,7 +51,7 @@ enum {
     LBM_ENOMEM = -2,    /* device allocation failed, or the workspace is too small */
     LBM_EDEVICE = -3,   /* a HIP call failed                                      */
     LBM_ESTATE = -4,    /* call out of order (e.g. no particles set yet)          */
-    LBM_EUNSTABLE = -5, /* a velocity became non-finite or |u| > 0.3              */
+    LBM_EUNSTABLE = -5, /* a velocity became non-finite or |u| > 0.3 (the sentinel) */
     LBM_EDOMAIN = -6    /* a particle left the box or lost all its nodes          */
 };
 
@@ -93,6 +93,8 @@ typedef struct {
                                eq. 13 at the wall velocity).  Nonzero only on the y axis, or
                                the y or z axis in 3D, tangential (no normal component), with
                                every other axis periodic; all zero: fixed walls.            */
+    int32_t check_every;    /* lbm_step reads the device sentinel every this many steps (of the
+                               absolute step count); 0 selects 64, a negative value never   */
 } lbm_config;
 
 typedef struct {
@@ -128,13 +130,34 @@ int lbm_destroy(lbm_ctx *ctx);
  * set, the lowest index owns a shared node, FP64 tests with no contraction,
  * minimum image on periodic axes), measure U^0 and omega^0 on the current
  * populations (eq. 22a-b), set U^{-1} = U^0, omega^{-1} = omega^0, A = 0.
- * EINVAL: n > max_particles, a bad shape/size, a body crossing a wall, a
- * radius too large for a periodic axis (a + 2 >= n/2), or a body with no node. */
+ * Any earlier differentiated run is discarded (lbm_backward then gives ESTATE).
+ * EINVAL, with the context unchanged: n > max_particles, a bad shape/size, a
+ * body crossing a wall, a radius too large for a periodic axis
+ * (a + 2 >= n/2), or a body that would own no node (its shape lies inside
+ * lower-index bodies; the host counts the nodes each body claims with the
+ * inclusion test of the device before anything changes).  Should the device
+ * still find a body with no node (an ellipse whose boundary passes through a
+ * node, where host and device cos/sin may differ in the last bit), the call
+ * returns EINVAL and leaves the context with no particles. */
 int lbm_set_particles(lbm_ctx *ctx, const lbm_particle *host_particles, int32_t n);
 
 /* Queue nsteps >= 0 full time steps (stream-collide-penalize, sums,
  * Algorithm 1, re-rasterisation).  With no particles set, only the lattice
- * update runs (pure fluid). */
+ * update runs (pure fluid).
+ *
+ * Sentinel: the lattice kernel raises a device flag when a node velocity is
+ * non-finite or exceeds 0.3 in magnitude (unstable), and the particle kernels
+ * one when a centre leaves the box or a body loses all its nodes (domain).
+ * After every check_every-th step (absolute count) lbm_step queues a copy of
+ * the flags to pinned host memory; at the next such step it waits for that
+ * copy (so the host never runs more than 2 check_every steps ahead of the
+ * device) and returns LBM_EUNSTABLE or LBM_EDOMAIN, queueing nothing more,
+ * if a flag was set: a diverging run stops within 2 check_every steps of the
+ * step that tripped it, and its state stays readable.  The particle kernels
+ * of the fused K = 1 step skip partner pairs farther apart than
+ * R_i + R_j + delta + 0.6, which is exact while the sentinel holds (every
+ * |u|, hence every |U_bar|, is at most 0.3); on the steps between a trip and
+ * the stop such forces may be missed. */
 int lbm_step(lbm_ctx *ctx, int64_t nsteps);
 
 /* As lbm_step, and write a per-step record of every particle into host_rec:
@@ -151,6 +174,12 @@ int lbm_sync(lbm_ctx *ctx);
  * may be NULL.  N = n[0] n[1] n[2], x fastest. */
 int lbm_get_fields(lbm_ctx *ctx, double *host_u, double *host_p, int32_t *host_owner);
 
+/* The same fields into device memory of the context's device (e.g. torch
+ * tensors), same layouts; any pointer may be NULL.  Queued on the context
+ * stream and not waited for: the caller orders its reads on that stream.
+ * The sentinel is not read (lbm_sync does). */
+int lbm_get_fields_device(lbm_ctx *ctx, double *dev_u, double *dev_p, int32_t *dev_owner);
+
 /* Populations f^n of the current step (after streaming, before collision),
  * host memory, FP64, direction-major [Q][N]. */
 int lbm_get_populations(lbm_ctx *ctx, double *host_f);
@@ -163,6 +192,45 @@ int lbm_set_populations(lbm_ctx *ctx, const double *host_f);
 /* Current particle state into host_particles[0..n): centre, orientation, U^n
  * and omega^n measured now, U^{n-1}, omega^{n-1}, A^n, node count. */
 int lbm_get_particles(lbm_ctx *ctx, lbm_particle *host_particles, int32_t n);
+
+/* ---- parameters and the state between steps ----
+ *
+ * lbm_set_params: replace the solid densities (host rho_s[0..np), or NULL to
+ * keep them), tau (> 1/2; a value <= 0 keeps it; alpha follows it when alpha
+ * <= 0 was given at lbm_create) and the gravity vector (host g[3], or NULL
+ * to keep it).  They act from the next step on: the solid-node acceleration
+ * (1 - rho_f/rho_s,i) g + A_i (sec. 2.1, 2.4), the collision constants C_i of
+ * sec. 2.3 and the BGK rate (eq. 10).  Right after lbm_set_particles (or a
+ * load of a state saved then), U^0 and omega^0 are measured again with the
+ * new parameters and U^{-1} = U^0, as lbm_set_particles would have.  Any
+ * earlier differentiated run is discarded.  EINVAL (nothing changed): tau
+ * <= 1/2, a fixed alpha above 1/tau, a non-positive or non-finite density or
+ * a non-finite g.  Waits for the stream.
+ *
+ * lbm_state_size / lbm_save_state / lbm_load_state: the whole state that the
+ * next step starts from, as one byte blob (the state Algorithm 1 carries
+ * from step to step, sec. 2.4):
+ *   header (lattice, storage, sizes, periodic axes, particle count, step
+ *   counter, tau, g, whether the state is the one right after
+ *   lbm_set_particles); per particle rho_s, a, b, shape, X^n, theta^n,
+ *   U^{n-1}, omega^{n-1}, A^n (FP64); then the populations in the storage
+ *   type, raw.
+ * The indicator is not stored: it is a function of X^n and theta^n (eq. 9)
+ * and is rasterised again on load, bit for bit as the step produced it.
+ * `buf` may be host or device memory (any address the HIP runtime
+ * recognises; unified addressing); lbm_state_size gives its size in bytes.
+ * Save waits for the stream.  Load validates the header against the context
+ * (same lattice, storage, sizes and periodic axes; particle count <=
+ * max_particles; else EINVAL and nothing changes), installs the parameters
+ * and the particles (as lbm_set_particles, without measuring U), the
+ * populations and the step counter, and clears the sentinel; the sentinel is
+ * not stored.  run(2n) equals run(n) + save + load (into this or another
+ * context of the same configuration) + run(n), bit for bit.  A loaded state
+ * with non-finite populations trips the sentinel on the first step. */
+int lbm_set_params(lbm_ctx *ctx, const double *host_rho_s, double tau, const double *host_g);
+int lbm_state_size(const lbm_ctx *ctx, size_t *bytes);
+int lbm_save_state(lbm_ctx *ctx, void *buf);
+int lbm_load_state(lbm_ctx *ctx, const void *buf);
 
 /* ---- differentiated runs (extension beyond the paper) ----
  * Gradients of a loss of the final particle centres with respect to the
@@ -186,6 +254,9 @@ int lbm_get_particles(lbm_ctx *ctx, lbm_particle *host_particles, int32_t n);
  * seeds.  The snapshot memory is released by lbm_set_particles or
  * lbm_destroy. */
 int lbm_forward_checkpointed(lbm_ctx *ctx, int64_t nsteps, int32_t every);
+/* (A differentiated run may also start right after lbm_load_state of a state
+ * saved right after lbm_set_particles; lbm_set_params, lbm_set_particles and
+ * lbm_load_state discard the run's checkpoints.) */
 int lbm_backward(lbm_ctx *ctx, const double *dL_dX, double *g_rho_s, double *g_tau, double *g_gmag);
 
 /* Per-kernel timing with HIP events (measurement aid).  While enabled,

@@ -8,6 +8,13 @@ hand-written adjoint (lbm_backward), so gradients of any loss of the final
 centres flow to the solid densities, tau and |g|, each on its input's device
 and dtype (a plain number for tau or |g| gets no gradient).  Every step runs in the HIP
 library; this module only marshals tensors.
+
+A Run keeps one library context: its first forward creates it and saves, on
+the device, the state right after the particles were set; every forward
+loads that state back and sets the parameters (lbm_set_params, which also
+measures U^0 again with them), so no context is rebuilt per forward.  The
+checkpoints belong to the context, so a Run holds one differentiated run at
+a time: backward through an earlier forward of the same Run raises.
 """
 from dataclasses import dataclass, field
 
@@ -26,6 +33,16 @@ class Run:
     storage: str = "f32"
     device: int = 0
     last: dict = field(default_factory=dict)
+    sim: object = field(default=None, repr=False)   # the library context
+    start: object = field(default=None, repr=False)  # its state right after set_particles (device bytes)
+    generation: int = 0                               # forwards run so far
+
+
+def _context(run):
+    if run.sim is None:
+        run.sim = lbm.Simulation(run.cfg, run.particles, storage=run.storage, device=run.device)
+        run.start = run.sim.save_state(on_device=True)
+    return run.sim
 
 
 def _number(x):
@@ -36,18 +53,19 @@ class LbmTrajectory(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rho_s, tau, gmag, run):
         rho = rho_s.detach().cpu().double().numpy()
-        cfg = dict(run.cfg)
-        cfg["tau"] = _number(tau)
-        g = np.asarray(cfg.get("g", (0.0, 0.0, 0.0)), dtype=np.float64)
+        g = np.asarray(run.cfg.get("g", (0.0, 0.0, 0.0)), dtype=np.float64)
         g0 = np.linalg.norm(g)
         if g0 == 0.0:
             raise ValueError("the gravity direction is taken from cfg['g'], which is zero")
-        cfg["g"] = tuple(g / g0 * _number(gmag))
-        parts = [dict(p, rho_s=float(r)) for p, r in zip(run.particles, rho)]
-        sim = lbm.Simulation(cfg, parts, storage=run.storage, device=run.device)
+        sim = _context(run)
+        sim.load_state(run.start)
+        sim.set_params(rho_s=rho, tau=_number(tau), g=g / g0 * _number(gmag))
         sim.forward_checkpointed(run.steps, run.every)
         X = sim.particles()["X"]
+        run.generation += 1
         ctx.sim = sim
+        ctx.run = run
+        ctx.generation = run.generation
         # each gradient goes back on its input's device and dtype (inputs may
         # be CUDA tensors or plain numbers)
         ctx.like = [(t.device, t.dtype) if torch.is_tensor(t) else None for t in (rho_s, tau, gmag)]
@@ -57,6 +75,8 @@ class LbmTrajectory(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gX):
+        if ctx.generation != ctx.run.generation:
+            raise RuntimeError("a later forward of the same Run replaced this run's checkpoints")
         g_rho, g_tau, g_g = ctx.sim.backward(gX.detach().cpu().double().numpy())
         out = []
         for k, g in enumerate((np.ascontiguousarray(g_rho), g_tau, g_g)):

@@ -11,6 +11,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <string>
+#include <unordered_set>
 #include <vector>
 
 #include "ctx.h"
@@ -378,6 +380,10 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
     c->slots_bytes = 0;
     c->slot_stride = c->slot_mx = c->slot_my = c->slot_mz = c->slot_sy = c->slot_sz = c->fused = 0;
     c->epoch = 0;
+    c->check_every = cfg->check_every == 0 ? 64 : cfg->check_every;
+    c->hflags = nullptr;
+    c->poll_ev = nullptr;
+    c->poll_pending = 0;
     c->prof = 0;
     c->tev[0] = c->tev[1] = nullptr;
     c->tev_used = 0;
@@ -391,9 +397,18 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
         g_create_err = std::string("hipSetDevice: ") + hipGetErrorString(e);
         return LBM_EDEVICE;
     }
+    if ((e = hipHostMalloc((void **)&c->hflags, 2 * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->poll_ev, hipEventDisableTiming)) != hipSuccess) {
+        if (c->hflags) (void)hipHostFree(c->hflags);
+        delete c;
+        g_create_err = std::string("sentinel set-up: ") + hipGetErrorString(e);
+        return LBM_EDEVICE;
+    }
     const Layout L = layout_for(&c->cfg, Q, d, N);
     if (cfg->workspace) {
         if (cfg->workspace_bytes < L.total || ((uintptr_t)cfg->workspace % ALIGN) != 0) {
+            (void)hipHostFree(c->hflags);
+            (void)hipEventDestroy(c->poll_ev);
             delete c;
             g_create_err = "workspace too small or not 256-byte aligned";
             return LBM_ENOMEM;
@@ -404,6 +419,8 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
     } else {
         e = hipMalloc(&c->ws, L.total);
         if (e != hipSuccess) {
+            (void)hipHostFree(c->hflags);
+            (void)hipEventDestroy(c->poll_ev);
             delete c;
             g_create_err = std::string("hipMalloc: ") + hipGetErrorString(e);
             return LBM_ENOMEM;
@@ -422,6 +439,8 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
         (e = hipMemsetAsync(c->P.hi, 0xFF, (size_t)c->cap * 3 * sizeof(int32_t), c->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
         if (c->own_mem) (void)hipFree(c->ws);
+        (void)hipHostFree(c->hflags);
+        (void)hipEventDestroy(c->poll_ev);
         delete c;
         g_create_err = std::string("initialisation: ") + hipGetErrorString(e);
         return LBM_EDEVICE;
@@ -440,24 +459,91 @@ int lbm_destroy(lbm_ctx *c)
     if (c->slots) (void)hipFree(c->slots);
     free_grad(c);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->poll_ev) (void)hipEventDestroy(c->poll_ev);
+    if (c->hflags) (void)hipHostFree(c->hflags);
     delete c;
     return LBM_OK;
 }
 
-int lbm_set_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
+} // extern "C"
+
+namespace {
+
+// The inclusion test of eq. (9) as the device evaluates it (raster_items in
+// particles.hip): the same operation order, every product and sum rounded on
+// its own (no contraction).
+bool host_inside(int shape, double a, double b, double cs, double sn, double dx, double dy, double dz)
 {
-    if (!c) return LBM_EINVAL;
+#pragma clang fp contract(off)
+    if (shape == LBM_DISK) return dx * dx + dy * dy <= a * a;
+    if (shape == LBM_SPHERE) return (dx * dx + dy * dy) + dz * dz <= a * a;
+    const double xi = cs * dx + sn * dy;
+    const double eta = (-sn) * dx + cs * dy;
+    return (b * b) * (xi * xi) + (a * a) * (eta * eta) <= (a * a) * (b * b);
+}
+
+// Number of nodes each of the n particles would own (lowest index wins),
+// counted on the host over each scan box (centre_box of the device: the
+// bounding radius plus two nodes, clipped at walls, unwrapped on periodic
+// axes).  Lets lbm_set_particles and lbm_load_state reject a body with no
+// node before anything on the device changes.
+std::vector<int> host_claims(const lbm_ctx *c, const lbm_particle *p, int n)
+{
+    const Geom &g = c->geo;
+    const int nn[3] = {g.nx, g.ny, g.nz};
+    const int per[3] = {g.per_x, g.per_y, g.per_z};
+    const int d = c->d;
+    std::vector<int> count(n, 0);
+    std::unordered_set<int64_t> claimed;
+    std::vector<int64_t> mine;
+    for (int i = 0; i < n; ++i) {
+        const lbm_particle &q = p[i];
+        const double b = q.shape == LBM_ELLIPSE ? q.b : q.a;
+        const double cs = q.shape == LBM_ELLIPSE ? cos(q.theta) : 1.0, sn = q.shape == LBM_ELLIPSE ? sin(q.theta) : 0.0;
+        int lo[3], hi[3];
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = hi[k] = 0;
+            if (k >= d) continue;
+            lo[k] = (int)floor(q.x[k] - q.a) - 2;
+            hi[k] = (int)ceil(q.x[k] + q.a) + 2;
+            if (!per[k]) {
+                lo[k] = std::max(lo[k], 0);
+                hi[k] = std::min(hi[k], nn[k] - 1);
+            }
+        }
+        mine.clear();
+        for (int z = lo[2]; z <= hi[2]; ++z)
+            for (int y = lo[1]; y <= hi[1]; ++y)
+                for (int x = lo[0]; x <= hi[0]; ++x) {
+                    const double dz = d == 3 ? (double)z - q.x[2] : 0.0;
+                    if (!host_inside(q.shape, q.a, b, cs, sn, (double)x - q.x[0], (double)y - q.x[1], dz)) continue;
+                    auto wrapn = [](int v, int m) { return v < 0 ? v + m : (v >= m ? v - m : v); };
+                    const int64_t id = wrapn(x, nn[0]) + (int64_t)nn[0] * (wrapn(y, nn[1]) + (int64_t)nn[1] * wrapn(z, nn[2]));
+                    if (!claimed.count(id)) ++count[i];
+                    mine.push_back(id);
+                }
+        claimed.insert(mine.begin(), mine.end());
+    }
+    return count;
+}
+
+// Host checks of a particle set (everything lbm_set_particles rejects with the
+// context unchanged).
+int check_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
+{
     if (n < 0 || n > c->cfg.max_particles) return fail(c, LBM_EINVAL, "particle count exceeds max_particles");
     if (n > 0 && !p) return fail(c, LBM_EINVAL, "particles is NULL");
-    const int d = c->d, cap = c->cap;
+    const int d = c->d;
     const int nn[3] = {c->geo.nx, c->geo.ny, c->geo.nz};
     const int per[3] = {c->geo.per_x, c->geo.per_y, c->geo.per_z};
     for (int i = 0; i < n; ++i) {
         const lbm_particle &q = p[i];
         const bool ok_shape = (d == 2 && (q.shape == LBM_DISK || q.shape == LBM_ELLIPSE)) || (d == 3 && q.shape == LBM_SPHERE);
         if (!ok_shape) return fail(c, LBM_EINVAL, "shape not valid for this lattice");
-        if (!(q.rho_s > 0) || !(q.a >= 1.0)) return fail(c, LBM_EINVAL, "rho_s must be > 0 and a >= 1");
+        if (!(q.rho_s > 0) || !isfinite(q.rho_s) || !(q.a >= 1.0) || !isfinite(q.a))
+            return fail(c, LBM_EINVAL, "rho_s must be > 0 and a >= 1");
         if (q.shape == LBM_ELLIPSE && !(q.b >= 1.0 && q.b <= q.a)) return fail(c, LBM_EINVAL, "ellipse needs a >= b >= 1");
+        if (q.shape == LBM_ELLIPSE && !isfinite(q.theta)) return fail(c, LBM_EINVAL, "non-finite orientation");
         for (int k = 0; k < d; ++k) {
             if (!isfinite(q.x[k])) return fail(c, LBM_EINVAL, "non-finite centre");
             if (per[k]) {
@@ -468,36 +554,67 @@ int lbm_set_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
             }
         }
     }
-    (void)hipSetDevice(c->device);
-    // clear the previous indicator
+    const std::vector<int> cnt = host_claims(c, p, n);
+    for (int i = 0; i < n; ++i)
+        if (cnt[i] == 0)
+            return fail(c, LBM_EINVAL, "particle " + std::to_string(i) +
+                                           " would own no lattice node (its shape lies inside lower-index particles)");
+    return LBM_OK;
+}
+
+// Collision constant C_i of sec. 2.3 for the current g and form.
+double coll_const(const lbm_ctx *c, const lbm_particle &q)
+{
+    const double b = q.shape == LBM_ELLIPSE ? q.b : q.a;
+    const double V = q.shape == LBM_DISK      ? M_PI * q.a * q.a
+                     : q.shape == LBM_ELLIPSE ? M_PI * q.a * b
+                                              : 4.0 / 3.0 * M_PI * q.a * q.a * q.a;
+    const double Cl = (q.rho_s - c->rp.rho_f) * c->rp.gmag;
+    return c->rp.cform == 1 ? Cl : Cl * V;
+}
+
+// Upload rho_s and C_i of the current particles (after a change of rho_s or g).
+int upload_constants(lbm_ctx *c)
+{
+    const int cap = c->cap;
+    std::vector<double> rho(cap, 1.0), C(cap, 0.0);
+    for (int i = 0; i < c->np; ++i) {
+        rho[i] = c->host_parts[i].rho_s;
+        C[i] = coll_const(c, c->host_parts[i]);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->P.rho_s, rho.data(), sizeof(double) * cap, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->P.Cc, C.data(), sizeof(double) * cap, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream)); // the host vectors go out of scope
+    return LBM_OK;
+}
+
+// Install n checked particles: clear the previous indicator, upload the
+// constants, centres, orientations and A = 0, choose the slot layout of the
+// fused-sums step.  The caller rasterises and sets the velocities.
+int install_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
+{
+    const int d = c->d, cap = c->cap;
     if (c->np > 0) HIPCHK(c, launch_raster_clear(c));
-    // host images of the particle arrays
-    std::vector<double> X(3 * cap, 0), th(cap, 0), z3(3 * cap, 0), rho(cap, 1), a(cap, 1), b(cap, 1), C(cap, 0);
+    std::vector<double> X(3 * cap, 0), th(cap, 0), z3(3 * cap, 0), a(cap, 1), b(cap, 1);
     std::vector<int32_t> shape(cap, 0);
     for (int i = 0; i < n; ++i) {
         for (int k = 0; k < d; ++k) X[3 * i + k] = p[i].x[k];
         th[i] = p[i].theta;
-        rho[i] = p[i].rho_s;
         a[i] = p[i].a;
         b[i] = p[i].shape == LBM_ELLIPSE ? p[i].b : p[i].a;
         shape[i] = p[i].shape;
-        const double V = p[i].shape == LBM_DISK      ? M_PI * p[i].a * p[i].a
-                         : p[i].shape == LBM_ELLIPSE ? M_PI * p[i].a * b[i]
-                                                     : 4.0 / 3.0 * M_PI * p[i].a * p[i].a * p[i].a;
-        const double Cl = (p[i].rho_s - c->rp.rho_f) * c->rp.gmag;
-        C[i] = c->rp.cform == 1 ? Cl : Cl * V;
     }
     const size_t b3 = sizeof(double) * 3 * cap, b1 = sizeof(double) * cap;
     HIPCHK(c, hipMemcpyAsync(c->P.X, X.data(), b3, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->P.theta, th.data(), b1, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->P.A, z3.data(), b3, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->P.rho_s, rho.data(), b1, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->P.a, a.data(), b1, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->P.b, b.data(), b1, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->P.Cc, C.data(), b1, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->P.shape, shape.data(), sizeof(int32_t) * cap, hipMemcpyHostToDevice, c->stream));
     c->np = n;
     c->host_parts.assign(p, p + n);
+    int rc = upload_constants(c); // also waits for the copies above
+    if (rc) return rc;
     // fused-sums step (K = 1): per-particle slot tables keyed by the wrapped
     // row and the wavefront index (slot_of).  A scan box spans at most
     // ceil(2a) + 7 nodes per axis; the key sizes are powers of two at least
@@ -549,25 +666,79 @@ int lbm_set_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
             c->fused = 1;
         }
     }
-    // indicator, acceleration table, U^0 and omega^0 on the current populations
-    HIPCHK(c, launch_rigid_raster(c, 0));
-    HIPCHK(c, launch_fields(c, c->f[c->cur], c->usol, nullptr, 1));
-    HIPCHK(c, launch_reduce(c, 0, nullptr));
-    // U^{-1} = U^0.  With fused sums U^{n-1} is read from U itself (U^n goes to
-    // Unext, swapped in after the step), so U_prev is an alias of U.  The alias
-    // may outlive a later set-up without fused sums; that is harmless because
+    // With fused sums U^{n-1} is read from U itself (U^n goes to Unext,
+    // swapped in after the step), so U_prev is an alias of U.  The alias may
+    // outlive a later set-up without fused sums; that is harmless because
     // every path leaves U_prev equal to U between steps, and the sums kernel
     // reads U_prev before it writes U.
     if (c->fused) c->P.Uprev = c->P.U;
-    else if (c->P.Uprev != c->P.U) HIPCHK(c, hipMemcpyAsync(c->P.Uprev, c->P.U, b3, hipMemcpyDeviceToDevice, c->stream));
+    return LBM_OK;
+}
+
+// U^0 and omega^0 on the current populations (eq. 22a-b), then U^{-1} = U^0
+// and omega^{-1} = omega^0 (the start of Algorithm 1).
+int measure_initial(lbm_ctx *c)
+{
+    const size_t b3 = sizeof(double) * 3 * c->cap;
+    HIPCHK(c, launch_fields(c, c->f[c->cur], c->usol, nullptr, 1));
+    HIPCHK(c, launch_reduce(c, 0, nullptr));
+    if (c->P.Uprev != c->P.U) HIPCHK(c, hipMemcpyAsync(c->P.Uprev, c->P.U, b3, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->P.Wprev, c->P.W, b3, hipMemcpyDeviceToDevice, c->stream));
-    std::vector<int32_t> Nn(cap, 0);
-    HIPCHK(c, hipMemcpyAsync(Nn.data(), c->P.N, sizeof(int32_t) * cap, hipMemcpyDeviceToHost, c->stream));
+    return LBM_OK;
+}
+
+// After the device rasterised: every body must own a node.  The host count
+// agrees with the device except where an ellipse boundary passes through a
+// node and the two cos/sin differ in the last bit; then the particles are
+// taken out again (the context is left with none).
+int check_device_claims(lbm_ctx *c)
+{
+    std::vector<int32_t> Nn(c->cap, 0);
+    HIPCHK(c, hipMemcpyAsync(Nn.data(), c->P.N, sizeof(int32_t) * c->cap, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int i = 0; i < n; ++i)
-        if (Nn[i] == 0) return fail(c, LBM_EINVAL, "a particle covers no lattice node");
+    for (int i = 0; i < c->np; ++i)
+        if (Nn[i] == 0) {
+            HIPCHK(c, launch_raster_clear(c));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            c->np = 0;
+            c->fused = 0;
+            c->host_parts.clear();
+            c->fresh = 0;
+            return fail(c, LBM_EINVAL, "a particle covers no lattice node on the device (a boundary tie); "
+                                       "the context now holds no particles");
+        }
+    return LBM_OK;
+}
+
+// Host side of the sentinel: wait for the queued copy of the device flags
+// and report what it read.
+int poll_result(lbm_ctx *c)
+{
+    c->poll_pending = 0;
+    HIPCHK(c, hipEventSynchronize(c->poll_ev));
+    if (c->hflags[0]) return fail(c, LBM_EUNSTABLE, "velocity non-finite or above 0.3 (sentinel read inside lbm_step)");
+    if (c->hflags[1])
+        return fail(c, LBM_EDOMAIN, "a particle left the box or lost all its nodes (sentinel read inside lbm_step)");
+    return LBM_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int lbm_set_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
+{
+    if (!c) return LBM_EINVAL;
+    (void)hipSetDevice(c->device);
+    int rc = check_particles(c, p, n);
+    if (rc) return rc;
+    free_grad(c); // checkpoints of an earlier differentiated run no longer match
+    if ((rc = install_particles(c, p, n))) return rc;
+    // indicator and acceleration table (A = 0), U^0, omega^0 on the current populations
+    HIPCHK(c, launch_rigid_raster(c, 0));
+    if ((rc = measure_initial(c))) return rc;
+    if ((rc = check_device_claims(c))) return rc;
     c->fresh = 1;
-    free_grad(c);
     return LBM_OK;
 }
 
@@ -575,7 +746,271 @@ int lbm_step(lbm_ctx *c, int64_t nsteps)
 {
     if (!c || nsteps < 0) return c ? fail(c, LBM_EINVAL, "nsteps < 0") : LBM_EINVAL;
     (void)hipSetDevice(c->device);
-    return step_impl(c, nsteps, nullptr);
+    const int64_t k = c->check_every;
+    if (k <= 0) return step_impl(c, nsteps, nullptr);
+    int64_t done = 0;
+    while (done < nsteps) {
+        const int64_t chunk = std::min(nsteps - done, k - c->step % k);
+        int rc = step_impl(c, chunk, nullptr);
+        if (rc) return rc;
+        done += chunk;
+        if (c->step % k) continue;
+        // a poll point: read the previous poll (the device has then finished
+        // every step but the last chunk), then queue this one
+        if (c->poll_pending && (rc = poll_result(c))) return rc;
+        HIPCHK(c, hipMemcpyAsync(c->hflags, c->flags, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipEventRecord(c->poll_ev, c->stream));
+        c->poll_pending = 1;
+    }
+    // a poll that has already completed is read without waiting
+    if (c->poll_pending && hipEventQuery(c->poll_ev) == hipSuccess) return poll_result(c);
+    return LBM_OK;
+}
+
+int lbm_get_fields_device(lbm_ctx *c, double *dev_u, double *dev_p, int32_t *dev_owner)
+{
+    if (!c) return LBM_EINVAL;
+    (void)hipSetDevice(c->device);
+    if (dev_u || dev_p) {
+        // the fields kernel writes both; a NULL one goes to the staging area
+        double *du = dev_u ? dev_u : c->staging, *dp = dev_p ? dev_p : c->staging + (size_t)3 * c->geo.N;
+        HIPCHK(c, launch_fields(c, c->f[c->cur], du, dp, 0));
+    }
+    if (dev_owner) HIPCHK(c, launch_owner_to_int(c, dev_owner));
+    return LBM_OK;
+}
+
+int lbm_set_params(lbm_ctx *c, const double *rho_s, double tau, const double *g)
+{
+    if (!c) return LBM_EINVAL;
+    (void)hipSetDevice(c->device);
+    const bool new_tau = tau > 0.0;
+    if (new_tau && !(tau > 0.5 && isfinite(tau))) return fail(c, LBM_EINVAL, "tau must exceed 1/2");
+    if (new_tau && !c->sp.alpha_tracks_tau && c->sp.alpha > 1.0 / tau * (1.0 + 1e-12))
+        return fail(c, LBM_EINVAL, "the fixed alpha would exceed 1/tau");
+    for (int i = 0; rho_s && i < c->np; ++i)
+        if (!(rho_s[i] > 0) || !isfinite(rho_s[i])) return fail(c, LBM_EINVAL, "densities must be positive and finite");
+    for (int k = 0; g && k < c->d; ++k)
+        if (!isfinite(g[k])) return fail(c, LBM_EINVAL, "gravity must be finite");
+    free_grad(c);
+    if (new_tau) {
+        c->cfg.tau = c->sp.tau = tau;
+        c->sp.omega = 1.0 / tau;
+        if (c->sp.alpha_tracks_tau) c->sp.alpha = 1.0 / tau;
+    }
+    if (g) {
+        for (int k = 0; k < 3; ++k) c->cfg.g[k] = c->rp.g[k] = k < c->d ? g[k] : 0.0;
+        c->rp.gmag = sqrt(c->rp.g[0] * c->rp.g[0] + c->rp.g[1] * c->rp.g[1] + c->rp.g[2] * c->rp.g[2]);
+    }
+    for (int i = 0; rho_s && i < c->np; ++i) c->host_parts[i].rho_s = rho_s[i];
+    if (c->np == 0) return LBM_OK;
+    int rc = upload_constants(c);
+    if (rc) return rc;
+    HIPCHK(c, launch_write_acc(c));
+    // right after the set-up U^{-1} = U^0, which depends on the acceleration
+    if (c->fresh && (rc = measure_initial(c))) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+} // extern "C"
+
+namespace {
+
+// Layout of a saved state (lbm_save_state).  Everything is little-endian
+// host layout; the per-particle block is structure-of-arrays, np entries
+// each: rho_s, a, b, shape (as a double), X[3], theta, U^{n-1}[3],
+// omega^{n-1}[3], A[3]; the populations follow at f_off.
+constexpr char STATE_MAGIC[8] = {'L', 'B', 'M', 'S', 'T', 'A', 'T', 'E'};
+constexpr int32_t STATE_VERSION = 1;
+struct StateHeader {
+    char magic[8];
+    int32_t version, lattice, storage, n[3], periodic[3], np, fresh, pad;
+    int64_t step;
+    uint64_t f_off, fbytes, total;
+    double tau, g[3];
+};
+constexpr int PSTATE = 17; // doubles per particle
+constexpr size_t STATE_PART_OFF = 256;
+
+size_t state_fbytes(const lbm_ctx *c) { return (size_t)c->Q * c->geo.N * storage_bytes(c->cfg.storage); }
+
+void state_layout(const lbm_ctx *c, int np, size_t &f_off, size_t &total)
+{
+    f_off = align_up(STATE_PART_OFF + (size_t)np * PSTATE * sizeof(double));
+    total = f_off + state_fbytes(c);
+}
+
+// offsets (in doubles from the particle block) of the SoA arrays
+struct PartOff {
+    size_t rho, a, b, shape, X, theta, Up, Wp, A;
+};
+PartOff part_off(int np)
+{
+    PartOff o;
+    o.rho = 0;
+    o.a = (size_t)np;
+    o.b = 2 * (size_t)np;
+    o.shape = 3 * (size_t)np;
+    o.X = 4 * (size_t)np;
+    o.theta = 7 * (size_t)np;
+    o.Up = 8 * (size_t)np;
+    o.Wp = 11 * (size_t)np;
+    o.A = 14 * (size_t)np;
+    return o;
+}
+
+} // namespace
+
+extern "C" {
+
+int lbm_state_size(const lbm_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return LBM_EINVAL;
+    size_t f_off;
+    state_layout(c, c->np, f_off, *bytes);
+    return LBM_OK;
+}
+
+int lbm_save_state(lbm_ctx *c, void *buf)
+{
+    if (!c || !buf) return c ? fail(c, LBM_EINVAL, "buf is NULL") : LBM_EINVAL;
+    (void)hipSetDevice(c->device);
+    const int np = c->np;
+    StateHeader h;
+    memset(&h, 0, sizeof(h));
+    memcpy(h.magic, STATE_MAGIC, 8);
+    h.version = STATE_VERSION;
+    h.lattice = c->cfg.lattice;
+    h.storage = c->cfg.storage;
+    for (int k = 0; k < 3; ++k) {
+        h.n[k] = k == 0 ? c->geo.nx : k == 1 ? c->geo.ny : c->geo.nz;
+        h.periodic[k] = k == 0 ? c->geo.per_x : k == 1 ? c->geo.per_y : c->geo.per_z;
+        h.g[k] = c->rp.g[k];
+    }
+    h.np = np;
+    h.fresh = c->fresh;
+    h.step = c->step;
+    h.tau = c->sp.tau;
+    size_t f_off, total;
+    state_layout(c, np, f_off, total);
+    h.f_off = f_off;
+    h.fbytes = state_fbytes(c);
+    h.total = total;
+    char *out = (char *)buf;
+    const PartOff o = part_off(np);
+    std::vector<double> cst(4 * (size_t)np);
+    for (int i = 0; i < np; ++i) {
+        const lbm_particle &q = c->host_parts[i];
+        cst[o.rho + i] = q.rho_s;
+        cst[o.a + i] = q.a;
+        cst[o.b + i] = q.shape == LBM_ELLIPSE ? q.b : q.a;
+        cst[o.shape + i] = (double)q.shape;
+    }
+    double *pb = (double *)(out + STATE_PART_OFF);
+    HIPCHK(c, hipMemcpyAsync(out, &h, sizeof(h), hipMemcpyDefault, c->stream));
+    if (np > 0) {
+        const size_t b3 = sizeof(double) * 3 * np;
+        HIPCHK(c, hipMemcpyAsync(pb, cst.data(), cst.size() * sizeof(double), hipMemcpyDefault, c->stream));
+        HIPCHK(c, hipMemcpyAsync(pb + o.X, c->P.X, b3, hipMemcpyDefault, c->stream));
+        HIPCHK(c, hipMemcpyAsync(pb + o.theta, c->P.theta, sizeof(double) * np, hipMemcpyDefault, c->stream));
+        HIPCHK(c, hipMemcpyAsync(pb + o.Up, c->P.Uprev, b3, hipMemcpyDefault, c->stream));
+        HIPCHK(c, hipMemcpyAsync(pb + o.Wp, c->P.Wprev, b3, hipMemcpyDefault, c->stream));
+        HIPCHK(c, hipMemcpyAsync(pb + o.A, c->P.A, b3, hipMemcpyDefault, c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(out + f_off, c->f[c->cur], h.fbytes, hipMemcpyDefault, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_load_state(lbm_ctx *c, const void *buf)
+{
+    if (!c || !buf) return c ? fail(c, LBM_EINVAL, "buf is NULL") : LBM_EINVAL;
+    (void)hipSetDevice(c->device);
+    const char *in = (const char *)buf;
+    StateHeader h;
+    HIPCHK(c, hipMemcpyAsync(&h, in, sizeof(h), hipMemcpyDefault, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (memcmp(h.magic, STATE_MAGIC, 8) || h.version != STATE_VERSION) return fail(c, LBM_EINVAL, "not a saved state");
+    const int nn[3] = {c->geo.nx, c->geo.ny, c->geo.nz}, per[3] = {c->geo.per_x, c->geo.per_y, c->geo.per_z};
+    bool same = h.lattice == c->cfg.lattice && h.storage == c->cfg.storage;
+    for (int k = 0; k < 3; ++k) same = same && h.n[k] == nn[k] && h.periodic[k] == per[k];
+    if (!same) return fail(c, LBM_EINVAL, "the state belongs to another lattice, storage or box");
+    size_t f_off, total;
+    if (h.np < 0 || h.np > c->cfg.max_particles) return fail(c, LBM_EINVAL, "the state holds more particles than max_particles");
+    state_layout(c, h.np, f_off, total);
+    if (h.f_off != f_off || h.total != total || h.fbytes != state_fbytes(c))
+        return fail(c, LBM_EINVAL, "inconsistent state header");
+    if (!(h.tau > 0.5) || (!c->sp.alpha_tracks_tau && c->sp.alpha > 1.0 / h.tau * (1.0 + 1e-12)))
+        return fail(c, LBM_EINVAL, "the state's tau is not valid for this context");
+    const int np = h.np;
+    const PartOff o = part_off(np);
+    std::vector<double> pb((size_t)np * PSTATE);
+    if (np > 0) {
+        HIPCHK(c, hipMemcpyAsync(pb.data(), in + STATE_PART_OFF, pb.size() * sizeof(double), hipMemcpyDefault, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    std::vector<lbm_particle> parts(np);
+    for (int i = 0; i < np; ++i) {
+        lbm_particle &q = parts[i];
+        memset(&q, 0, sizeof(q));
+        q.shape = (int32_t)pb[o.shape + i];
+        q.rho_s = pb[o.rho + i];
+        q.a = pb[o.a + i];
+        q.b = pb[o.b + i];
+        for (int k = 0; k < 3; ++k) q.x[k] = k < c->d ? pb[o.X + 3 * i + k] : 0.0;
+        q.theta = pb[o.theta + i];
+    }
+    // the parameters first (the collision constants depend on g), then the same
+    // checks as lbm_set_particles, before anything else changes
+    const RigidParams rp0 = c->rp;
+    const StepParams sp0 = c->sp;
+    c->sp.tau = h.tau;
+    c->sp.omega = 1.0 / h.tau;
+    if (c->sp.alpha_tracks_tau) c->sp.alpha = 1.0 / h.tau;
+    for (int k = 0; k < 3; ++k) c->rp.g[k] = k < c->d ? h.g[k] : 0.0;
+    c->rp.gmag = sqrt(c->rp.g[0] * c->rp.g[0] + c->rp.g[1] * c->rp.g[1] + c->rp.g[2] * c->rp.g[2]);
+    int rc = check_particles(c, parts.data(), np);
+    if (rc) {
+        c->rp = rp0;
+        c->sp = sp0;
+        return rc;
+    }
+    c->cfg.tau = h.tau;
+    for (int k = 0; k < 3; ++k) c->cfg.g[k] = c->rp.g[k];
+    free_grad(c);
+    HIPCHK(c, hipStreamSynchronize(c->stream)); // no poll still pending on the flags
+    c->poll_pending = 0;
+    if ((rc = install_particles(c, parts.data(), np))) return rc;
+    if (np > 0) {
+        // U^{n-1} goes to U as well (with fused sums U_prev is U itself; without,
+        // the sums read U_prev and overwrite U), omega^{n-1} likewise
+        const size_t b3 = sizeof(double) * 3 * np;
+        std::vector<double> X(3 * (size_t)np, 0.0);
+        for (int i = 0; i < np; ++i)
+            for (int k = 0; k < c->d; ++k) X[3 * i + k] = parts[i].x[k];
+        HIPCHK(c, hipMemcpyAsync(c->P.X, X.data(), b3, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->P.theta, pb.data() + o.theta, sizeof(double) * np, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->P.A, pb.data() + o.A, b3, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->P.U, pb.data() + o.Up, b3, hipMemcpyHostToDevice, c->stream));
+        if (c->P.Uprev != c->P.U)
+            HIPCHK(c, hipMemcpyAsync(c->P.Uprev, pb.data() + o.Up, b3, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->P.W, pb.data() + o.Wp, b3, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->P.Wprev, pb.data() + o.Wp, b3, hipMemcpyHostToDevice, c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->f[c->cur], in + f_off, h.fbytes, hipMemcpyDefault, c->stream));
+    if (np > 0) {
+        // the indicator of X^n, theta^n and the acceleration table from A^n
+        HIPCHK(c, launch_rigid_raster(c, 0));
+        // node counts for the check below (U and omega measured into scratch)
+        HIPCHK(c, launch_fields(c, c->f[c->cur], c->usol, nullptr, 1));
+        HIPCHK(c, launch_reduce(c, 0, nullptr, 1));
+    }
+    HIPCHK(c, hipMemsetAsync(c->flags, 0, 2 * sizeof(int32_t), c->stream));
+    if ((rc = check_device_claims(c))) return rc;
+    c->step = h.step;
+    c->fresh = h.fresh;
+    return LBM_OK;
 }
 
 int lbm_step_record(lbm_ctx *c, int64_t nsteps, double *host_rec)

@@ -118,6 +118,13 @@ struct lbm_ctx {
     double *staging; // [4][N] doubles for field/population transfers
     double *wall_tab; // [2][19] moving-wall terms (StepParams::wall_tab)
     int32_t *flags;  // [0] unstable, [1] domain
+    // sentinel polling inside lbm_step: every `check_every` steps (absolute step
+    // count) the flags are copied to pinned host memory behind an event;
+    // the next poll point waits for that event and reads them
+    int check_every;
+    int32_t *hflags; // pinned host memory, [2]
+    hipEvent_t poll_ev;
+    int poll_pending;
     lbm::PartDev P;
     int np, cap;
     // fused-sums step (K = 1): slot buffer (library-owned), its layout, the stamp counter
@@ -178,6 +185,7 @@ hipError_t launch_raster_clear(lbm_ctx *c);
 hipError_t launch_reduce(lbm_ctx *c, int step, double *rec, int scratch = 0);
 hipError_t launch_rigid_raster(lbm_ctx *c, int update);
 hipError_t launch_rigid_substeps(lbm_ctx *c);
+hipError_t launch_write_acc(lbm_ctx *c); // acceleration table from rho_s, g, A
 hipError_t launch_rigid_fused(lbm_ctx *c, double *rec); // Algorithm 1 + raster from the slots
 SlotParams slot_params(lbm_ctx *c, bool on);
 hipError_t launch_owner_to_int(lbm_ctx *c, int32_t *out);

@@ -25,6 +25,8 @@
 using namespace lbm;
 
 struct GradState {
+    // the particle set and slot layout the run was recorded with
+    int np = 0, fused = 0, slot_stride = 0;
     int64_t T = 0;
     int every = 0, nsnap = 0;
     size_t fbytes = 0, obytes = 0, pbytes = 0;
@@ -138,6 +140,9 @@ int lbm_forward_checkpointed(lbm_ctx *c, int64_t nsteps, int32_t every)
     free_grad(c);
     GradState *G = new GradState();
     c->grad = G;
+    G->np = c->np;
+    G->fused = c->fused;
+    G->slot_stride = c->slot_stride;
     G->T = nsteps;
     G->every = every;
     G->nsnap = (int)((nsteps + every - 1) / every) + 1; // segment starts + final state
@@ -184,6 +189,8 @@ int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau
     if (!c || !dL_dX) return LBM_EINVAL;
     GradState *G = c->grad;
     if (!G) return c->err = "no differentiated forward run to go back through", LBM_ESTATE;
+    if (G->np != c->np || G->fused != c->fused || G->slot_stride != c->slot_stride)
+        return c->err = "the particles changed since the differentiated forward run", LBM_ESTATE;
     (void)hipSetDevice(c->device);
     const int np = c->np, Q = c->Q;
     const int64_t N = c->geo.N;

@@ -487,6 +487,17 @@ __global__ __launch_bounds__(BS) void k_rigid_raster(uint16_t *__restrict__ owne
     raster_items<UNR>(owner, g, d, i, s_X, shape, Ri, bi, s_cs, s_sn, s_lo, s_hi, threadIdx.x, BS);
 }
 
+// Acceleration table a_i = b_i g + A_i of every particle from the current
+// rho_s, g and A (after a change of the parameters).
+__global__ __launch_bounds__(256) void k_write_acc(PartDev P, RigidParams rp)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rp.np) return;
+    double A[3];
+    for (int k = 0; k < 3; ++k) A[k] = P.A[3 * i + k];
+    write_acc(P, rp, i, P.rho_s[i], A);
+}
+
 // ------------------------------------- fused-sums step: Algorithm 1 from slots
 // K = 1 with the momentum sums taken by the lattice kernel (slot_sums): one
 // workgroup per particle i
@@ -884,6 +895,15 @@ hipError_t launch_rigid_raster(lbm_ctx *c, int update)
     rp.np = c->np;
     uint16_t *out = c->owner_next ? c->owner_next : c->owner;
     return launch(c, k_rigid_raster<RIGID_BS>, dim3(c->np), dim3(RIGID_BS), out, c->P, rp, c->geo, update, c->flags);
+}
+
+hipError_t launch_write_acc(lbm_ctx *c)
+{
+    if (c->np == 0) return hipSuccess;
+    RigidParams rp = c->rp;
+    rp.np = c->np;
+    hipLaunchKernelGGL(k_write_acc, dim3((c->np + 255) / 256), dim3(256), 0, c->stream, c->P, rp);
+    return hipGetLastError();
 }
 
 hipError_t launch_rigid_substeps(lbm_ctx *c)

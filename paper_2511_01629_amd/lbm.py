@@ -25,7 +25,8 @@ CODES = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "EUNSTABLE
 EXPORTS = ["lbm_workspace_size", "lbm_create", "lbm_destroy", "lbm_set_particles", "lbm_step", "lbm_step_record",
            "lbm_sync", "lbm_get_fields", "lbm_get_populations", "lbm_set_populations", "lbm_get_particles",
            "lbm_get_step", "lbm_last_error", "lbm_profile", "lbm_profile_read", "lbm_copy",
-           "lbm_forward_checkpointed", "lbm_backward"]
+           "lbm_forward_checkpointed", "lbm_backward", "lbm_get_fields_device", "lbm_set_params",
+           "lbm_state_size", "lbm_save_state", "lbm_load_state"]
 
 
 class LbmUnavailable(RuntimeError):
@@ -46,7 +47,7 @@ class Config(C.Structure):
         ("delta", C.c_double), ("K", C.c_int32), ("collision_form", C.c_int32), ("gravity_form", C.c_int32),
         ("fluid_accel", C.c_double * 3), ("penalize_all", C.c_int32), ("device", C.c_int32),
         ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
-        ("max_particles", C.c_int32), ("wall_velocity", C.c_double * 18),
+        ("max_particles", C.c_int32), ("wall_velocity", C.c_double * 18), ("check_every", C.c_int32),
     ]
 
 
@@ -94,6 +95,11 @@ def load():
     lib.lbm_copy.argtypes = [P, P, C.c_size_t, P]
     lib.lbm_forward_checkpointed.argtypes = [P, I64, I32]
     lib.lbm_backward.argtypes = [P, dp, dp, dp, dp]
+    lib.lbm_get_fields_device.argtypes = [P, P, P, P]
+    lib.lbm_set_params.argtypes = [P, dp, C.c_double, dp]
+    lib.lbm_state_size.argtypes = [P, C.POINTER(C.c_size_t)]
+    lib.lbm_save_state.argtypes = [P, P]
+    lib.lbm_load_state.argtypes = [P, P]
     _LIB = lib
     return lib
 
@@ -133,6 +139,7 @@ def make_config(cfg, storage=None, device=0, max_particles=0):
         w = np.asarray(cfg["wall_velocity"], dtype=np.float64)
         wv[: w.shape[0], : w.shape[1], : w.shape[2]] = w
     c.wall_velocity = (C.c_double * 18)(*wv.ravel())
+    c.check_every = int(cfg.get("check_every", 0))
     return c
 
 
@@ -274,6 +281,62 @@ class Simulation:
     def set_populations(self, f):
         f = np.ascontiguousarray(np.moveaxis(np.asarray(f, dtype=np.float64).reshape(*self.shape, self.Q), -1, 0))
         self._check(self.lib.lbm_set_populations(self.ctx, f.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def fields_device(self):
+        """u (nz, ny, nx, d), p (nz, ny, nx) float64 and owner (nz, ny, nx) int32
+        as torch tensors on the context's device, filled on its stream (no
+        host round trip)."""
+        t = self.torch
+        dev = self.workspace.device
+        u = t.empty((*self.shape, self.d), dtype=t.float64, device=dev)
+        p = t.empty(self.shape, dtype=t.float64, device=dev)
+        own = t.empty(self.shape, dtype=t.int32, device=dev)
+        self._check(self.lib.lbm_get_fields_device(self.ctx, C.c_void_p(u.data_ptr()), C.c_void_p(p.data_ptr()),
+                                                   C.c_void_p(own.data_ptr())))
+        return u, p, own
+
+    def set_params(self, rho_s=None, tau=None, g=None):
+        """Replace the solid densities (n), tau and/or the gravity vector;
+        None keeps a value."""
+        rho = None
+        if rho_s is not None:
+            rho = np.ascontiguousarray(np.asarray(rho_s, dtype=np.float64).reshape(self.np))
+        gv = None
+        if g is not None:
+            gv = np.ascontiguousarray((list(np.asarray(g, dtype=np.float64).ravel()) + [0.0, 0.0, 0.0])[:3])
+        dp = C.POINTER(C.c_double)
+        self._check(self.lib.lbm_set_params(self.ctx, rho.ctypes.data_as(dp) if rho is not None else None,
+                                            float(tau) if tau is not None else 0.0,
+                                            gv.ctypes.data_as(dp) if gv is not None else None))
+
+    def state_size(self):
+        n = C.c_size_t()
+        self._check(self.lib.lbm_state_size(self.ctx, C.byref(n)))
+        return int(n.value)
+
+    def save_state(self, on_device=False):
+        """The whole between-step state as bytes: a numpy uint8 array (host) or,
+        with on_device, a torch uint8 tensor on the context's device."""
+        n = self.state_size()
+        if on_device:
+            buf = self.torch.empty(n, dtype=self.torch.uint8, device=self.workspace.device)
+            ptr = buf.data_ptr()
+        else:
+            buf = np.zeros(n, dtype=np.uint8)
+            ptr = buf.ctypes.data
+        self._check(self.lib.lbm_save_state(self.ctx, C.c_void_p(ptr)))
+        return buf
+
+    def load_state(self, buf):
+        """Install a state saved by save_state (host array or device tensor)."""
+        if hasattr(buf, "data_ptr"):
+            ptr = buf.data_ptr()
+        else:
+            buf = np.ascontiguousarray(buf, dtype=np.uint8)
+            ptr = buf.ctypes.data
+        self._check(self.lib.lbm_load_state(self.ctx, C.c_void_p(ptr)))
+        hdr = np.frombuffer(bytes(buf[:64].cpu().numpy()) if hasattr(buf, "cpu") else bytes(buf[:64]), dtype=np.int32)
+        self.np = int(hdr[11])
 
     def particles(self):
         arr = (Particle * max(self.np, 1))()

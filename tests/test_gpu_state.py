@@ -1,0 +1,239 @@
+"""The between-step state and the parameters through the C ABI.
+
+* save/load: run(2n) equals run(n) + lbm_save_state + lbm_load_state + run(n),
+  bit for bit, in every storage type, in D2Q9 with contacts (momentum sums in
+  the lattice kernel), with K = 3 sub-steps (the separate sums kernel), in
+  D3Q19, and with no particles; the state blob in host or device memory,
+  loaded into a fresh context or back into the one that saved it.  The state
+  is what Algorithm 1 carries from step to step (sec. 2.4: X^n, theta^n,
+  U^{n-1}, omega^{n-1}, A^n) plus the populations.
+* The sentinel inside lbm_step: a NaN population loaded with a state makes
+  lbm_step return LBM_EUNSTABLE within 2 check_every steps.
+* lbm_set_params: a context set up with one set of densities, tau and g and
+  then given another equals, bit for bit, a context created with the second.
+* lbm_set_particles: a set that would leave a body with no node is rejected
+  on the host with the context unchanged (a differentiated run recorded
+  before still goes back through); a successful call discards that run.
+* lbm_get_fields_device: the fields written into torch tensors equal the
+  host copy.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import banner, pair, rel
+from paper_2511_01629_amd import lbm
+from paper_2511_01629_amd.workloads import place, random_state
+
+pytestmark = pytest.mark.gpu
+
+
+def _contacts(K=1):
+    kinds = [("disk", 5.0, 5.0)] * 5 + [("ellipse", 6.0, 3.0)] * 3
+    parts = place((64, 96), kinds, seed=7, rho_range=(1.2, 1.8), upper_axis=1, gap=0.3, margin=0.3)
+    cfg = dict(lattice="D2Q9", n=(64, 96, 1), periodic=(0, 0, 0), tau=0.6, g=(0.0, -2e-4, 0.0), K=K)
+    return cfg, parts
+
+
+def _spheres():
+    cfg = dict(lattice="D3Q19", n=(24, 20, 28), periodic=(1, 0, 0), tau=0.65, g=(0.0, 0.0, -4e-4))
+    parts = [dict(shape="sphere", rho_s=1.6, a=4.0, x=(8.0, 9.5, 10.0)),
+             dict(shape="sphere", rho_s=1.3, a=4.5, x=(17.2, 10.0, 14.5))]
+    return cfg, parts
+
+
+def _same(a, b):
+    """Bitwise equality of two simulations' observable state."""
+    assert np.array_equal(a.populations(), b.populations())
+    Pa, Pb = a.particles(), b.particles()
+    for key in ("X", "theta", "U", "omega", "U_prev", "omega_prev", "A", "N"):
+        assert np.array_equal(Pa[key], Pb[key]), key
+    ua, pa, oa = a.fields()
+    ub, pb, ob = b.fields()
+    assert np.array_equal(ua, ub) and np.array_equal(pa, pb) and np.array_equal(oa, ob)
+    assert a.step_index == b.step_index
+
+
+CASES = [("contacts", "f64"), ("contacts", "f32"), ("contacts", "f16"), ("contacts", "bf16"),
+         ("substeps", "f64"), ("spheres", "f32"), ("fluid", "f32")]
+
+
+@pytest.mark.parametrize("case,storage", CASES)
+@pytest.mark.parametrize("where", ["host", "device"])
+def test_save_load_resumes_bitwise(case, storage, where):
+    banner(f"save/load {case} {storage} {where}")
+    cfg, parts = {"contacts": _contacts(), "substeps": _contacts(K=3), "spheres": _spheres(),
+                  "fluid": (dict(_contacts()[0], fluid_accel=(1e-5, -2e-5, 0.0)), [])}[case]
+    n = 40
+    ref = lbm.Simulation(cfg, parts, storage=storage)
+    ref.step(2 * n)
+    a = lbm.Simulation(cfg, parts, storage=storage)
+    a.step(n)
+    blob = a.save_state(on_device=(where == "device"))
+    assert len(blob) == a.state_size()
+    b = lbm.Simulation(cfg, [], storage=storage, max_particles=max(len(parts), 1))
+    b.load_state(blob)
+    assert b.np == len(parts) and b.step_index == n
+    b.step(n)
+    _same(ref, b)
+    # back into the context that saved it, after it ran on
+    a.step(7)
+    a.load_state(blob)
+    a.step(n)
+    _same(ref, a)
+
+
+def test_load_rejects_another_lattice():
+    banner("load validation")
+    cfg, parts = _contacts()
+    a = lbm.Simulation(cfg, parts, storage="f32")
+    blob = a.save_state()
+    for other, storage in ((dict(cfg, n=(64, 97, 1)), "f32"), (cfg, "f64"), (dict(cfg, periodic=(1, 0, 0)), "f32")):
+        b = lbm.Simulation(other, [], storage=storage, max_particles=8)
+        with pytest.raises(lbm.LbmError) as e:
+            b.load_state(blob)
+        assert e.value.code == lbm.LBM_EINVAL
+    small = lbm.Simulation(cfg, [], storage="f32", max_particles=2)  # fewer slots than bodies
+    with pytest.raises(lbm.LbmError) as e:
+        small.load_state(blob)
+    assert e.value.code == lbm.LBM_EINVAL
+    bad = blob.copy()
+    bad[0] ^= 0xFF
+    with pytest.raises(lbm.LbmError) as e:
+        a.load_state(bad)
+    assert e.value.code == lbm.LBM_EINVAL
+    a.step(3)  # the rejected loads changed nothing
+    ref = lbm.Simulation(cfg, parts, storage="f32")
+    ref.step(3)
+    _same(ref, a)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_nan_in_loaded_state_stops_lbm_step(storage):
+    """A non-finite population installed by lbm_load_state trips the
+    sentinel on the first step; lbm_step returns LBM_EUNSTABLE at a poll
+    point within 2 check_every steps and queues no more."""
+    banner(f"sentinel NaN {storage}")
+    k = 8
+    cfg, parts = _contacts()
+    cfg = dict(cfg, check_every=k)
+    a = lbm.Simulation(cfg, parts, storage=storage)
+    a.step(5)
+    blob = a.save_state()
+    f_off = int(np.frombuffer(blob[64:72].tobytes(), dtype=np.uint64)[0])
+    elt = 8 if storage == "f64" else 4
+    node = 30 * 64 + 17  # a fluid node away from the bodies, population 1
+    pos = f_off + (1 * 64 * 96 + node) * elt
+    blob[pos:pos + elt] = np.frombuffer(np.array([np.nan], dtype=np.float64 if elt == 8 else np.float32).tobytes(),
+                                        dtype=np.uint8)
+    a.load_state(blob)
+    with pytest.raises(lbm.LbmError) as e:
+        a.step(1000)
+    assert e.value.code == lbm.LBM_EUNSTABLE
+    stopped = a.step_index
+    print(f"[measured] {storage}: tripped at step 6, lbm_step stopped at step {stopped} (check_every {k})", flush=True)
+    assert 5 < stopped <= 5 + 2 * k + k  # the first poll point after the load is at most k steps away
+    # the sentinel is sticky until the next load
+    with pytest.raises(lbm.LbmError):
+        a.sync()
+    # with polling off the same run is only reported by lbm_sync
+    b = lbm.Simulation(dict(cfg, check_every=-1), parts, storage=storage)
+    b.load_state(blob)
+    b.step(100)
+    assert b.step_index == 105
+    with pytest.raises(lbm.LbmError) as e:
+        b.sync()
+    assert e.value.code == lbm.LBM_EUNSTABLE
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_set_params_equals_fresh_context(storage):
+    """Densities, tau and g replaced right after the set-up: the run equals a
+    context created with the new values from the start (U^0 measured again
+    with the new acceleration), bit for bit; and replaced again mid-run, the
+    run continues from the same state with the new values."""
+    banner(f"set_params {storage}")
+    cfg, parts = _contacts()
+    rho1 = [p["rho_s"] * 1.05 for p in parts]
+    g1 = (0.0, -3e-4, 0.0)
+    a = lbm.Simulation(cfg, parts, storage=storage)
+    a.set_params(rho_s=rho1, tau=0.62, g=g1)
+    b = lbm.Simulation(dict(cfg, tau=0.62, g=g1), [dict(p, rho_s=r) for p, r in zip(parts, rho1)], storage=storage)
+    for s in (30, 30):
+        a.step(s)
+        b.step(s)
+    _same(a, b)
+    # mid-run: both change to a third set; same state in, same state out
+    rho2 = [r * 0.97 for r in rho1]
+    for sim in (a, b):
+        sim.set_params(rho_s=rho2, tau=0.7)
+        sim.step(20)
+    _same(a, b)
+    # the change acted: a run that kept the second set differs
+    c = lbm.Simulation(dict(cfg, tau=0.62, g=g1), [dict(p, rho_s=r) for p, r in zip(parts, rho1)], storage=storage)
+    c.step(80)
+    assert not np.array_equal(c.particles()["X"], a.particles()["X"])
+    for bad in (dict(tau=0.5), dict(rho_s=[-1.0] * len(parts)), dict(g=(np.nan, 0.0, 0.0))):
+        with pytest.raises(lbm.LbmError) as e:
+            a.set_params(**bad)
+        assert e.value.code == lbm.LBM_EINVAL
+
+
+def test_set_params_oracle_parity():
+    """A context whose parameters are replaced right after the set-up matches
+    the FP64 oracle run with those parameters from the start (1e-12)."""
+    banner("set_params vs oracle")
+    from oracle import oracle as O
+
+    cfg, parts = _contacts()
+    cfg2 = dict(cfg, tau=0.66, g=(0.0, -1.5e-4, 0.0))
+    parts2 = [dict(p, rho_s=p["rho_s"] + 0.1) for p in parts]
+    sim = lbm.Simulation(cfg, parts, storage="f64")
+    sim.set_params(rho_s=[p["rho_s"] for p in parts2], tau=0.66, g=(0.0, -1.5e-4, 0.0))
+    rg = sim.step_record(60)
+    ro = O.Oracle(cfg2, parts2).step(60, record=True)
+    assert np.abs(rg[:, :, 0:3] - ro[:, :, 0:3]).max() < 1e-10
+    assert rel(rg[:, :, 4:7], ro[:, :, 4:7]) < 1e-11
+
+
+def test_failed_set_particles_changes_nothing():
+    """Two coincident disks, the second inside the first: the second would own
+    no node, so lbm_set_particles rejects the set on the host before anything
+    changes; the differentiated run recorded before it still goes back
+    through with the same gradient.  A successful lbm_set_particles discards
+    that run (lbm_backward then reports ESTATE)."""
+    banner("set_particles failure")
+    cfg, parts = _contacts()
+    sim = lbm.Simulation(cfg, parts, storage="f64", max_particles=8)
+    sim.forward_checkpointed(20, 5)
+    X0 = sim.particles()["X"].copy()
+    seed = np.zeros((len(parts), 3))
+    seed[:, 1] = 1.0 / len(parts)
+    g1 = sim.backward(seed)
+    inner = [dict(shape="disk", rho_s=1.3, a=6.0, x=(30.0, 50.0, 0.0)),
+             dict(shape="disk", rho_s=1.3, a=3.0, x=(30.0, 50.0, 0.0))]
+    with pytest.raises(lbm.LbmError) as e:
+        sim.set_particles(inner)
+    assert e.value.code == lbm.LBM_EINVAL and b"no lattice node" in str(e.value).encode()
+    sim.np = len(parts)
+    assert np.array_equal(sim.particles()["X"], X0)
+    g2 = sim.backward(seed)
+    assert np.array_equal(g1[0], g2[0]) and g1[1] == g2[1] and g1[2] == g2[2]
+    sim.set_particles(parts[:3])
+    with pytest.raises(lbm.LbmError) as e:
+        sim.backward(seed[:3])
+    assert e.value.code == lbm.LBM_ESTATE
+
+
+@pytest.mark.parametrize("kind", ["D2Q9", "D3Q19"])
+def test_fields_device(kind):
+    banner(f"fields on device {kind}")
+    cfg, parts = _contacts() if kind == "D2Q9" else _spheres()
+    Q = 9 if kind == "D2Q9" else 19
+    shp = (cfg["n"][2] if kind == "D3Q19" else 1, cfg["n"][1], cfg["n"][0])
+    sim, _ = pair(cfg, parts, storage="f32", f0=random_state(shp, Q, 1e-3, seed=21).astype(np.float32))
+    sim.step(5)
+    ud, pd, od = sim.fields_device()
+    sim.stream.synchronize()
+    uh, ph, oh = sim.fields()
+    assert np.array_equal(ud.cpu().numpy(), uh) and np.array_equal(pd.cpu().numpy(), ph)
+    assert np.array_equal(od.cpu().numpy(), oh)
