@@ -165,6 +165,21 @@ int lbm_step(lbm_ctx *ctx, int64_t nsteps);
  * step n (values before that step's update).  Waits for the stream. */
 int lbm_step_record(lbm_ctx *ctx, int64_t nsteps, double *host_rec);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * lbm_step_record with no allocation.  The per-step records go through a
+ * static device array of LBM_NOALLOC_REC_DOUBLES doubles (8 MiB), one per
+ * GPU, held until the process ends, instead of memory the library would
+ * allocate; lbm_step_record's results, bit for bit.  EINVAL if nsteps x
+ * max(n, 1) x 20 exceeds LBM_NOALLOC_REC_DOUBLES (e.g. 3276 steps of 16
+ * particles); ESTATE while lbm_profile is on (it creates events); EDEVICE if
+ * the array's address cannot be looked up on this device.  Every
+ * context on a GPU shares that GPU's array, which keeps the last call's
+ * records: calls that overlap in time on one GPU (other host threads, other
+ * streams) race.  Waits for the stream. */
+#define LBM_NOALLOC_REC_DOUBLES (1 << 20)
+int lbm_step_record_noalloc(lbm_ctx *ctx, int64_t nsteps, double *host_rec);
+
 /* Wait for queued work; report LBM_EUNSTABLE / LBM_EDOMAIN if the device
  * sentinel tripped since the context was created. */
 int lbm_sync(lbm_ctx *ctx);

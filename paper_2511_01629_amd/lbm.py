@@ -26,7 +26,7 @@ EXPORTS = ["lbm_workspace_size", "lbm_create", "lbm_destroy", "lbm_set_particles
            "lbm_sync", "lbm_get_fields", "lbm_get_populations", "lbm_set_populations", "lbm_get_particles",
            "lbm_get_step", "lbm_last_error", "lbm_profile", "lbm_profile_read", "lbm_copy",
            "lbm_forward_checkpointed", "lbm_backward", "lbm_get_fields_device", "lbm_set_params",
-           "lbm_state_size", "lbm_save_state", "lbm_load_state"]
+           "lbm_state_size", "lbm_save_state", "lbm_load_state", "lbm_step_record_noalloc"]
 
 
 class LbmUnavailable(RuntimeError):
@@ -100,6 +100,7 @@ def load():
     lib.lbm_state_size.argtypes = [P, C.POINTER(C.c_size_t)]
     lib.lbm_save_state.argtypes = [P, P]
     lib.lbm_load_state.argtypes = [P, P]
+    lib.lbm_step_record_noalloc.argtypes = [P, I64, dp]
     _LIB = lib
     return lib
 
@@ -226,6 +227,13 @@ class Simulation:
     def step_record(self, n):
         rec = np.zeros((int(n), max(self.np, 1), 14))
         self._check(self.lib.lbm_step_record(self.ctx, int(n), rec.ctypes.data_as(C.POINTER(C.c_double))))
+        return rec[:, : self.np]
+
+    def step_record_noalloc(self, n):
+        """step_record through the library's static record array (no device
+        allocation by the library)."""
+        rec = np.zeros((int(n), max(self.np, 1), 14))
+        self._check(self.lib.lbm_step_record_noalloc(self.ctx, int(n), rec.ctypes.data_as(C.POINTER(C.c_double))))
         return rec[:, : self.np]
 
     def sync(self):
