@@ -95,6 +95,17 @@ typedef struct {
                                every other axis periodic; all zero: fixed walls.            */
     int32_t check_every;    /* lbm_step reads the device sentinel every this many steps (of the
                                absolute step count); 0 selects 64, a negative value never   */
+    double rigid_beta;      /* rigid-velocity forcing, an extension beyond the paper (whose
+                               constraint acts through the stress, eq. 17): in [0, 1], 0 off.
+                               On the nodes of particle i the acceleration gains
+                               2 beta (U_i + omega_i x r - u), u the velocity of eq. (15a) with
+                               the gravity acceleration alone, r = x - X_i^n, U_i, omega_i the
+                               momentum sums of the same step (eq. 22a-b), so the velocity
+                               that enters f^eq and the Guo force is (1 - beta) u +
+                               beta (U_i + omega_i x r).  Costs a second pass over the solid
+                               nodes (and the separate sums kernel) every step.           */
+    int32_t no_stress_penalty; /* 1: leave out the penalization source of eq. (17) (to compare
+                               the forcing with the paper's stress penalty); 0: the paper   */
 } lbm_config;
 
 typedef struct {
@@ -255,7 +266,8 @@ int lbm_load_state(lbm_ctx *ctx, const void *buf);
  * (a binary indicator makes the loss piecewise smooth).
  *
  * lbm_forward_checkpointed: run nsteps >= 1 steps starting right after
- * lbm_set_particles (else ESTATE; K must be 1, else EINVAL), snapshotting the state every `every`
+ * lbm_set_particles (else ESTATE; K must be 1, rigid_beta 0 and the stress
+ * penalty on, else EINVAL), snapshotting the state every `every`
  * steps and keeping every step's particle record (device memory allocated
  * by the library: about (nsteps/every + 1) population buffers plus small
  * records).  Waits for the stream.
@@ -284,9 +296,10 @@ int lbm_backward(lbm_ctx *ctx, const double *dL_dX, double *g_rho_s, double *g_t
  * launches where the lattice kernel takes the sums, which it does with K = 1
  * whenever the set-up found a slot layout), 2 Algorithm 1 with the new
  * indicator (K = 1) or the sub-step integration (K > 1), 3 the indicator
- * after sub-steps (K > 1 only).  host_ms and host_count are host arrays of
+ * after sub-steps (K > 1 only), 4 the rigid-velocity forcing pass
+ * (rigid_beta > 0 only).  host_ms and host_count are host arrays of
  * LBM_NKERNELS. */
-#define LBM_NKERNELS 4
+#define LBM_NKERNELS 5
 int lbm_profile(lbm_ctx *ctx, int32_t enable);
 int lbm_profile_read(lbm_ctx *ctx, double *host_ms, int64_t *host_count, int32_t reset);
 

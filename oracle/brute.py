@@ -146,12 +146,24 @@ def step(state):
             W = solve3(T, Lv)
         meas.append((N, Uv, W))
 
-    # S5: collision (eq. 10, 13, 14, 17)
+    # S5: collision (eq. 10, 13, 14, 17); with the rigid-velocity forcing (an
+    # extension, beta > 0) a solid node's acceleration gains
+    # 2 beta (U_i + omega_i x r - u), u the fluid velocity of S3
+    beta = state.get("beta", 0.0)
+    stress = not state.get("no_stress_penalty", False)
     post = {}
     for nd in nodes:
         i = owner[nd]
         acc = accel(i)
         u, p, fv = U[nd], P[nd], f[nd]
+        if i >= 0 and beta > 0:
+            _, Ui, Wi = meas[i]
+            r = disp(nd, parts[i]["X"])
+            rigid = [Ui[0] + Wi[1] * r[2] - Wi[2] * r[1], Ui[1] + Wi[2] * r[0] - Wi[0] * r[2],
+                     Ui[2] + Wi[0] * r[1] - Wi[1] * r[0]]
+            acc = [acc[k] + (2 * beta * (rigid[k] - u[k]) if k < d else 0.0) for k in range(3)]
+            u = [sum(fv[a] * c[a][k] for a in range(Q)) + acc[k] / 2 for k in range(3)]
+            p = (CS2 * sum(fv[1:]) - w[0] / 2 * dot(u, u)) / (1 - w[0])
         fe = feq(c, w, p, u)
         Pi = [[sum((fv[a] - fe[a]) * c[a][r] * c[a][s] for a in range(Q)) for s in range(3)] for r in range(3)]
         trPi = sum(Pi[k][k] for k in range(d))
@@ -161,7 +173,7 @@ def step(state):
             cu = dot(ca, u)
             F = (1 - 1 / (2 * tau)) * w[a] * sum(((ca[k] - u[k]) / CS2 + cu * ca[k] / CS2 ** 2) * acc[k] for k in range(3))
             S = 0.0
-            if i >= 0:
+            if i >= 0 and stress:
                 PiCC = sum(Pi[r][s] * ca[r] * ca[s] for r in range(3) for s in range(3))
                 S = w[a] / (2 * CS2 ** 2) * alpha * (PiCC - CS2 * trPi)
             out.append(fv[a] - (fv[a] - fe[a]) / tau + F + S)
@@ -276,7 +288,8 @@ def solve3(T, b):
     return out
 
 
-def initial_state(kind, n, periodic, tau, alpha, rho_f, g, u0, parts, eps_p=2.0, eps_w=1.0, delta=1.0, K=1):
+def initial_state(kind, n, periodic, tau, alpha, rho_f, g, u0, parts, eps_p=2.0, eps_w=1.0, delta=1.0, K=1,
+                  beta=0.0, no_stress_penalty=False):
     """f = f^eq(0, u0) everywhere; U^{-1} = U^0 from the initial indicator."""
     c, w = velocities(kind)
     u0 = list(u0) + [0.0] * (3 - len(u0))
@@ -284,7 +297,8 @@ def initial_state(kind, n, periodic, tau, alpha, rho_f, g, u0, parts, eps_p=2.0,
     fe = feq(c, w, 0.0, u0)
     nodes = [(x, y, z) for z in range(n[2]) for y in range(n[1]) for x in range(n[0])]
     st = dict(kind=kind, n=tuple(n), periodic=tuple(periodic), tau=tau, alpha=alpha if alpha > 0 else 1.0 / tau,
-              rho_f=rho_f, g=g, eps_p=eps_p, eps_w=eps_w, delta=delta, K=K,
+              rho_f=rho_f, g=g, eps_p=eps_p, eps_w=eps_w, delta=delta, K=K, beta=beta,
+              no_stress_penalty=no_stress_penalty,
               f={nd: list(fe) for nd in nodes}, parts=[])
     for pt in parts:
         q = dict(pt)

@@ -208,6 +208,10 @@ typedef struct {
     /* tangential velocity of the halfway walls, [axis][low, high side][component];
      * moving walls only on the y or z axis, every other axis periodic */
     double wall_u[3][2][3];
+    /* rigid-velocity forcing (an extension, not the paper's method): beta in
+     * [0, 1], 0 = off; and a switch that leaves out the stress penalization */
+    double rigid_beta;
+    int no_stress_penalty;
 } ora_cfg;
 
 typedef struct {
@@ -240,6 +244,8 @@ typedef struct {
     int penalize_all;
     int wall_axis; /* 0: no moving wall; else the axis of the moving walls */
     double wall_u[2][3];
+    double beta;           /* rigid-velocity forcing strength (0: off) */
+    int no_stress_penalty; /* 1: S of eq. (17) left out */
     int np;
     particle_t *p;
     real *f, *ft, *u, *pr;
@@ -438,6 +444,30 @@ static void reduce_particles(ora_ctx *c)
     free(cnt);
 }
 
+/* Rigid-velocity forcing (an extension beyond the paper, off unless beta > 0):
+ * on a node of particle i, the acceleration that moves the velocity of
+ * eq. (15a) a fraction beta of the way from the fluid's own velocity u (S3,
+ * with the gravity acceleration only) to the rigid motion of the particle,
+ * U_i^n + omega_i^n x r with r = x - X_i^n (minimum image) and U^n, omega^n the
+ * momentum sums of this step (S4, eq. 22a-b):
+ *     a_rig = 2 beta (U_i + omega_i x r - u),
+ * since eq. (15a) adds half the acceleration to the velocity, so that
+ * u + a_rig/2 = (1 - beta) u + beta (U_i + omega_i x r).  The velocity is
+ * then the rigid motion exactly for beta = 1, and the forcing adds no net
+ * momentum over the particle (sum of a_rig = 2 beta omega x sum r, zero
+ * when the nodes are centred on X_i). */
+static void rigid_forcing(const ora_ctx *c, long id, real acc[3])
+{
+    const int d = c->L.d;
+    const particle_t *P = &c->p[c->owner[id]];
+    const long xs[3] = {id % c->n[0], (id / c->n[0]) % c->n[1], id / ((long)c->n[0] * c->n[1])};
+    real r[3] = {0, 0, 0};
+    for (int k = 0; k < d; k++) r[k] = (double)unwrap_coord(c, k, xs[k], RE(P->X[k])) - P->X[k];
+    const real wr[3] = {P->W[1] * r[2] - P->W[2] * r[1], P->W[2] * r[0] - P->W[0] * r[2],
+                        P->W[0] * r[1] - P->W[1] * r[0]};
+    for (int k = 0; k < d; k++) acc[k] += 2.0 * c->beta * (P->U[k] + wr[k] - c->u[id * 3 + k]);
+}
+
 /* S5 + S6: collide every node, then pull-stream with halfway bounce-back on
  * wall axes and wrap-around on periodic axes (sec. 2.2 eq. 10). */
 static void collide_stream(ora_ctx *c)
@@ -447,7 +477,8 @@ static void collide_stream(ora_ctx *c)
     for (long i = 0; i < c->N; i++) {
         real acc[3], u[3], p;
         node_accel(c, c->owner[i], acc);
-        int solid = c->owner[i] >= 0 || c->penalize_all;
+        if (c->owner[i] >= 0 && c->beta > 0.0) rigid_forcing(c, i, acc);
+        int solid = (c->owner[i] >= 0 || c->penalize_all) && !c->no_stress_penalty;
         collide_node(&c->L, c->tau, c->alpha, solid, &c->f[i * Q], acc, &c->ft[i * Q], u, &p);
     }
 #pragma omp parallel for schedule(static)
@@ -641,6 +672,12 @@ int ora_create(const ora_cfg *cfg, ora_ctx **out)
     c->gform = cfg->gravity_form;
     for (int k = 0; k < 3; k++) c->fluid_accel[k] = (k < c->L.d) ? cfg->fluid_accel[k] : 0.0;
     c->penalize_all = cfg->penalize_all;
+    if (!(cfg->rigid_beta >= 0.0 && cfg->rigid_beta <= 1.0)) {
+        free(c);
+        return -1;
+    }
+    c->beta = cfg->rigid_beta;
+    c->no_stress_penalty = cfg->no_stress_penalty != 0;
     /* moving walls: one axis (y or z), tangential velocities, others periodic */
     for (int k = 0; k < 3; k++)
         for (int sd = 0; sd < 2; sd++)

@@ -9,7 +9,8 @@ Configurations and particles are plain dicts:
              tau=..., alpha=0 (-> 1/tau), rho_f=1, g=(gx, gy, gz), u0=(...),
              p0=0, eps_p=2, eps_w=1, delta=1, K=1, collision_form=0,
              gravity_form=0, fluid_accel=(0, 0, 0), penalize_all=0,
-             wall_velocity=None or [axis][low, high wall][component])
+             wall_velocity=None or [axis][low, high wall][component],
+             rigid_beta=0 (rigid-velocity forcing, an extension), no_stress_penalty=0)
   particle = dict(shape="disk"|"ellipse"|"sphere", rho_s=..., a=..., b=...,
                   x=(X, Y, Z), theta=...)
 Fields come back with shape (nz, ny, nx, ...) (x fastest).
@@ -35,7 +36,7 @@ class _Cfg(C.Structure):
         ("eps_p", C.c_double), ("eps_w", C.c_double), ("delta", C.c_double),
         ("K", C.c_int), ("collision_form", C.c_int), ("gravity_form", C.c_int),
         ("fluid_accel", C.c_double * 3), ("penalize_all", C.c_int),
-        ("wall_u", C.c_double * 18),
+        ("wall_u", C.c_double * 18), ("rigid_beta", C.c_double), ("no_stress_penalty", C.c_int),
     ]
 
 
@@ -120,6 +121,8 @@ def _make_cfg(cfg):
         w = np.asarray(cfg["wall_velocity"], dtype=np.float64)
         wv[: w.shape[0], : w.shape[1], : w.shape[2]] = w
     c.wall_u = (C.c_double * 18)(*wv.ravel())
+    c.rigid_beta = float(cfg.get("rigid_beta", 0.0))
+    c.no_stress_penalty = int(bool(cfg.get("no_stress_penalty", 0)))
     return c
 
 

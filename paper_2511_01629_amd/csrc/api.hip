@@ -102,6 +102,7 @@ int validate_cfg(const lbm_config *cfg, std::string &why, int &Q, int &d, int64_
     if (cfg->K < 1) return why = "K must be >= 1", LBM_EINVAL;
     if (!(cfg->rho_f > 0)) return why = "rho_f must be positive", LBM_EINVAL;
     if (cfg->eps_p <= 0 || cfg->eps_w <= 0 || cfg->delta <= 0) return why = "eps_p, eps_w, delta must be positive", LBM_EINVAL;
+    if (!(cfg->rigid_beta >= 0.0 && cfg->rigid_beta <= 1.0)) return why = "rigid_beta must lie in [0, 1]", LBM_EINVAL;
     // moving walls: one axis (y, or z in 3D), tangential, every other axis periodic
     int wall_axis = 0;
     for (int k = 0; k < 3; ++k)
@@ -272,10 +273,16 @@ int lbm::step_impl(lbm_ctx *c, int64_t nsteps, double *rec_dev)
             c->P.Uprev = c->P.U;
         } else if (c->rp.K == 1) {
             HIPCHK(c, timed(1, [](lbm_ctx *cc, void *r) { return launch_reduce(cc, 1, (double *)r); }, rec));
+            if (c->sp.beta > 0)
+                HIPCHK(c, timed(4, [](lbm_ctx *cc, void *b) { return launch_force(cc, ((void **)b)[0], ((void **)b)[1]); },
+                                bufs));
             HIPCHK(c, timed(2, [](lbm_ctx *cc, void *) { return launch_rigid_raster(cc, 1); }, nullptr));
             std::swap(c->P.X, c->P.Xn);
         } else {
             HIPCHK(c, timed(1, [](lbm_ctx *cc, void *r) { return launch_reduce(cc, 1, (double *)r); }, rec));
+            if (c->sp.beta > 0)
+                HIPCHK(c, timed(4, [](lbm_ctx *cc, void *b) { return launch_force(cc, ((void **)b)[0], ((void **)b)[1]); },
+                                bufs));
             HIPCHK(c, timed(2, [](lbm_ctx *cc, void *) { return launch_rigid_substeps(cc); }, nullptr));
             std::swap(c->P.X, c->P.Xn);
             HIPCHK(c, timed(3, [](lbm_ctx *cc, void *) { return launch_rigid_raster(cc, 0); }, nullptr));
@@ -350,6 +357,8 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
         if (c->sp.fluid_acc[k] != 0.0) c->sp.has_fluid_acc = 1;
     }
     c->sp.penalize_all = cfg->penalize_all != 0;
+    c->sp.beta = cfg->rigid_beta;
+    c->sp.stress = cfg->no_stress_penalty == 0;
     c->sp.alpha_tracks_tau = !(cfg->alpha > 0);
     double wall_tab[2][19];
     if (d == 2) wall_terms<D2Q9>(cfg, c->sp, wall_tab);
@@ -624,7 +633,7 @@ int install_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
     // period, so that a wavefront never holds nodes of two images of one box.
     // Otherwise the momentum sums run as a kernel of their own.
     c->fused = 0;
-    if (c->rp.K == 1 && n > 0) {
+    if (c->rp.K == 1 && n > 0 && !(c->sp.beta > 0)) { // the forcing pass needs the indicator after the sums
         const Geom &g = c->geo;
         int ext = 0;
         for (int i = 0; i < n; ++i) ext = std::max(ext, (int)ceil(2.0 * p[i].a) + 7);

@@ -73,6 +73,10 @@ struct StepParams {
     // population pulled from behind that wall gains ([2][19] doubles)
     int wall_axis;
     const double *wall_tab;
+    // rigid-velocity forcing (an extension): strength beta (0: off), and
+    // whether the penalization source of eq. (17) acts (1: the paper's method)
+    double beta;
+    int stress;
 };
 
 // Device pointers of one backward step of Algorithm 1 (see adjoint.hip).
@@ -179,6 +183,7 @@ hipError_t launch_init_uniform(lbm_ctx *c, void *fout, const double *feq);
 hipError_t launch_fields(lbm_ctx *c, const void *fin, double *u_out, double *p_out, int solid_only);
 hipError_t launch_populations(lbm_ctx *c, const void *fin, double *out, int q0, int nq);
 hipError_t launch_set_populations(lbm_ctx *c, const double *fn, void *fout, int q0, int nq);
+hipError_t launch_force(lbm_ctx *c, const void *fin, void *fout); // rigid-velocity forcing pass
 
 // particles.hip
 hipError_t launch_raster_clear(lbm_ctx *c);

@@ -873,7 +873,8 @@ hipError_t launch_reduce(lbm_ctx *c, int step, double *rec, int scratch)
 {
     if (c->np == 0) return hipSuccess;
     const uint16_t *oin = c->owner;
-    uint16_t *oclr = c->owner_next ? nullptr : c->owner;
+    // the rigid-velocity forcing pass reads the indicator after the sums and clears it
+    uint16_t *oclr = (c->owner_next || c->sp.beta > 0) ? nullptr : c->owner;
     const dim3 grid(c->np);
     const double *us = c->usol;
     PartDev P = c->P;

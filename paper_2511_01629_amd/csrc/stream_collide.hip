@@ -379,6 +379,54 @@ __global__ __launch_bounds__(256) void k_init_uniform(typename S::raw *__restric
 
 static inline unsigned blocks_for(int64_t N) { return (unsigned)((N + 255) / 256); }
 
+// Rigid-velocity forcing (an extension beyond the paper, lbm_config.rigid_beta
+// > 0): after the momentum sums of the step gave U_i^n and omega_i^n, the
+// nodes of each particle are collided again with the acceleration
+// a_g + 2 beta (U_i + omega_i x r - u), where u is the node's velocity with
+// the gravity acceleration a_g alone (eq. 15a) and r = x - X_i^n (nearest
+// image): eq. (15a) adds half the acceleration, so the velocity that enters
+// the equilibrium and the Guo force is (1 - beta) u + beta (U_i + omega_i x r).
+// One workgroup per particle walks its scan box; a node it owns is pulled
+// again from the step's input buffer (which the step leaves unchanged),
+// collided, written over the lattice kernel's unforced result, and its
+// indicator entry reset (the sums left the indicator in place for this pass).
+template <class L, class S, class T, int BS>
+__global__ __launch_bounds__(BS) void k_force(const typename S::raw *__restrict__ fin,
+                                              typename S::raw *__restrict__ fout, uint16_t *owner,
+                                              const T *__restrict__ acc_tab, PartDev P, int32_t *__restrict__ flags,
+                                              Geom g, StepParams sp)
+{
+    const int i = blockIdx.x;
+    const Box b = make_box(P.lo + 3 * i, P.hi + 3 * i);
+    const double X0 = P.X[3 * i], X1 = P.X[3 * i + 1], X2 = L::D == 3 ? P.X[3 * i + 2] : 0.0;
+    const double U0 = P.U[3 * i], U1 = P.U[3 * i + 1], U2 = P.U[3 * i + 2];
+    const double W0 = P.W[3 * i], W1 = P.W[3 * i + 1], W2 = P.W[3 * i + 2];
+    const T ag[3] = {acc_tab[3 * i], acc_tab[3 * i + 1], acc_tab[3 * i + 2]};
+    const T beta2 = (T)(2.0 * sp.beta);
+    const int N = (int)g.N;
+    CellWalk w(b.ext[0] > 0 ? b.ext[0] : 1, b.ext[1] > 0 ? b.ext[1] : 1, threadIdx.x, BS);
+    for (int cell = threadIdx.x; cell < b.cells; cell += BS) {
+        int xu, yu, zu;
+        const int idx = walk_node(b, w, g, xu, yu, zu);
+        w.next();
+        if (owner[idx] != (uint16_t)i) continue;
+        const int x = wrap(xu, g.nx), y = wrap(yu, g.ny), z = wrap(zu, g.nz);
+        T f[L::Q];
+        pull<L, S, T>(fin, idx, x, y, z, g, N, f);
+        wall_motion<L, T>(f, y, z, g, sp);
+        T ux, uy, uz, p;
+        moments<L, T>(f, ag[0], ag[1], ag[2], ux, uy, uz, p);
+        const double rx = (double)xu - X0, ry = (double)yu - X1, rz = L::D == 3 ? (double)zu - X2 : 0.0;
+        const double vx = U0 + (W1 * rz - W2 * ry), vy = U1 + (W2 * rx - W0 * rz), vz = U2 + (W0 * ry - W1 * rx);
+        const T acc[3] = {ag[0] + beta2 * ((T)vx - ux), ag[1] + beta2 * ((T)vy - uy),
+                          L::D == 3 ? ag[2] + beta2 * ((T)vz - uz) : T(0)};
+        collide_node<L, T>(f, 0, acc, sp, flags, nullptr, idx, N, ux, uy, uz);
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) st<S, T>(fout + q * N + idx, f[q]);
+        owner[idx] = FLUID;
+    }
+}
+
 hipError_t launch_stream_collide(lbm_ctx *c, const void *fin, void *fout)
 {
     const SlotParams sl = slot_params(c, c->fused != 0);
@@ -454,6 +502,19 @@ hipError_t launch_set_populations(lbm_ctx *c, const double *fn, void *fout, int 
         hipLaunchKernelGGL((k_set_populations<Lt, St, Tt>), dim3(blocks_for(c->geo.N)), dim3(256), 0, c->stream, fn,
                            (typename St::raw *)fout, q, c->geo, c->sp);
         return hipGetLastError();
+    });
+}
+
+hipError_t launch_force(lbm_ctx *c, const void *fin, void *fout)
+{
+    if (c->np == 0) return hipSuccess;
+    return dispatch(c, [&](auto L, auto S, auto T) {
+        using Lt = decltype(L);
+        using St = decltype(S);
+        using Tt = decltype(T);
+        const Tt *acc = std::is_same<Tt, double>::value ? (const Tt *)c->P.acc_d : (const Tt *)c->P.acc_f;
+        return launch(c, k_force<Lt, St, Tt, 256>, dim3(c->np), dim3(256), (const typename St::raw *)fin,
+                      (typename St::raw *)fout, c->owner, acc, c->P, c->flags, c->geo, c->sp);
     });
 }
 

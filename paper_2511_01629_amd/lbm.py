@@ -48,6 +48,7 @@ class Config(C.Structure):
         ("fluid_accel", C.c_double * 3), ("penalize_all", C.c_int32), ("device", C.c_int32),
         ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
         ("max_particles", C.c_int32), ("wall_velocity", C.c_double * 18), ("check_every", C.c_int32),
+        ("rigid_beta", C.c_double), ("no_stress_penalty", C.c_int32),
     ]
 
 
@@ -141,6 +142,8 @@ def make_config(cfg, storage=None, device=0, max_particles=0):
         wv[: w.shape[0], : w.shape[1], : w.shape[2]] = w
     c.wall_velocity = (C.c_double * 18)(*wv.ravel())
     c.check_every = int(cfg.get("check_every", 0))
+    c.rigid_beta = float(cfg.get("rigid_beta", 0.0))
+    c.no_stress_penalty = int(bool(cfg.get("no_stress_penalty", 0)))
     return c
 
 
@@ -259,7 +262,7 @@ class Simulation:
                                           g_rho.ctypes.data_as(C.POINTER(C.c_double)), C.byref(g_tau), C.byref(g_g)))
         return g_rho[: self.np], g_tau.value, g_g.value
 
-    KERNELS = ("stream_collide", "reduce_clear", "rigid_raster", "raster_after_substeps")
+    KERNELS = ("stream_collide", "reduce_clear", "rigid_raster", "raster_after_substeps", "rigid_forcing")
 
     def profile(self, enable=True):
         self._check(self.lib.lbm_profile(self.ctx, int(bool(enable))))

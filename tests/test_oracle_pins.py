@@ -307,8 +307,9 @@ def test_collision_force_wall():
 
 # ---------------------------------------------------------- whole step vs brute force
 
-def _compare_with_brute(kind, n, periodic, parts, g, steps, seed, K=1):
-    cfg = dict(lattice=kind, n=n, periodic=periodic, tau=0.7, g=g, eps_p=2.0, eps_w=1.0, delta=1.0, K=K)
+def _compare_with_brute(kind, n, periodic, parts, g, steps, seed, K=1, beta=0.0, no_stress_penalty=False):
+    cfg = dict(lattice=kind, n=n, periodic=periodic, tau=0.7, g=g, eps_p=2.0, eps_w=1.0, delta=1.0, K=K,
+               rigid_beta=beta, no_stress_penalty=int(no_stress_penalty))
     o = O.Oracle(cfg, parts)
     Q = 9 if kind == "D2Q9" else 19
     shp = (n[2] if kind == "D3Q19" else 1, n[1], n[0])
@@ -316,7 +317,7 @@ def _compare_with_brute(kind, n, periodic, parts, g, steps, seed, K=1):
     o.set_f(f0)
     o.reset_particles(parts)
     st = brute.initial_state(kind, n if len(n) == 3 else tuple(n) + (1,), periodic, 0.7, 0.0, 1.0, g, (0, 0, 0),
-                             parts, K=K)
+                             parts, K=K, beta=beta, no_stress_penalty=no_stress_penalty)
     for nd in st["f"]:
         x, y, z = nd
         st["f"][nd] = list(f0[z, y, x])
@@ -432,6 +433,102 @@ def test_gravity_form_momentum(gravity_form, expect):
     assert N > 100
     assert abs(P[1] - N * expect * g[1]) <= 1e-12 * abs(N * expect * g[1])
     assert abs(P[0]) < 1e-17
+
+
+# ------------------------------------- rigid-velocity forcing (an extension)
+
+@pytest.mark.parametrize("kind,beta,nopen", [("D2Q9", 0.6, False), ("D2Q9", 1.0, True), ("D3Q19", 0.5, False)])
+def test_rigid_forcing_vs_brute(kind, beta, nopen):
+    """The optional forcing toward the rigid motion U_i + omega_i x r (with and
+    without the stress penalization) over whole steps, bodies in contact,
+    against the independent brute-force transcription."""
+    if kind == "D2Q9":
+        parts = [dict(shape="disk", rho_s=1.6, a=2.2, x=(3.1, 3.2)),
+                 dict(shape="ellipse", rho_s=1.3, a=2.5, b=1.2, x=(7.6, 4.4), theta=0.4)]
+        _compare_with_brute("D2Q9", (9, 8, 1), (1, 0, 0), parts, (0.0, -1e-3, 0.0), 3, 1, beta=beta,
+                            no_stress_penalty=nopen)
+    else:
+        parts = [dict(shape="sphere", rho_s=1.6, a=1.6, x=(2.0, 2.1, 2.3)),
+                 dict(shape="sphere", rho_s=1.4, a=1.4, x=(3.4, 3.0, 3.9))]
+        _compare_with_brute("D3Q19", (5, 5, 6), (0, 1, 0), parts, (0.0, 0.0, -1e-3), 2, 2, beta=beta)
+
+
+def test_rigid_forcing_fixed_point():
+    """A body whose nodes already move rigidly (u = U0 + omega0 x r on a disk
+    centred on a node, so that the momentum sums return U0 and omega0
+    exactly) is a fixed point of the forcing: with beta = 1 the step equals
+    the unforced one to round-off."""
+    n = (40, 36, 1)
+    X = np.array([20.0, 17.0])
+    U0 = np.array([0.013, -0.007])
+    w0 = 2.3e-3
+    f = np.zeros((1, n[1], n[0], 9))
+    for y in range(n[1]):
+        for x in range(n[0]):
+            r = np.array([x, y]) - X
+            f[0, y, x] = O.feq("D2Q9", 0.0, U0 + w0 * np.array([-r[1], r[0]]))
+    out = []
+    for beta in (0.0, 1.0):
+        o = O.Oracle(dict(lattice="D2Q9", n=n, periodic=(1, 1, 0), tau=0.8, rigid_beta=beta),
+                     [dict(shape="disk", rho_s=1.0, a=7.0, x=tuple(X))])
+        o.set_f(f)
+        o.reset_particles([dict(shape="disk", rho_s=1.0, a=7.0, x=tuple(X))])
+        o.step(1)
+        out.append(o.f())
+    assert np.abs(out[1] - out[0]).max() < 1e-17 * 1e2
+
+
+@pytest.mark.parametrize("X,beta", [((20.0, 17.0), 0.7), ((20.3, 16.6), 0.7), ((20.3, 16.6), 0.25)])
+def test_rigid_forcing_momentum_and_torque(X, beta):
+    """What the forcing adds to the lattice over one step, against the
+    unforced step from the same state (periodic box, a random field confined
+    near the body, so streaming keeps the total momentum and the angular
+    momentum about X exactly): the added momentum is the sum of
+    2 beta (U + omega x r - u) over the body, which the sums of eq. (22)
+    reduce to 2 beta omega z x sum r, and the added angular momentum is
+    2 beta (sum r) x U; both vanish for a body centred on a node.  U and
+    omega are this step's sums (not the previous step's, which the state
+    holds as U_prev and differ here)."""
+    n = (48, 40, 1)
+    X = np.array(X)
+    rng = np.random.default_rng(3)
+    f = np.zeros((1, n[1], n[0], 9))
+    yy, xx = np.mgrid[0:n[1], 0:n[0]]
+    near = (xx - X[0]) ** 2 + (yy - X[1]) ** 2 <= 10.0 ** 2
+    f[0][near] = rng.normal(0, 2e-3, (near.sum(), 9))
+    body = [dict(shape="disk", rho_s=1.4, a=7.0, x=tuple(X))]
+    res = []
+    for b in (0.0, beta):
+        cfg = dict(lattice="D2Q9", n=n, periodic=(1, 1, 0), tau=0.8, g=(0.0, -1e-4, 0.0), rigid_beta=b)
+        o = O.Oracle(cfg, body)
+        o.set_f(f)
+        o.reset_particles(body)
+        P = o.particles()
+        raw = P["raw"].copy()
+        raw[:, 10:13] = [[0.004, -0.002, 0.0]]  # U^{n-1} unlike U^n
+        o.load_particles(raw, 0)
+        P = o.particles()
+        _, _, own = o.fields()
+        o.step(1)
+        fn = o.f()[0]
+        c, _, _ = _lat("D2Q9")
+        j = np.einsum("yxa,ak->yxk", fn, c)[..., :2]
+        M = j.reshape(-1, 2).sum(axis=0)
+        L = ((xx - X[0]) * j[..., 1] - (yy - X[1]) * j[..., 0]).sum()
+        res.append((M, L, P, own[0]))
+    (M0, L0, P, own), (M1, L1, _, _) = res
+    sel = own == 0
+    rs = np.stack([xx[sel] - X[0], yy[sel] - X[1]], axis=1).sum(axis=0)
+    U, w = P["U"][0, :2], P["omega"][0, 2]
+    dM_expect = 2 * beta * w * np.array([-rs[1], rs[0]])
+    dL_expect = 2 * beta * (rs[0] * U[1] - rs[1] * U[0])
+    scale = 2 * beta * sel.sum() * np.abs(U).max()
+    assert np.abs((M1 - M0) - dM_expect).max() <= 1e-12 * scale
+    assert abs((L1 - L0) - dL_expect) <= 1e-12 * scale * 7.0
+    if X[0] == int(X[0]) and X[1] == int(X[1]):
+        assert np.abs(rs).max() == 0.0
+    else:
+        assert np.abs(dM_expect).max() > 1e-6 * scale  # the centroid offset makes the pin non-trivial
 
 
 # ---------------------------------------------------------- conservation and textbook flows
