@@ -209,6 +209,17 @@ def copy_ceiling(nbytes=COPY_BYTES, reps=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(name, budget_s):
     """The FP64 oracle as it stands, on the host cores, on the first steps of
     the same workload until `budget_s` seconds of stepping have run."""
@@ -227,9 +238,24 @@ def cpu_baseline(name, budget_s):
         if el >= budget_s or steps >= 10000:
             break
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=N * steps / el / 1e6, unit="MLUPS", cores=cores, kind="oracle",
+    return dict(value=N * steps / el / 1e6, unit="MLUPS", cores=cores, kind="oracle", cpu=cpu_model(),
                 sample=f"{name}: {steps} FP64 steps of the full {N}-node lattice after one warm-up step "
                        f"({el:.1f} s)")
+
+
+def cpu_baseline_one_thread(name, budget_s):
+    """The same on one host thread, in a child process (the oracle's OpenMP
+    thread count is fixed when it loads); the child touches no GPU."""
+    import subprocess
+
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; "
+            "print(json.dumps(bench.cpu_baseline(%r, %r)))" % (ROOT, name, budget_s))
+    env = dict(os.environ, OMP_NUM_THREADS="1", HIP_VISIBLE_DEVICES="", ROCR_VISIBLE_DEVICES="")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        log(f"one-thread baseline failed: {r.stderr[-400:]}")
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def main():
@@ -282,6 +308,7 @@ def main():
             r = run_mode(name, storage, steps, max(10, args.warmup // 4))
             modes[f"{name}/{storage}"] = {k: r[k] for k in ("mlups", "ms_per_step", "kernel_gbs", "kernel_frac",
                                                              "kernel_avg_us", "breakdown_us")}
+            modes[f"{name}/{storage}"]["step_frac"] = r["step_gbs_alg"] / HBM_PEAK_GBS
             log(f"  {r['mlups']:.0f} MLUPS, fused kernel {r['kernel_gbs']:.0f} GB/s")
     if not args.no_modes:
         log("forward + adjoint adjoint_512x1024 f32 (5000 steps; checkpoint every 100, and every step kept)")
@@ -298,7 +325,11 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         cpu = cpu_baseline(args.workload, args.cpu_seconds)
-        log(f"  {cpu['value']:.1f} MLUPS on {cpu['cores']} threads")
+        log(f"  {cpu['value']:.1f} MLUPS on {cpu['cores']} threads ({cpu['cpu']})")
+        one = cpu_baseline_one_thread(args.workload, args.cpu_seconds)
+        if one:
+            cpu["one_thread"] = {"value": one["value"], "unit": "MLUPS", "cores": 1, "sample": one["sample"]}
+            log(f"  {one['value']:.1f} MLUPS on 1 thread")
 
     key = f"{args.workload}/{args.storage}"
     traffic = measured_traffic(key)
@@ -324,7 +355,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": head["kernel_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": head["kernel_frac"], "traffic": traffic,
                      "kernel": "k_stream_collide", "alg_bytes_per_launch": head["kernel_alg_bytes"],
-                     "avg_launch_us": head["kernel_avg_us"]},
+                     "avg_launch_us": head["kernel_avg_us"],
+                     # the whole step (lattice update + particle side) against the same peak
+                     "step_achieved": head["step_gbs_alg"], "step_frac": head["step_gbs_alg"] / HBM_PEAK_GBS},
         "step_breakdown_us": head["breakdown_us"],
         "copy_ceiling_gbs": ceiling,
         "modes": modes,
