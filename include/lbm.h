@@ -171,6 +171,20 @@ int lbm_set_particles(lbm_ctx *ctx, const lbm_particle *host_particles, int32_t 
  * the stop such forces may be missed. */
 int lbm_step(lbm_ctx *ctx, int64_t nsteps);
 
+/* lbm_step with the lattice cut into nslabs slabs along its last axis (y in
+ * 2D, z in 3D), the layout a run over nslabs GPUs would give each GPU,
+ * emulated on this one: each slab's populations live in buffers of their
+ * own with one halo row (plane) on each side, updated by a kernel of their
+ * own and exchanged every step by explicit device copies; each slab writes
+ * its solid nodes' momentum sums (eq. 22a-b) to a table of its own, and the
+ * tables are merged before Algorithm 1 runs once on the result (the
+ * cross-slab particle sums).  The state afterwards equals lbm_step's bit for
+ * bit.  The slab buffers are allocated by the library (about 2 Q s N bytes
+ * plus a slot table per extra slab) and kept for later calls.  EINVAL:
+ * nslabs outside [1, min(64, rows of the split axis)], K > 1, rigid_beta > 0.
+ * Waits for the stream and reports the sentinel like lbm_sync. */
+int lbm_step_slabs(lbm_ctx *ctx, int64_t nsteps, int32_t nslabs);
+
 /* As lbm_step, and write a per-step record of every particle into host_rec:
  * nsteps x n x 14 doubles, per particle X[3] theta U[3] omega[3] A[3] N of
  * step n (values before that step's update).  Waits for the stream. */

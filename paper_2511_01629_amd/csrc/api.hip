@@ -384,6 +384,8 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
     c->cur = 0;
     c->rec_dev = nullptr;
     c->rec_cap = 0;
+    c->slab_mem = nullptr;
+    c->slab_bytes = 0;
     c->owner_next = nullptr;
     c->slots = nullptr;
     c->slots_bytes = 0;
@@ -466,6 +468,7 @@ int lbm_destroy(lbm_ctx *c)
     if (c->own_mem) (void)hipFree(c->ws);
     if (c->rec_dev) (void)hipFree(c->rec_dev);
     if (c->slots) (void)hipFree(c->slots);
+    if (c->slab_mem) (void)hipFree(c->slab_mem);
     free_grad(c);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->poll_ev) (void)hipEventDestroy(c->poll_ev);

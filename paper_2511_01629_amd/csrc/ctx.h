@@ -139,6 +139,8 @@ struct lbm_ctx {
     int64_t step;
     double *rec_dev;
     size_t rec_cap;
+    void *slab_mem; // slab buffers and slot tables of lbm_step_slabs (library-owned)
+    size_t slab_bytes;
     std::vector<lbm_particle> host_parts; // inputs of the last lbm_set_particles
     // differentiated run (lbm_forward_checkpointed / lbm_backward)
     GradState *grad;

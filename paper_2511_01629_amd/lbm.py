@@ -26,7 +26,8 @@ EXPORTS = ["lbm_workspace_size", "lbm_create", "lbm_destroy", "lbm_set_particles
            "lbm_sync", "lbm_get_fields", "lbm_get_populations", "lbm_set_populations", "lbm_get_particles",
            "lbm_get_step", "lbm_last_error", "lbm_profile", "lbm_profile_read", "lbm_copy",
            "lbm_forward_checkpointed", "lbm_backward", "lbm_get_fields_device", "lbm_set_params",
-           "lbm_state_size", "lbm_save_state", "lbm_load_state", "lbm_step_record_noalloc"]
+           "lbm_state_size", "lbm_save_state", "lbm_load_state", "lbm_step_record_noalloc",
+           "lbm_step_slabs"]
 
 
 class LbmUnavailable(RuntimeError):
@@ -102,6 +103,7 @@ def load():
     lib.lbm_save_state.argtypes = [P, P]
     lib.lbm_load_state.argtypes = [P, P]
     lib.lbm_step_record_noalloc.argtypes = [P, I64, dp]
+    lib.lbm_step_slabs.argtypes = [P, I64, I32]
     _LIB = lib
     return lib
 
@@ -226,6 +228,11 @@ class Simulation:
 
     def step(self, n=1):
         self._check(self.lib.lbm_step(self.ctx, int(n)))
+
+    def step_slabs(self, n, nslabs=2):
+        """n steps with the lattice cut into nslabs slabs (explicit halo
+        copies and cross-slab momentum sums); same result as step(n)."""
+        self._check(self.lib.lbm_step_slabs(self.ctx, int(n), int(nslabs)))
 
     def step_record(self, n):
         rec = np.zeros((int(n), max(self.np, 1), 14))

@@ -109,7 +109,7 @@ def test_null_arguments():
                lib.lbm_profile_read(None, None, None, 0), lib.lbm_get_step(None, C.byref(step)),
                lib.lbm_get_fields_device(None, None, None, None), lib.lbm_set_params(None, None, 0.0, None),
                lib.lbm_state_size(None, C.byref(size)), lib.lbm_save_state(None, None),
-               lib.lbm_load_state(None, None)):
+               lib.lbm_load_state(None, None), lib.lbm_step_slabs(None, 1, 2)):
         assert rc == lbm.LBM_EINVAL
     assert lib.lbm_workspace_size(C.byref(lbm.make_config(_base())), None) == lbm.LBM_EINVAL
     # lbm_copy: NULL with bytes > 0, misaligned pointers, sizes that are not whole 16-byte words
