@@ -805,3 +805,21 @@ def test_complex_step_matches_finite_differences():
         ref = fd(mod, h)
         assert abs(dl) > 0
         assert abs(dl - ref) <= 1e-5 * abs(ref), (dl, ref)
+
+
+def test_stored_gradient_complex_step_vs_central_differences():
+    """The stored oracle gradient of the differentiated workload (5000 steps,
+    tests/golden/adjoint_512x1024_grad.json, written by the script beside it):
+    the complex-step derivative agrees with the central differences of the
+    replayed oracle for every parameter that has them (all 18 once the
+    script has run them all), to the differences' own accuracy."""
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_512x1024_grad.json")
+    gold = json.load(open(path))
+    cs, fd = np.asarray(gold["grad_complex_step"]), gold["grad_central_diff"]
+    have = [k for k, v in enumerate(fd) if v is not None]
+    assert len(have) >= 4
+    for k in have:
+        assert abs(cs[k] - fd[k]) <= 1e-6 * abs(fd[k]), (gold["params"][k], cs[k], fd[k])
