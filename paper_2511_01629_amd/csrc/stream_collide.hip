@@ -96,6 +96,72 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename S::raw *__
     }
 }
 
+// The 2D update with NS adjacent segments of one row per workgroup, every
+// lane issuing the loads of all its NS nodes before it converts any: on a
+// lattice whose single-segment grid is at most two rounds of workgroups (the
+// cache-resident differentiated workload: 9.25 -> 8.33 us per step on
+// 512x1024 in FP32), fewer, longer workgroups finish sooner; on the 2048x4096
+// lattice the same kernel is 10 % slower (FP32) and stays unused there.
+// Node arithmetic as in k_stream_collide, so the results are the same bits.
+template <class L, class S, class T, int BS, int NS>
+__global__ __launch_bounds__(BS) void k_stream_collide_multi(const typename S::raw *__restrict__ fin,
+                                                           typename S::raw *__restrict__ fout, const uint16_t *owner,
+                                                           const T *__restrict__ acc_tab, double *__restrict__ usol,
+                                                           int32_t *__restrict__ flags, Geom g, StepParams sp, int gxw,
+                                                           unsigned gxm, SlotParams sl)
+{
+    static_assert(L::D == 2, "2D rows");
+    const int row = div_magic((int)blockIdx.x, gxw, gxm);
+    const int bw = (int)blockIdx.x - row * gxw; // uniform
+    const int y = row, z = 0;
+    const int N = (int)g.N;
+    using R = decltype(ld_reg<S>(fin));
+    R r[NS][L::Q];
+    uint16_t own[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const int seg = bw * NS + k;
+        const int x = seg * BS + (int)threadIdx.x;
+        const int idx = row * g.nx + x;
+        own[k] = FLUID;
+        if (x < g.nx) {
+            const RowPull<L> rp(x, y, z, idx, seg > 0 && seg * BS + BS < g.nx, g);
+            if (rp.interior) { // uniform
+#pragma unroll
+                for (int q = 0; q < L::Q; ++q) {
+                    const typename S::raw *src = fin + (q * rp.N + rp.rb[L::cy[q] + 1][L::cz[q] + 1] - L::cx[q]);
+                    r[k][q] = ld_reg<S>(src + (unsigned)rp.x);
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < L::Q; ++q) r[k][q] = ld_reg<S>(fin + rp.offset(q));
+            }
+            own[k] = owner[idx];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const int x = (bw * NS + k) * BS + (int)threadIdx.x;
+        const int idx = row * g.nx + x;
+        const bool valid = x < g.nx;
+        T ux = 0, uy = 0, uz = 0;
+        if (valid) {
+            T f[L::Q];
+#pragma unroll
+            for (int q = 0; q < L::Q; ++q) f[q] = from_reg<S, T>(r[k][q]);
+            wall_motion<L, T>(f, y, z, g, sp);
+            collide_node<L, T>(f, own[k], acc_tab, sp, flags, usol, idx, N, ux, uy, uz);
+#pragma unroll
+            for (int q = 0; q < L::Q; ++q) st<S, T>(fout + q * N + idx, f[q]);
+        }
+        if (sl.slots) { // uniform
+            const bool solid = valid && own[k] != FLUID;
+            slot_sums<L::D>(solid, own[k], x, y, z, (double)ux, (double)uy, (double)uz, sl);
+            if (solid && sl.clear) sl.clear[idx] = FLUID;
+        }
+    }
+}
+
 // D3Q19 variant with the source rows staged through LDS, so that every
 // global access is a wide aligned vector.  A workgroup of TPB threads owns a
 // segment of W = NPL * TPB nodes of one row, NPL = 16 / element size (8 for
@@ -453,6 +519,17 @@ hipError_t launch_stream_collide(lbm_ctx *c, const void *fin, void *fout)
                 if (c->geo.nx >= 128 * NPL) return staged(std::integral_constant<int, 128>{});
                 return staged(std::integral_constant<int, 64>{});
             }
+        }
+        if constexpr (Lt::D == 2 && sizeof(typename St::raw) <= 4) {
+            auto multi = [&](auto ns) {
+                constexpr int NS = decltype(ns)::value;
+                const int gxw = (c->geo.nx + 256 * NS - 1) / (256 * NS);
+                return launch(c, k_stream_collide_multi<Lt, St, Tt, 256, NS>, dim3((unsigned)(gxw * c->geo.ny)),
+                              dim3(256), (const typename St::raw *)fin, (typename St::raw *)fout,
+                              (const uint16_t *)c->owner, acc, usol, c->flags, c->geo, c->sp, gxw, magic_for(gxw), sl);
+            };
+            const int64_t blocks1 = (int64_t)((c->geo.nx + 255) / 256) * c->geo.ny;
+            if (blocks1 <= 4096) return multi(std::integral_constant<int, 2>{});
         }
         constexpr bool d2f64 = Lt::D == 2 && sizeof(Tt) == 8;
         constexpr int BS = d2f64 ? 512 : 256;
