@@ -300,6 +300,22 @@ int lbm_forward_checkpointed(lbm_ctx *ctx, int64_t nsteps, int32_t every);
  * lbm_load_state discard the run's checkpoints.) */
 int lbm_backward(lbm_ctx *ctx, const double *dL_dX, double *g_rho_s, double *g_tau, double *g_gmag);
 
+/* The same two calls with every device buffer they need taken from
+ * caller-owned device memory (e.g. torch tensors) instead of the library's
+ * allocations: lbm_grad_workspace_size gives, for a run of nsteps steps with
+ * checkpoints every `every` steps on the context as it is set up now, the
+ * bytes of the forward workspace (the per-step particle records and the
+ * snapshots, or every frame when every = 1; it must stay allocated and
+ * untouched until the run's last lbm_backward_ws, or until the next
+ * differentiated run, lbm_set_particles, lbm_set_params or lbm_load_state)
+ * and of the backward workspace (segment frames, adjoint populations and
+ * partial sums; needed only during the call).  ENOMEM if a workspace is
+ * smaller than that; EINVAL for a NULL workspace.  The library frees neither. */
+int lbm_grad_workspace_size(lbm_ctx *ctx, int64_t nsteps, int32_t every, size_t *fwd_bytes, size_t *bwd_bytes);
+int lbm_forward_checkpointed_ws(lbm_ctx *ctx, int64_t nsteps, int32_t every, void *dev_ws, size_t ws_bytes);
+int lbm_backward_ws(lbm_ctx *ctx, const double *dL_dX, double *g_rho_s, double *g_tau, double *g_gmag, void *dev_ws,
+                    size_t ws_bytes);
+
 /* Per-kernel timing with HIP events (measurement aid).  While enabled,
  * every kernel lbm_step queues records its own start and end in a pair of
  * events (the kernel's execution, without the dispatch latency), and lbm_step waits

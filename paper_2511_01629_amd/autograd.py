@@ -12,7 +12,9 @@ library; this module only marshals tensors.
 A Run keeps one library context: its first forward creates it and saves, on
 the device, the state right after the particles were set; every forward
 loads that state back and sets the parameters (lbm_set_params, which also
-measures U^0 again with them), so no context is rebuilt per forward.  The
+measures U^0 again with them), so no context is rebuilt per forward; the
+checkpoints and the backward's scratch are torch tensors (torch's allocator
+owns every buffer of the differentiated run).  The
 checkpoints belong to the context, so a Run holds one differentiated run at
 a time: backward through an earlier forward of the same Run raises.
 """
@@ -60,7 +62,7 @@ class LbmTrajectory(torch.autograd.Function):
         sim = _context(run)
         sim.load_state(run.start)
         sim.set_params(rho_s=rho, tau=_number(tau), g=g / g0 * _number(gmag))
-        sim.forward_checkpointed(run.steps, run.every)
+        sim.forward_checkpointed(run.steps, run.every, torch_memory=True)
         X = sim.particles()["X"]
         run.generation += 1
         ctx.sim = sim

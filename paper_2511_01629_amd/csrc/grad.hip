@@ -36,6 +36,7 @@ struct GradState {
     std::vector<int> snapCur;
     std::vector<int64_t> snapStep;
     double *rec = nullptr; // T x np x REC_STRIDE
+    std::vector<void *> owned; // library allocations (none when the caller supplied the memory)
 };
 
 namespace {
@@ -106,13 +107,107 @@ int run_frames(lbm_ctx *c, GradState *G, char *fr, char *ow, int64_t n, double *
     return rc;
 }
 
-template <class Tp> int dev_alloc(lbm_ctx *c, Tp **p, size_t n, std::vector<void *> &owned)
+// The memory of a differentiated run, taken piece by piece (each 256-byte
+// aligned): allocated by the library (base == NULL, count == false; freed with
+// the run), carved from a caller's buffer of `cap` bytes (never freed here),
+// or only counted (count == true: a size query).
+struct Carver {
+    lbm_ctx *c;
+    char *base;
+    size_t cap;
+    bool count;
+    std::vector<void *> *owned;
+    size_t off = 0;
+
+    template <class Tp> int take(Tp **p, size_t n, bool zero)
+    {
+        const size_t bytes = (std::max<size_t>(n, 1) * sizeof(Tp) + 255) / 256 * 256;
+        *p = nullptr;
+        if (count) {
+            off += bytes;
+            return LBM_OK;
+        }
+        if (base) {
+            if (off + bytes > cap) return c->err = "the caller's workspace is too small", LBM_ENOMEM;
+            *p = (Tp *)(base + off);
+        } else {
+            const hipError_t e = hipMalloc((void **)p, bytes);
+            if (e != hipSuccess) return c->err = std::string("hipMalloc: ") + hipGetErrorString(e), LBM_ENOMEM;
+            owned->push_back(*p);
+        }
+        off += bytes;
+        if (zero) HIPCHK(c, hipMemsetAsync(*p, 0, bytes, c->stream));
+        return LBM_OK;
+    }
+};
+
+size_t frame_bytes(const lbm_ctx *c) { return (size_t)c->Q * c->geo.N * storage_bytes(c->cfg.storage); }
+size_t owner_bytes(const lbm_ctx *c) { return (size_t)((c->geo.N + 1) / 2 * 2) * sizeof(uint16_t); }
+
+// The forward run's pieces: the particle records, then the frames (every = 1)
+// or the snapshots.
+int carve_forward(Carver &m, int64_t T, int every, size_t fbytes, size_t obytes, size_t pbytes, double **rec,
+                  char **hist, char **snap)
 {
-    HIPCHK(c, hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(Tp)));
-    owned.push_back(*p);
-    HIPCHK(c, hipMemsetAsync(*p, 0, std::max<size_t>(n, 1) * sizeof(Tp), c->stream));
-    return LBM_OK;
+    const int nsnap = (int)((T + every - 1) / every) + 1;
+    *hist = *snap = nullptr;
+    int rc = m.take(rec, (size_t)T * m.c->np * REC_STRIDE, false);
+    if (!rc && every == 1) rc = m.take(hist, (size_t)(T + 1) * (fbytes + obytes), false);
+    if (!rc && every > 1) rc = m.take(snap, (size_t)nsnap * (fbytes + obytes + pbytes), false);
+    return rc;
 }
+
+// The backward sweep's pieces (lbm_backward): per-(particle, slot) records of
+// the a_bar sums where the forward step has slots; one or two segment buffers
+// of every + 1 frames; particle constants; the two adjoint population
+// buffers; the per-node a_bar field (without slots); per-workgroup tau
+// partials; the particle adjoints.
+struct BackBufs {
+    double *aslots = nullptr;
+    char *seg = nullptr, *seg2 = nullptr, *lam = nullptr;
+    double *cst = nullptr;
+    int32_t *cshape = nullptr;
+    double *asol = nullptr, *taup = nullptr, *Xbar = nullptr, *Abar = nullptr, *Upbar = nullptr, *rho_g = nullptr,
+           *g_g = nullptr, *uext_d = nullptr, *acc_d = nullptr;
+    float *uext_f = nullptr, *acc_f = nullptr;
+};
+
+int carve_backward(Carver &m, int64_t T, int every, size_t fbytes, size_t obytes, BackBufs &b)
+{
+    lbm_ctx *c = m.c;
+    const int np = c->np, Q = c->Q;
+    const int64_t N = c->geo.N;
+    const size_t lam_elt = c->cfg.storage == LBM_F64 ? 8 : 4;
+    const size_t nblocks = (size_t)((c->geo.nx + 255) / 256) * c->geo.ny * c->geo.nz;
+    const bool all = every == 1;
+    const int nseg = all ? 1 : (int)((T + every - 1) / every);
+    const bool overlap = !all && nseg > 1;
+    const size_t segsize = all ? 1 : (size_t)(every + 1) * (fbytes + obytes); // every + 1 frames of each
+    const bool slots = c->fused && c->slots && np > 0;
+    int rc = LBM_OK;
+    if (slots) rc = m.take(&b.aslots, (size_t)np * (size_t)c->slot_stride * (size_t)(c->d + 1), false);
+    if (!rc) rc = m.take(&b.seg, segsize, true);
+    if (!rc && overlap) rc = m.take(&b.seg2, segsize, true);
+    if (!rc) rc = m.take(&b.cst, 4 * (size_t)np, true);
+    if (!rc) rc = m.take(&b.cshape, (size_t)np, true);
+    if (!rc) rc = m.take(&b.lam, 2 * Q * N * lam_elt, true);
+    if (!rc) rc = m.take(&b.asol, slots ? 1 : (size_t)c->d * N, true);
+    if (!rc) rc = m.take(&b.taup, nblocks, true);
+    if (!rc) rc = m.take(&b.Xbar, 6 * (size_t)np, true);
+    if (!rc) rc = m.take(&b.Abar, 3 * (size_t)np, true);
+    if (!rc) rc = m.take(&b.Upbar, 6 * (size_t)np, true);
+    if (!rc) rc = m.take(&b.rho_g, np, true);
+    if (!rc) rc = m.take(&b.g_g, np, true);
+    if (!rc) rc = m.take(&b.uext_d, 3 * (size_t)np, true);
+    if (!rc) rc = m.take(&b.acc_d, 3 * (size_t)np, true);
+    if (!rc) rc = m.take(&b.uext_f, 3 * (size_t)np, true);
+    if (!rc) rc = m.take(&b.acc_f, 3 * (size_t)np, true);
+    return rc;
+}
+
+int forward_impl(lbm_ctx *c, int64_t nsteps, int32_t every, void *ws, size_t ws_bytes);
+int backward_impl(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau, double *g_gmag, void *ws,
+                  size_t ws_bytes);
 
 } // namespace
 
@@ -120,9 +215,7 @@ void lbm::free_grad(lbm_ctx *c)
 {
     if (!c->grad) return;
     (void)hipStreamSynchronize(c->stream);
-    if (c->grad->snap) (void)hipFree(c->grad->snap);
-    if (c->grad->hist) (void)hipFree(c->grad->hist);
-    if (c->grad->rec) (void)hipFree(c->grad->rec);
+    for (void *p : c->grad->owned) (void)hipFree(p);
     delete c->grad;
     c->grad = nullptr;
 }
@@ -131,7 +224,47 @@ extern "C" {
 
 int lbm_forward_checkpointed(lbm_ctx *c, int64_t nsteps, int32_t every)
 {
+    return c ? forward_impl(c, nsteps, every, nullptr, 0) : LBM_EINVAL;
+}
+
+int lbm_forward_checkpointed_ws(lbm_ctx *c, int64_t nsteps, int32_t every, void *ws, size_t ws_bytes)
+{
     if (!c) return LBM_EINVAL;
+    if (!ws) return c->err = "workspace is NULL", LBM_EINVAL;
+    return forward_impl(c, nsteps, every, ws, ws_bytes);
+}
+
+int lbm_backward_ws(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau, double *g_gmag, void *ws,
+                    size_t ws_bytes)
+{
+    if (!c || !dL_dX) return LBM_EINVAL;
+    if (!ws) return c->err = "workspace is NULL", LBM_EINVAL;
+    return backward_impl(c, dL_dX, g_rho_s, g_tau, g_gmag, ws, ws_bytes);
+}
+
+int lbm_grad_workspace_size(lbm_ctx *c, int64_t nsteps, int32_t every, size_t *fwd_bytes, size_t *bwd_bytes)
+{
+    if (!c) return LBM_EINVAL;
+    if (nsteps < 1 || every < 1) return c->err = "nsteps and every must be >= 1", LBM_EINVAL;
+    const size_t fb = frame_bytes(c), ob = owner_bytes(c);
+    Carver f{c, nullptr, 0, true, nullptr};
+    double *rec;
+    char *hist, *snap;
+    carve_forward(f, nsteps, every, fb, ob, part_bytes(c), &rec, &hist, &snap);
+    Carver b{c, nullptr, 0, true, nullptr};
+    BackBufs bb;
+    carve_backward(b, nsteps, every, fb, ob, bb);
+    if (fwd_bytes) *fwd_bytes = f.off;
+    if (bwd_bytes) *bwd_bytes = b.off;
+    return LBM_OK;
+}
+
+} // extern "C"
+
+namespace {
+
+int forward_impl(lbm_ctx *c, int64_t nsteps, int32_t every, void *ws, size_t ws_bytes)
+{
     if (nsteps < 1 || every < 1) return c->err = "nsteps and every must be >= 1", LBM_EINVAL;
     if (!c->fresh) return c->err = "a differentiated run must start right after lbm_set_particles", LBM_ESTATE;
     if (c->np == 0) return c->err = "no particles", LBM_ESTATE;
@@ -148,13 +281,19 @@ int lbm_forward_checkpointed(lbm_ctx *c, int64_t nsteps, int32_t every)
     G->T = nsteps;
     G->every = every;
     G->nsnap = (int)((nsteps + every - 1) / every) + 1; // segment starts + final state
-    G->fbytes = (size_t)c->Q * c->geo.N * storage_bytes(c->cfg.storage);
-    G->obytes = (size_t)((c->geo.N + 1) / 2 * 2) * sizeof(uint16_t);
+    G->fbytes = frame_bytes(c);
+    G->obytes = owner_bytes(c);
     G->pbytes = part_bytes(c);
-    HIPCHK(c, hipMalloc((void **)&G->rec, (size_t)nsteps * c->np * REC_STRIDE * sizeof(double)));
+    {
+        Carver m{c, (char *)ws, ws_bytes, false, &G->owned};
+        const int rc = carve_forward(m, nsteps, every, G->fbytes, G->obytes, G->pbytes, &G->rec, &G->hist, &G->snap);
+        if (rc) {
+            free_grad(c);
+            return rc;
+        }
+    }
     if (every == 1) {
         // keep every frame: step n reads frame n and writes frame n + 1
-        HIPCHK(c, hipMalloc((void **)&G->hist, (size_t)(nsteps + 1) * (G->fbytes + G->obytes)));
         char *fr = G->hist, *ow = G->hist + (size_t)(nsteps + 1) * G->fbytes;
         HIPCHK(c, hipMemcpyAsync(fr, c->f[c->cur], G->fbytes, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(ow, c->owner, G->obytes, hipMemcpyDeviceToDevice, c->stream));
@@ -171,7 +310,6 @@ int lbm_forward_checkpointed(lbm_ctx *c, int64_t nsteps, int32_t every)
     G->snapP.resize(G->nsnap);
     G->snapCur.resize(G->nsnap);
     G->snapStep.resize(G->nsnap);
-    HIPCHK(c, hipMalloc((void **)&G->snap, (size_t)G->nsnap * (G->fbytes + G->obytes + G->pbytes)));
     for (int64_t s = 0; s < nsteps; ++s) {
         if (s % every == 0) {
             int rc = snapshot(c, G, (int)(s / every));
@@ -186,9 +324,9 @@ int lbm_forward_checkpointed(lbm_ctx *c, int64_t nsteps, int32_t every)
     return lbm_sync(c);
 }
 
-int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau, double *g_gmag)
+int backward_impl(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau, double *g_gmag, void *ws,
+                  size_t ws_bytes)
 {
-    if (!c || !dL_dX) return LBM_EINVAL;
     GradState *G = c->grad;
     if (!G) return c->err = "no differentiated forward run to go back through", LBM_ESTATE;
     if (G->np != c->np || G->fused != c->fused || G->slot_stride != c->slot_stride)
@@ -220,45 +358,32 @@ int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau
         }
         for (void *p : owned) (void)hipFree(p);
     };
-    char *seg = nullptr, *seg2 = nullptr, *lam = nullptr;
-    double *cst = nullptr;
-    int32_t *cshape = nullptr;
-    double *asol = nullptr, *taup = nullptr, *Xbar = nullptr, *Abar = nullptr, *Upbar = nullptr, *rho_g = nullptr,
-           *g_g = nullptr, *uext_d = nullptr, *acc_d = nullptr;
-    float *uext_f = nullptr, *acc_f = nullptr;
     const bool all = G->hist != nullptr;
     const int nseg = all ? 1 : G->nsnap - 1;
     const bool overlap = !all && nseg > 1;
-    // segment frames: every + 1 population buffers, then every + 1 indicators
-    const size_t segsize = all ? 1 : (size_t)(G->every + 1) * (G->fbytes + G->obytes);
     int rc = LBM_OK;
-    // per-(particle, slot) records of the lattice adjoint's a_bar sums, where
-    // the forward step has a slot layout (else a_bar goes to asol per node)
-    double *aslots = nullptr;
-    int64_t astamp = 0;
-    if (c->fused && c->slots && np > 0) {
-        const size_t nrec = (size_t)np * (size_t)c->slot_stride * (size_t)(c->d + 1);
-        if ((rc = dev_alloc(c, &aslots, nrec, owned))) {
+    BackBufs bb;
+    {
+        Carver m{c, (char *)ws, ws_bytes, false, &owned};
+        if ((rc = carve_backward(m, G->T, G->every, G->fbytes, G->obytes, bb))) {
             cleanup();
             return rc;
         }
-        // NaN stamps: no record counts until a step writes it
-        if (hipMemsetAsync(aslots, 0xFF, nrec * sizeof(double), c->stream) != hipSuccess) {
-            cleanup();
-            return c->err = "slot initialisation failed", LBM_EDEVICE;
-        }
     }
-    if ((rc = dev_alloc(c, &seg, segsize, owned)) || (overlap && (rc = dev_alloc(c, &seg2, segsize, owned))) ||
-        (rc = dev_alloc(c, &cst, 4 * (size_t)np, owned)) || (rc = dev_alloc(c, &cshape, (size_t)np, owned)) ||
-        (rc = dev_alloc(c, &lam, 2 * Q * N * lam_elt, owned)) ||
-        (rc = dev_alloc(c, &asol, aslots ? 1 : (size_t)c->d * N, owned)) || (rc = dev_alloc(c, &taup, nblocks, owned)) ||
-        (rc = dev_alloc(c, &Xbar, 6 * (size_t)np, owned)) || (rc = dev_alloc(c, &Abar, 3 * (size_t)np, owned)) ||
-        (rc = dev_alloc(c, &Upbar, 6 * (size_t)np, owned)) || (rc = dev_alloc(c, &rho_g, np, owned)) ||
-        (rc = dev_alloc(c, &g_g, np, owned)) || (rc = dev_alloc(c, &uext_d, 3 * (size_t)np, owned)) ||
-        (rc = dev_alloc(c, &acc_d, 3 * (size_t)np, owned)) || (rc = dev_alloc(c, &uext_f, 3 * (size_t)np, owned)) ||
-        (rc = dev_alloc(c, &acc_f, 3 * (size_t)np, owned))) {
+    char *seg = bb.seg, *seg2 = bb.seg2, *lam = bb.lam;
+    double *cst = bb.cst;
+    int32_t *cshape = bb.cshape;
+    double *asol = bb.asol, *taup = bb.taup, *Xbar = bb.Xbar, *Abar = bb.Abar, *Upbar = bb.Upbar, *rho_g = bb.rho_g,
+           *g_g = bb.g_g, *uext_d = bb.uext_d, *acc_d = bb.acc_d;
+    float *uext_f = bb.uext_f, *acc_f = bb.acc_f;
+    // per-(particle, slot) records of the lattice adjoint's a_bar sums, where
+    // the forward step has a slot layout (else a_bar goes to asol per node)
+    double *aslots = bb.aslots;
+    int64_t astamp = 0;
+    if (aslots && hipMemsetAsync(aslots, 0xFF, (size_t)np * c->slot_stride * (c->d + 1) * sizeof(double),
+                                 c->stream) != hipSuccess) { // NaN stamps: no record counts until a step writes it
         cleanup();
-        return rc;
+        return c->err = "slot initialisation failed", LBM_EDEVICE;
     }
     // the particle constants the adjoint kernels read, in memory of their own
     // (a snapshot restore on the side stream rewrites the workspace copies)
@@ -413,4 +538,11 @@ int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau
     return rr;
 }
 
-} // extern "C"
+} // namespace
+
+extern "C" int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau, double *g_gmag)
+{
+    if (!c || !dL_dX) return LBM_EINVAL;
+    return backward_impl(c, dL_dX, g_rho_s, g_tau, g_gmag, nullptr, 0);
+}
+

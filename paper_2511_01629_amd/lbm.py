@@ -27,7 +27,7 @@ EXPORTS = ["lbm_workspace_size", "lbm_create", "lbm_destroy", "lbm_set_particles
            "lbm_get_step", "lbm_last_error", "lbm_profile", "lbm_profile_read", "lbm_copy",
            "lbm_forward_checkpointed", "lbm_backward", "lbm_get_fields_device", "lbm_set_params",
            "lbm_state_size", "lbm_save_state", "lbm_load_state", "lbm_step_record_noalloc",
-           "lbm_step_slabs"]
+           "lbm_step_slabs", "lbm_grad_workspace_size", "lbm_forward_checkpointed_ws", "lbm_backward_ws"]
 
 
 class LbmUnavailable(RuntimeError):
@@ -104,6 +104,9 @@ def load():
     lib.lbm_load_state.argtypes = [P, P]
     lib.lbm_step_record_noalloc.argtypes = [P, I64, dp]
     lib.lbm_step_slabs.argtypes = [P, I64, I32]
+    lib.lbm_grad_workspace_size.argtypes = [P, I64, I32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+    lib.lbm_forward_checkpointed_ws.argtypes = [P, I64, I32, P, C.c_size_t]
+    lib.lbm_backward_ws.argtypes = [P, dp, dp, dp, dp, P, C.c_size_t]
     _LIB = lib
     return lib
 
@@ -255,8 +258,24 @@ class Simulation:
         self._check(self.lib.lbm_get_step(self.ctx, C.byref(s)))
         return s.value
 
-    def forward_checkpointed(self, nsteps, every):
-        self._check(self.lib.lbm_forward_checkpointed(self.ctx, int(nsteps), int(every)))
+    def grad_workspace_size(self, nsteps, every):
+        f, b = C.c_size_t(), C.c_size_t()
+        self._check(self.lib.lbm_grad_workspace_size(self.ctx, int(nsteps), int(every), C.byref(f), C.byref(b)))
+        return int(f.value), int(b.value)
+
+    def forward_checkpointed(self, nsteps, every, torch_memory=False):
+        """The differentiated forward run.  torch_memory: its checkpoints live
+        in a torch tensor held by this object (torch's allocator owns them),
+        and backward() takes its scratch from torch too."""
+        self._grad_torch = bool(torch_memory)
+        if not torch_memory:
+            self._fwd_ws = None
+            self._check(self.lib.lbm_forward_checkpointed(self.ctx, int(nsteps), int(every)))
+            return
+        fb, self._bwd_bytes = self.grad_workspace_size(nsteps, every)
+        self._fwd_ws = self.torch.empty(fb, dtype=self.torch.uint8, device=self.workspace.device)
+        self._check(self.lib.lbm_forward_checkpointed_ws(self.ctx, int(nsteps), int(every),
+                                                         C.c_void_p(self._fwd_ws.data_ptr()), fb))
 
     def backward(self, dL_dX):
         """Gradients (d rho_s [n], d tau, d |g|) of a loss whose gradient with
@@ -265,8 +284,16 @@ class Simulation:
         g_rho = np.zeros(max(self.np, 1))
         g_tau = C.c_double()
         g_g = C.c_double()
-        self._check(self.lib.lbm_backward(self.ctx, seed.ctypes.data_as(C.POINTER(C.c_double)),
-                                          g_rho.ctypes.data_as(C.POINTER(C.c_double)), C.byref(g_tau), C.byref(g_g)))
+        dp = C.POINTER(C.c_double)
+        if getattr(self, "_grad_torch", False):
+            ws = self.torch.empty(self._bwd_bytes, dtype=self.torch.uint8, device=self.workspace.device)
+            self._check(self.lib.lbm_backward_ws(self.ctx, seed.ctypes.data_as(dp), g_rho.ctypes.data_as(dp),
+                                                 C.byref(g_tau), C.byref(g_g), C.c_void_p(ws.data_ptr()),
+                                                 self._bwd_bytes))
+            del ws
+        else:
+            self._check(self.lib.lbm_backward(self.ctx, seed.ctypes.data_as(dp), g_rho.ctypes.data_as(dp),
+                                              C.byref(g_tau), C.byref(g_g)))
         return g_rho[: self.np], g_tau.value, g_g.value
 
     KERNELS = ("stream_collide", "reduce_clear", "rigid_raster", "raster_after_substeps", "rigid_forcing")

@@ -215,3 +215,35 @@ def test_adjoint_many_bodies_f64():
     go = oracle_gradient(cfg, parts, steps, w)
     ga = gpu_gradient(cfg, parts, steps, 10, w)
     _check(ga, go, 1e-8)
+
+
+@pytest.mark.parametrize("every", [1, 8])
+def test_adjoint_in_caller_memory(every):
+    """lbm_forward_checkpointed_ws / lbm_backward_ws with every buffer in torch
+    tensors (sized by lbm_grad_workspace_size) give the library-allocated
+    run's gradients bit for bit; a workspace one byte short is rejected with
+    ENOMEM."""
+    banner(f"adjoint in caller memory every={every}")
+    kinds = [("disk", 5.0, 5.0)] * 4 + [("ellipse", 6.0, 3.0)] * 2
+    parts = place((64, 96), kinds, seed=7, rho_range=(1.2, 1.8), upper_axis=1, gap=0.3, margin=0.3)
+    cfg = dict(lattice="D2Q9", n=(64, 96, 1), periodic=(0, 0, 0), tau=0.6, g=(0.0, -2e-4, 0.0))
+    w = np.random.default_rng(3).normal(size=(len(parts), 3))
+    out = []
+    for torch_memory in (False, True):
+        sim = lbm.Simulation(cfg, parts, storage="f32")
+        sim.forward_checkpointed(40, every, torch_memory=torch_memory)
+        out.append(sim.backward(w))
+        if torch_memory:
+            fb, bb = sim.grad_workspace_size(40, every)
+            assert sim._fwd_ws.numel() == fb and bb > 0
+    (r0, t0, g0), (r1, t1, g1) = out
+    assert np.array_equal(r0, r1) and t0 == t1 and g0 == g1
+    import ctypes as C
+
+    import torch
+
+    sim = lbm.Simulation(cfg, parts, storage="f32")
+    fb, bb = sim.grad_workspace_size(40, every)
+    small = torch.empty(fb - 1, dtype=torch.uint8, device="cuda")
+    rc = sim.lib.lbm_forward_checkpointed_ws(sim.ctx, 40, every, C.c_void_p(small.data_ptr()), fb - 1)
+    assert rc == lbm.LBM_ENOMEM
