@@ -359,6 +359,7 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
     c->sp.penalize_all = cfg->penalize_all != 0;
     c->sp.beta = cfg->rigid_beta;
     c->sp.stress = cfg->no_stress_penalty == 0;
+    if (!c->sp.stress) c->sp.alpha = 0.0; // S of eq. (17) is linear in alpha: off
     c->sp.alpha_tracks_tau = !(cfg->alpha > 0);
     double wall_tab[2][19];
     if (d == 2) wall_terms<D2Q9>(cfg, c->sp, wall_tab);
@@ -808,7 +809,7 @@ int lbm_set_params(lbm_ctx *c, const double *rho_s, double tau, const double *g)
     if (new_tau) {
         c->cfg.tau = c->sp.tau = tau;
         c->sp.omega = 1.0 / tau;
-        if (c->sp.alpha_tracks_tau) c->sp.alpha = 1.0 / tau;
+        if (c->sp.alpha_tracks_tau && c->sp.stress) c->sp.alpha = 1.0 / tau;
     }
     if (g) {
         for (int k = 0; k < 3; ++k) c->cfg.g[k] = c->rp.g[k] = k < c->d ? g[k] : 0.0;
@@ -979,7 +980,7 @@ int lbm_load_state(lbm_ctx *c, const void *buf)
     const StepParams sp0 = c->sp;
     c->sp.tau = h.tau;
     c->sp.omega = 1.0 / h.tau;
-    if (c->sp.alpha_tracks_tau) c->sp.alpha = 1.0 / h.tau;
+    if (c->sp.alpha_tracks_tau && c->sp.stress) c->sp.alpha = 1.0 / h.tau;
     for (int k = 0; k < 3; ++k) c->rp.g[k] = k < c->d ? h.g[k] : 0.0;
     c->rp.gmag = sqrt(c->rp.g[0] * c->rp.g[0] + c->rp.g[1] * c->rp.g[1] + c->rp.g[2] * c->rp.g[2]);
     int rc = check_particles(c, parts.data(), np);

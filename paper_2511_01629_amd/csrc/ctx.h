@@ -74,7 +74,8 @@ struct StepParams {
     int wall_axis;
     const double *wall_tab;
     // rigid-velocity forcing (an extension): strength beta (0: off), and
-    // whether the penalization source of eq. (17) acts (1: the paper's method)
+    // whether the penalization source of eq. (17) acts (1: the paper's
+    // method; 0: alpha is held at 0, which switches the source off)
     double beta;
     int stress;
 };

@@ -344,7 +344,7 @@ __device__ __forceinline__ void collide_node(T *f, uint16_t own, const T *__rest
         if (L::cy[q] * L::cz[q] > 0) Pyz += fneq[q];
         if (L::cy[q] * L::cz[q] < 0) Pyz -= fneq[q];
     }
-    const T al = pen && sp.stress ? (T)sp.alpha : T(0);
+    const T al = pen ? (T)sp.alpha : T(0);
     const T trace3 = (Pxx + Pyy + Pzz) * T(1.0 / 3.0);
     const T gpre = T(1) - T(0.5) * om;
     const T ua = L::D == 3 ? ux * ax + uy * ay + uz * az : ux * ax + uy * ay;
