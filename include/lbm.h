@@ -106,6 +106,11 @@ typedef struct {
                                nodes (and the separate sums kernel) every step.           */
     int32_t no_stress_penalty; /* 1: leave out the penalization source of eq. (17) (to compare
                                the forcing with the paper's stress penalty); 0: the paper   */
+    double max_radius;      /* > 0: the largest bounding radius any lbm_set_particles will
+                               use; the workspace then also holds the per-particle
+                               momentum-sum slot tables of the K = 1 step (so a caller's
+                               workspace owns them).  0, or a larger body later: the
+                               library allocates those tables at lbm_set_particles.       */
 } lbm_config;
 
 typedef struct {

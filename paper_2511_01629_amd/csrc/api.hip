@@ -33,8 +33,43 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 int storage_bytes(int s) { return s == LBM_F64 ? 8 : s == LBM_F32 ? 4 : 2; }
 
+// Sizes of the slot tables of the fused-sums step (K = 1): per-particle
+// tables keyed by the wrapped row and the wavefront index (slot_of).  A scan
+// box spans at most ext = ceil(2a) + 7 nodes per axis; the key sizes are
+// powers of two at least that many rows and wavefronts, and on a periodic
+// axis must divide the period (or cover it), so that no two rows or
+// wavefronts of a box share a slot; on a periodic x axis a box must also stay
+// 63 nodes short of the period, so that a wavefront never holds nodes of two
+// images of one box.  Returns false where the sizes cannot be met (the
+// momentum sums then run as a kernel of their own).
+struct SlotSizes {
+    int Mx, My, Mz;
+    int64_t stride;
+    size_t bytes; // for `cap` particles
+};
+bool slot_sizes(const int n[3], const int per[3], int d, int ext, int cap, SlotSizes &z)
+{
+    auto pow2 = [](int v) {
+        int q = 1;
+        while (q < v) q <<= 1;
+        return q;
+    };
+    const int wn = (n[0] + 63) / 64;
+    const int kwn = std::min(wn, (ext + 62) / 64 + 1 + (per[0] && n[0] % 64 ? 1 : 0));
+    z.Mx = pow2(kwn);
+    z.My = pow2(ext);
+    z.Mz = d == 3 ? pow2(ext) : 1;
+    auto axis_ok = [&](int p, int len, int M) { return !p || (ext <= len && (len % M == 0 || M >= len)); };
+    bool ok = axis_ok(per[1], n[1], z.My) && (d == 2 || axis_ok(per[2], n[2], z.Mz));
+    ok = ok && (!per[0] || (ext + 63 <= n[0] && (wn % z.Mx == 0 || z.Mx >= wn)));
+    z.stride = (int64_t)z.Mx * z.My * z.Mz;
+    z.bytes = (size_t)cap * (size_t)z.stride * slot_width(d) * sizeof(double);
+    const bool coords = n[0] < (1 << 21) && n[1] < (1 << 21) && n[2] < (1 << 21); // packed first nodes
+    return ok && coords && z.stride <= 65536 && z.bytes <= ((size_t)1 << 30);
+}
+
 struct Layout {
-    size_t f0, f1, owner, usol, staging, flags, wall, pd, pf, pi, total;
+    size_t f0, f1, owner, usol, staging, flags, wall, pd, pf, pi, slots, slots_bytes, total;
 };
 
 Layout layout_for(const lbm_config *cfg, int Q, int d, int64_t N)
@@ -63,6 +98,19 @@ Layout layout_for(const lbm_config *cfg, int Q, int d, int64_t N)
     off += align_up((size_t)cap * 3 * sizeof(float));
     L.pi = off;
     off += align_up((size_t)cap * 8 * sizeof(int32_t));
+    // the slot tables for bodies up to max_radius, when it is given (else the
+    // library allocates them at lbm_set_particles)
+    L.slots = off;
+    L.slots_bytes = 0;
+    if (cfg->max_radius > 0 && cfg->K == 1 && !(cfg->rigid_beta > 0)) {
+        const int n[3] = {cfg->n[0], cfg->n[1], d == 3 ? cfg->n[2] : 1};
+        const int per[3] = {cfg->periodic[0] != 0, cfg->periodic[1] != 0, d == 3 && cfg->periodic[2] != 0};
+        SlotSizes z;
+        if (slot_sizes(n, per, d, (int)ceil(2.0 * cfg->max_radius) + 7, cap, z)) {
+            L.slots_bytes = align_up(z.bytes);
+            off += L.slots_bytes;
+        }
+    }
     L.total = off;
     return L;
 }
@@ -103,6 +151,7 @@ int validate_cfg(const lbm_config *cfg, std::string &why, int &Q, int &d, int64_
     if (!(cfg->rho_f > 0)) return why = "rho_f must be positive", LBM_EINVAL;
     if (cfg->eps_p <= 0 || cfg->eps_w <= 0 || cfg->delta <= 0) return why = "eps_p, eps_w, delta must be positive", LBM_EINVAL;
     if (!(cfg->rigid_beta >= 0.0 && cfg->rigid_beta <= 1.0)) return why = "rigid_beta must lie in [0, 1]", LBM_EINVAL;
+    if (!(cfg->max_radius >= 0.0 && cfg->max_radius < 1e6)) return why = "max_radius must be >= 0 and finite", LBM_EINVAL;
     // moving walls: one axis (y, or z in 3D), tangential, every other axis periodic
     int wall_axis = 0;
     for (int k = 0; k < 3; ++k)
@@ -221,6 +270,8 @@ void carve(lbm_ctx *c, const Layout &L)
     c->P.N = pi + cap;
     c->P.lo = pi + 2 * cap;
     c->P.hi = pi + 5 * cap;
+    c->ws_slots = L.slots_bytes ? (double *)(base + L.slots) : nullptr;
+    c->ws_slots_bytes = L.slots_bytes;
 }
 
 } // namespace
@@ -468,7 +519,7 @@ int lbm_destroy(lbm_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     if (c->own_mem) (void)hipFree(c->ws);
     if (c->rec_dev) (void)hipFree(c->rec_dev);
-    if (c->slots) (void)hipFree(c->slots);
+    if (c->slots && c->slots != c->ws_slots) (void)hipFree(c->slots);
     if (c->slab_mem) (void)hipFree(c->slab_mem);
     free_grad(c);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
@@ -628,54 +679,40 @@ int install_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
     c->host_parts.assign(p, p + n);
     int rc = upload_constants(c); // also waits for the copies above
     if (rc) return rc;
-    // fused-sums step (K = 1): per-particle slot tables keyed by the wrapped
-    // row and the wavefront index (slot_of).  A scan box spans at most
-    // ceil(2a) + 7 nodes per axis; the key sizes are powers of two at least
-    // that many rows and wavefronts, and on a periodic axis must divide the
-    // period (or cover it), so that no two rows or wavefronts of a box share a
-    // slot; on a periodic x axis a box must also stay 63 nodes short of the
-    // period, so that a wavefront never holds nodes of two images of one box.
-    // Otherwise the momentum sums run as a kernel of their own.
+    // fused-sums step (K = 1): the slot tables (slot_sizes), in the
+    // workspace when it holds a large enough region, else allocated here
     c->fused = 0;
     if (c->rp.K == 1 && n > 0 && !(c->sp.beta > 0)) { // the forcing pass needs the indicator after the sums
         const Geom &g = c->geo;
         int ext = 0;
         for (int i = 0; i < n; ++i) ext = std::max(ext, (int)ceil(2.0 * p[i].a) + 7);
-        auto pow2 = [](int v) {
-            int q = 1;
-            while (q < v) q <<= 1;
-            return q;
-        };
         auto lg = [](int v) {
             int k = 0;
             while ((1 << k) < v) ++k;
             return k;
         };
-        const int wn = (g.nx + 63) / 64;
-        const int kwn = std::min(wn, (ext + 62) / 64 + 1 + (g.per_x && g.nx % 64 ? 1 : 0));
-        const int Mx = pow2(kwn), My = pow2(ext), Mz = d == 3 ? pow2(ext) : 1;
-        auto axis_ok = [&](int per, int len, int M) { return !per || (ext <= len && (len % M == 0 || M >= len)); };
-        bool ok = axis_ok(g.per_y, g.ny, My) && (d == 2 || axis_ok(g.per_z, g.nz, Mz));
-        ok = ok && (!g.per_x || (ext + 63 <= g.nx && (wn % Mx == 0 || Mx >= wn)));
-        const int64_t stride = (int64_t)Mx * My * Mz;
-        const size_t need = (size_t)cap * (size_t)stride * slot_width(d) * sizeof(double);
-        const bool coords = g.nx < (1 << 21) && g.ny < (1 << 21) && g.nz < (1 << 21); // packed first nodes
-        if (ok && coords && stride <= 65536 && need <= ((size_t)1 << 30)) {
-            if (need > c->slots_bytes) {
-                if (c->slots) HIPCHK(c, hipFree(c->slots));
+        const int nn[3] = {g.nx, g.ny, g.nz}, per[3] = {g.per_x, g.per_y, g.per_z};
+        SlotSizes z;
+        if (slot_sizes(nn, per, d, ext, cap, z)) {
+            if (z.bytes <= c->ws_slots_bytes) {
+                if (c->slots && c->slots != c->ws_slots) HIPCHK(c, hipFree(c->slots));
+                c->slots = c->ws_slots;
+                c->slots_bytes = c->ws_slots_bytes;
+            } else if (c->slots == c->ws_slots || z.bytes > c->slots_bytes) {
+                if (c->slots && c->slots != c->ws_slots) HIPCHK(c, hipFree(c->slots));
                 c->slots = nullptr;
                 c->slots_bytes = 0;
-                HIPCHK(c, hipMalloc((void **)&c->slots, need));
-                c->slots_bytes = need;
+                HIPCHK(c, hipMalloc((void **)&c->slots, z.bytes));
+                c->slots_bytes = z.bytes;
             }
             // NaN stamps: no slot counts until a step writes it
             HIPCHK(c, hipMemsetAsync(c->slots, 0xFF, c->slots_bytes, c->stream));
-            c->slot_stride = (int)stride;
-            c->slot_mx = Mx - 1;
-            c->slot_my = My - 1;
-            c->slot_mz = Mz - 1;
-            c->slot_sy = lg(Mx);
-            c->slot_sz = lg(Mx) + lg(My);
+            c->slot_stride = (int)z.stride;
+            c->slot_mx = z.Mx - 1;
+            c->slot_my = z.My - 1;
+            c->slot_mz = z.Mz - 1;
+            c->slot_sy = lg(z.Mx);
+            c->slot_sz = lg(z.Mx) + lg(z.My);
             c->fused = 1;
         }
     }

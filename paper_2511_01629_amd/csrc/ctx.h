@@ -133,8 +133,10 @@ struct lbm_ctx {
     lbm::PartDev P;
     int np, cap;
     // fused-sums step (K = 1): slot buffer (library-owned), its layout, the stamp counter
-    double *slots;
+    double *slots;        // the slot tables in use: ws_slots or a library allocation
     size_t slots_bytes;
+    double *ws_slots;     // the workspace's slot region (lbm_config.max_radius), or NULL
+    size_t ws_slots_bytes;
     int slot_stride, slot_mx, slot_my, slot_mz, slot_sy, slot_sz, fused;
     int64_t epoch;
     int64_t step;

@@ -49,7 +49,7 @@ class Config(C.Structure):
         ("fluid_accel", C.c_double * 3), ("penalize_all", C.c_int32), ("device", C.c_int32),
         ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
         ("max_particles", C.c_int32), ("wall_velocity", C.c_double * 18), ("check_every", C.c_int32),
-        ("rigid_beta", C.c_double), ("no_stress_penalty", C.c_int32),
+        ("rigid_beta", C.c_double), ("no_stress_penalty", C.c_int32), ("max_radius", C.c_double),
     ]
 
 
@@ -149,6 +149,7 @@ def make_config(cfg, storage=None, device=0, max_particles=0):
     c.check_every = int(cfg.get("check_every", 0))
     c.rigid_beta = float(cfg.get("rigid_beta", 0.0))
     c.no_stress_penalty = int(bool(cfg.get("no_stress_penalty", 0)))
+    c.max_radius = float(cfg.get("max_radius", 0.0))
     return c
 
 
@@ -190,6 +191,9 @@ class Simulation:
         self.shape = (n[2] if self.d == 3 else 1, n[1], n[0])
         self.N = int(np.prod(self.shape))
         cap = max_particles if max_particles is not None else max(len(particles), 1)
+        if "max_radius" not in cfg and len(particles):
+            # the workspace (a torch tensor) then also holds the momentum-sum slot tables
+            cfg = dict(cfg, max_radius=max(float(p["a"]) for p in particles))
         self._cfg = make_config(cfg, storage, device, cap)
         size = C.c_size_t()
         self._check(self.lib.lbm_workspace_size(C.byref(self._cfg), C.byref(size)), None)

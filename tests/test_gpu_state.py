@@ -135,6 +135,18 @@ def test_nan_in_loaded_state_stops_lbm_step(storage):
     # the sentinel is sticky until the next load
     with pytest.raises(lbm.LbmError):
         a.sync()
+    # stepping one step per call polls at the same absolute steps (and a
+    # call reads a poll that has already completed without waiting, so it
+    # may stop sooner than one long call)
+    c = lbm.Simulation(cfg, parts, storage=storage)
+    c.load_state(blob)
+    calls = 0
+    with pytest.raises(lbm.LbmError) as e:
+        for _ in range(1000):
+            c.step(1)
+            calls += 1
+    assert e.value.code == lbm.LBM_EUNSTABLE and 5 < c.step_index <= 5 + 2 * k + k
+    assert calls == c.step_index - 5 - 1  # the call that reported it ran its step
     # with polling off the same run is only reported by lbm_sync
     b = lbm.Simulation(dict(cfg, check_every=-1), parts, storage=storage)
     b.load_state(blob)
@@ -237,3 +249,36 @@ def test_fields_device(kind):
     uh, ph, oh = sim.fields()
     assert np.array_equal(ud.cpu().numpy(), uh) and np.array_equal(pd.cpu().numpy(), ph)
     assert np.array_equal(od.cpu().numpy(), oh)
+
+
+def test_slot_tables_in_workspace():
+    """lbm_config.max_radius puts the momentum-sum slot tables in the caller's
+    workspace: the same bits as tables the library allocates, through a later
+    set with a body larger than max_radius (the library allocates then) and
+    back to small bodies (the workspace again), and in a differentiated run."""
+    banner("slot tables in the workspace")
+    cfg, parts = _contacts()
+    lib = lbm.Simulation(dict(cfg, max_radius=0.0), parts, storage="f32", max_particles=9)
+    ws = lbm.Simulation(cfg, parts, storage="f32", max_particles=9)  # max_radius: the largest body
+    assert ws.workspace.numel() > lib.workspace.numel()
+    for s in (lib, ws):
+        s.step(40)
+    _same(lib, ws)
+    big = [dict(shape="disk", rho_s=1.4, a=9.0, x=(20.0, 22.0, 0.0)),
+           dict(shape="disk", rho_s=1.3, a=5.0, x=(45.0, 60.0, 0.0))]
+    for s in (lib, ws):
+        s.set_particles(big)
+        s.step(30)
+    _same(lib, ws)
+    for s in (lib, ws):
+        s.set_particles(parts)
+        s.step(30)
+    _same(lib, ws)
+    seed = np.zeros((len(parts), 3))
+    seed[:, 1] = 1.0 / len(parts)
+    grads = []
+    for s in (lib, ws):
+        s.set_particles(parts)  # a differentiated run starts from a set
+        s.forward_checkpointed(20, 5)
+        grads.append(s.backward(seed))
+    assert np.array_equal(grads[0][0], grads[1][0]) and grads[0][1:] == grads[1][1:]
