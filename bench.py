@@ -122,7 +122,7 @@ def run_mode(name, storage, steps, warmup, profile=True):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     sim.sync()  # raises if the run went unstable or a body left the box
-    out = dict(workload=name, storage=storage, nodes=N, particles=len(parts), steps=steps, ms=ms,
+    out = dict(workload=name, storage=storage, nodes=N, Q=Q, particles=len(parts), steps=steps, ms=ms,
                ms_per_step=ms / steps, mlups=N * steps / (ms * 1e-3) / 1e6)
     if profile:
         sim.profile(True)
@@ -140,7 +140,36 @@ def run_mode(name, storage, steps, warmup, profile=True):
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    if profile:
+        # the bandwidth a plain copy reaches with the same access pattern: Q arrays of
+        # N elements read and written together, 16-byte lanes
+        out["pattern_ceiling_gbs"] = pattern_ceiling(Q, STORAGE_BYTES[storage] * N)
+        out["kernel_frac_of_pattern"] = out["kernel_gbs"] / out["pattern_ceiling_gbs"]
     return out
+
+
+def pattern_ceiling(narrays, bytes_per_array, reps=20):
+    """GB/s of lbm_copy_arrays over narrays arrays of bytes_per_array bytes."""
+    import torch
+
+    from paper_2511_01629_amd import lbm
+
+    per = (bytes_per_array + 15) // 16 * 16
+    a = torch.empty(narrays * per, dtype=torch.uint8, device="cuda")
+    b = torch.empty(narrays * per, dtype=torch.uint8, device="cuda")
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        lbm.copy_arrays(b.data_ptr(), a.data_ptr(), narrays, per, st.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        lbm.copy_arrays(b.data_ptr(), a.data_ptr(), narrays, per, st.cuda_stream)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * narrays * per / (ms * 1e-3) / 1e9
 
 
 def run_adjoint(name, storage, every, max_steps=None):
@@ -298,7 +327,8 @@ def main():
         return
     log(f"headline {args.workload} {args.storage}: warmup {args.warmup}, steps {args.steps}")
     head = run_mode(args.workload, args.storage, args.steps, args.warmup)
-    log(f"  {head['mlups']:.0f} MLUPS, fused kernel {head['kernel_gbs']:.0f} GB/s ({head['kernel_frac']:.3f})")
+    log(f"  {head['mlups']:.0f} MLUPS, fused kernel {head['kernel_gbs']:.0f} GB/s ({head['kernel_frac']:.3f}), "
+        f"{head['Q']}-array copy of the same bytes {head['pattern_ceiling_gbs']:.0f} GB/s")
 
     modes = {}
     if not args.no_modes:
@@ -307,9 +337,11 @@ def main():
             log(f"mode {name} {storage}")
             r = run_mode(name, storage, steps, max(10, args.warmup // 4))
             modes[f"{name}/{storage}"] = {k: r[k] for k in ("mlups", "ms_per_step", "kernel_gbs", "kernel_frac",
-                                                             "kernel_avg_us", "breakdown_us")}
+                                                             "kernel_avg_us", "breakdown_us", "pattern_ceiling_gbs",
+                                                             "kernel_frac_of_pattern")}
             modes[f"{name}/{storage}"]["step_frac"] = r["step_gbs_alg"] / HBM_PEAK_GBS
-            log(f"  {r['mlups']:.0f} MLUPS, fused kernel {r['kernel_gbs']:.0f} GB/s")
+            log(f"  {r['mlups']:.0f} MLUPS, fused kernel {r['kernel_gbs']:.0f} GB/s, "
+                f"{r['Q']}-array copy of the same bytes {r['pattern_ceiling_gbs']:.0f} GB/s")
     if not args.no_modes:
         log("forward + adjoint adjoint_512x1024 f32 (5000 steps; checkpoint every 100, and every step kept)")
         for every in (100, 1):
@@ -357,7 +389,10 @@ def main():
                      "kernel": "k_stream_collide", "alg_bytes_per_launch": head["kernel_alg_bytes"],
                      "avg_launch_us": head["kernel_avg_us"],
                      # the whole step (lattice update + particle side) against the same peak
-                     "step_achieved": head["step_gbs_alg"], "step_frac": head["step_gbs_alg"] / HBM_PEAK_GBS},
+                     "step_achieved": head["step_gbs_alg"], "step_frac": head["step_gbs_alg"] / HBM_PEAK_GBS,
+                     # a plain copy of the same Q arrays (Q streams read and Q written together)
+                     "pattern_ceiling": head["pattern_ceiling_gbs"],
+                     "frac_of_pattern": head["kernel_frac_of_pattern"]},
         "step_breakdown_us": head["breakdown_us"],
         "copy_ceiling_gbs": ceiling,
         "modes": modes,

@@ -346,6 +346,15 @@ int lbm_profile_read(lbm_ctx *ctx, double *host_ms, int64_t *host_count, int32_t
  * reference of the measurements. */
 int lbm_copy(void *dst, const void *src, size_t bytes, void *stream);
 
+/* The same copy over `narrays` arrays of `bytes_per_array` bytes each, laid
+ * out one after another at src and dst (array a at a * bytes_per_array), in
+ * one kernel whose threads each move one 16-byte word of every array, loads
+ * first: narrays streams read and narrays written together, the access
+ * pattern of a lattice update over Q population arrays.  narrays in 1..32
+ * (EINVAL otherwise); pointers and bytes_per_array as for lbm_copy.  Used as
+ * the bandwidth reference of that pattern in the measurements. */
+int lbm_copy_arrays(void *dst, const void *src, int32_t narrays, size_t bytes_per_array, void *stream);
+
 /* Number of completed steps. */
 int lbm_get_step(const lbm_ctx *ctx, int64_t *step);
 

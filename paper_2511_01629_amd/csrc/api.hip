@@ -1229,6 +1229,15 @@ int lbm_copy(void *dst, const void *src, size_t bytes, void *stream)
     return launch_copy(dst, src, bytes, (hipStream_t)stream) == hipSuccess ? LBM_OK : LBM_EDEVICE;
 }
 
+int lbm_copy_arrays(void *dst, const void *src, int32_t narrays, size_t bytes_per_array, void *stream)
+{
+    if (narrays < 1 || narrays > 32) return LBM_EINVAL;
+    if ((!dst || !src) && bytes_per_array) return LBM_EINVAL;
+    if (((uintptr_t)dst | (uintptr_t)src | bytes_per_array) % 16) return LBM_EINVAL;
+    return launch_copy_arrays(dst, src, narrays, bytes_per_array, (hipStream_t)stream) == hipSuccess ? LBM_OK
+                                                                                                    : LBM_EDEVICE;
+}
+
 int lbm_get_step(const lbm_ctx *c, int64_t *step)
 {
     if (!c || !step) return LBM_EINVAL;

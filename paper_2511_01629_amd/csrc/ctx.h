@@ -200,6 +200,7 @@ hipError_t launch_rigid_fused(lbm_ctx *c, double *rec); // Algorithm 1 + raster 
 SlotParams slot_params(lbm_ctx *c, bool on);
 hipError_t launch_owner_to_int(lbm_ctx *c, int32_t *out);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+hipError_t launch_copy_arrays(void *dst, const void *src, int na, size_t bytes_per_array, hipStream_t s);
 
 // adjoint.hip
 hipError_t launch_adj_lattice(lbm_ctx *c, const void *fprev, const uint16_t *owner, const double *uext_d,

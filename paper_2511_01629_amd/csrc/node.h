@@ -190,6 +190,24 @@ __device__ __forceinline__ T from_reg(R r)
     else return r;
 }
 
+// base + i elements, with base made opaque to the compiler as a wave-uniform
+// value and the element offset taken as a 32-bit byte offset (i * sizeof(P)
+// < 2^32 for every lattice the library accepts): the access then takes the
+// scalar-base form of the global instructions, base in scalar registers plus
+// one 32-bit lane offset, instead of a 64-bit address add per access.
+template <class P>
+__device__ __forceinline__ P *uniform_at(P *base, int i)
+{
+    const uint64_t v = (uint64_t)base;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    // arithmetic on a global (address space 1) pointer, so that the access
+    // stays a global one after the integer round trip
+    typedef __attribute__((address_space(1))) char gchar;
+    gchar *b = (gchar *)(((uint64_t)hi << 32) | lo);
+    return (P *)(b + (uint32_t)i * (uint32_t)sizeof(P));
+}
+
 // Loads in both branches and the conversion after them, so that no wait for
 // the loads is placed at the branch join.
 template <class L, class S, class T>
@@ -200,7 +218,7 @@ __device__ __forceinline__ void pull_row(const typename S::raw *__restrict__ fin
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) {
             const typename S::raw *src = fin + (q * rp.N + rp.rb[L::cy[q] + 1][L::cz[q] + 1] - L::cx[q]);
-            r[q] = ld_reg<S>(src + (unsigned)rp.x);
+            r[q] = ld_reg<S>(uniform_at(src, rp.x));
         }
     } else {
 #pragma unroll

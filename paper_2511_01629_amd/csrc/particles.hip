@@ -843,7 +843,42 @@ __global__ __launch_bounds__(256) void k_copy(u32x4 *__restrict__ dst, const u32
     if (i < n16) dst[i] = src[i];
 }
 
+// The same copy over NA arrays at once (array a at a * n16 words of src and
+// dst): each thread moves word i of every array, all loads before the first
+// store, so that NA streams are read and NA written together, as the lattice
+// update reads and writes its Q population arrays.  NA = 0: a runtime count
+// na, one array after another per thread.
+template <int NA>
+__global__ __launch_bounds__(256) void k_copy_arrays(u32x4 *__restrict__ dst, const u32x4 *__restrict__ src,
+                                                     size_t n16, int na)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n16) return;
+    if constexpr (NA > 0) {
+        u32x4 v[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) v[a] = __builtin_nontemporal_load(src + (size_t)a * n16 + i);
+#pragma unroll
+        for (int a = 0; a < NA; ++a) __builtin_nontemporal_store(v[a], dst + (size_t)a * n16 + i);
+    } else {
+        for (int a = 0; a < na; ++a) dst[(size_t)a * n16 + i] = src[(size_t)a * n16 + i];
+    }
+}
+
 // ----------------------------------------------------------------- launchers
+hipError_t launch_copy_arrays(void *dst, const void *src, int na, size_t bytes_per_array, hipStream_t s)
+{
+    const size_t n16 = bytes_per_array / 16;
+    if (n16 == 0 || na == 0) return hipSuccess;
+    const size_t blocks = (n16 + 255) / 256;
+    if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks), block(256);
+    if (na == 9) hipLaunchKernelGGL(k_copy_arrays<9>, grid, block, 0, s, (u32x4 *)dst, (const u32x4 *)src, n16, na);
+    else if (na == 19) hipLaunchKernelGGL(k_copy_arrays<19>, grid, block, 0, s, (u32x4 *)dst, (const u32x4 *)src, n16, na);
+    else hipLaunchKernelGGL(k_copy_arrays<0>, grid, block, 0, s, (u32x4 *)dst, (const u32x4 *)src, n16, na);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s)
 {
     const size_t n16 = bytes / 16;

@@ -24,7 +24,7 @@ CODES = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "EUNSTABLE
 
 EXPORTS = ["lbm_workspace_size", "lbm_create", "lbm_destroy", "lbm_set_particles", "lbm_step", "lbm_step_record",
            "lbm_sync", "lbm_get_fields", "lbm_get_populations", "lbm_set_populations", "lbm_get_particles",
-           "lbm_get_step", "lbm_last_error", "lbm_profile", "lbm_profile_read", "lbm_copy",
+           "lbm_get_step", "lbm_last_error", "lbm_profile", "lbm_profile_read", "lbm_copy", "lbm_copy_arrays",
            "lbm_forward_checkpointed", "lbm_backward", "lbm_get_fields_device", "lbm_set_params",
            "lbm_state_size", "lbm_save_state", "lbm_load_state", "lbm_step_record_noalloc",
            "lbm_step_slabs", "lbm_grad_workspace_size", "lbm_forward_checkpointed_ws", "lbm_backward_ws"]
@@ -95,6 +95,7 @@ def load():
     lib.lbm_profile.argtypes = [P, I32]
     lib.lbm_profile_read.argtypes = [P, dp, C.POINTER(C.c_int64), I32]
     lib.lbm_copy.argtypes = [P, P, C.c_size_t, P]
+    lib.lbm_copy_arrays.argtypes = [P, P, I32, C.c_size_t, P]
     lib.lbm_forward_checkpointed.argtypes = [P, I64, I32]
     lib.lbm_backward.argtypes = [P, dp, dp, dp, dp]
     lib.lbm_get_fields_device.argtypes = [P, P, P, P]
@@ -170,6 +171,15 @@ def copy(dst_ptr, src_ptr, nbytes, stream_handle):
     rc = load().lbm_copy(C.c_void_p(dst_ptr), C.c_void_p(src_ptr), int(nbytes), C.c_void_p(stream_handle))
     if rc != LBM_OK:
         raise LbmError(rc, "lbm_copy failed")
+
+
+def copy_arrays(dst_ptr, src_ptr, narrays, bytes_per_array, stream_handle):
+    """Copy of narrays consecutive arrays in one kernel (measurement aid: the
+    lattice update's pattern of Q concurrent streams)."""
+    rc = load().lbm_copy_arrays(C.c_void_p(dst_ptr), C.c_void_p(src_ptr), int(narrays), int(bytes_per_array),
+                                C.c_void_p(stream_handle))
+    if rc != LBM_OK:
+        raise LbmError(rc, "lbm_copy_arrays failed")
 
 
 class Simulation:

@@ -119,6 +119,13 @@ def test_null_arguments():
     assert lib.lbm_copy(C.c_void_p(0x1008), C.c_void_p(0x2000), 16, None) == lbm.LBM_EINVAL
     assert lib.lbm_copy(C.c_void_p(0x1000), C.c_void_p(0x2000), 24, None) == lbm.LBM_EINVAL
     assert lib.lbm_copy(None, None, 0, None) == lbm.LBM_OK
+    # lbm_copy_arrays: the same, and an array count outside 1..32
+    assert lib.lbm_copy_arrays(None, None, 9, 16, None) == lbm.LBM_EINVAL
+    assert lib.lbm_copy_arrays(C.c_void_p(0x1000), C.c_void_p(0x2004), 9, 16, None) == lbm.LBM_EINVAL
+    assert lib.lbm_copy_arrays(C.c_void_p(0x1000), C.c_void_p(0x2000), 9, 40, None) == lbm.LBM_EINVAL
+    assert lib.lbm_copy_arrays(C.c_void_p(0x1000), C.c_void_p(0x2000), 0, 16, None) == lbm.LBM_EINVAL
+    assert lib.lbm_copy_arrays(C.c_void_p(0x1000), C.c_void_p(0x2000), 33, 16, None) == lbm.LBM_EINVAL
+    assert lib.lbm_copy_arrays(None, None, 9, 0, None) == lbm.LBM_OK
     # a rejected configuration leaves its reason for lbm_last_error(NULL)
     bad = lbm.make_config(_base(), storage="f32", max_particles=8)
     bad.tau = 0.4

@@ -35,3 +35,22 @@ def test_copy_rejects_partial_words():
     with pytest.raises(lbm.LbmError) as e:
         lbm.copy(b.data_ptr(), a.data_ptr(), 40, torch.cuda.current_stream().cuda_stream)
     assert e.value.code == lbm.LBM_EINVAL
+
+
+@pytest.mark.parametrize("narrays,words", [(9, 256 * 3 + 5), (19, 300), (3, 257), (1, 1)])
+def test_copy_arrays_exact(narrays, words):
+    """The multi-array copy (the Q-stream bandwidth reference) moves every
+    array exactly and nothing beyond the last one."""
+    banner(f"copy_arrays {narrays} x {words} words")
+    import torch
+
+    per = 16 * words
+    nbytes = narrays * per
+    g = torch.Generator().manual_seed(narrays * 1000 + words)
+    src = torch.randint(0, 256, (nbytes + 64,), dtype=torch.uint8, generator=g).cuda()
+    dst = torch.zeros(nbytes + 64, dtype=torch.uint8, device="cuda")
+    st = torch.cuda.current_stream()
+    lbm.copy_arrays(dst.data_ptr(), src.data_ptr(), narrays, per, st.cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:nbytes], src[:nbytes])
+    assert not dst[nbytes:].any()
