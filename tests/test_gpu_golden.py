@@ -66,9 +66,10 @@ def test_disk_settling_20000_steps(storage):
     assert eX <= bX and eU <= bU and eu <= bu
 
 
-# max over the records of max_i |X - X_oracle| (l.u.) and of max_i |U - U_oracle| / max |U_oracle|:
-# twice the measured maxima (FP32 4.82e-4, FP16 3.56e-3, BF16 8.01e-3 l.u. at 4000 steps)
-SED_BOUNDS = {"f32": (9.6e-4, 1.0), "f16": (7.1e-3, 1.0), "bf16": (1.6e-2, 1.0)}
+# max over the records of max_i |X - X_oracle| (l.u.) and of max_i |U - U_oracle| / max |U_oracle|
+# over the full 10000 steps: twice the maxima measured on MI355X (FP32 9.14e-4 l.u. and 8.60e-4;
+# FP16 1.36e-2 and 4.45e-3; BF16 8.55e-2 and 4.03e-2; no body reaches 0.1 R = 0.8 l.u.)
+SED_BOUNDS = {"f32": (1.9e-3, 1.8e-3), "f16": (2.8e-2, 9.0e-3), "bf16": (0.18, 8.1e-2)}
 
 
 def _error_growth(name, storage, gold, d):
