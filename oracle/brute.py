@@ -94,26 +94,37 @@ def step(state):
         a, b = pt["a"], pt["b"]
         return (b * b) * (xi * xi) + (a * a) * (eta * eta) <= (a * a) * (b * b)
 
-    owner = {}
+    # the fractional indicator (an extension, disks and spheres): the band
+    # |r| < R + 1/2 with chi = min(1, R + 1/2 - |r|), the first particle whose
+    # band holds the node owns it; chi = 1 on the nodes of the binary indicator
+    frac = state.get("fractional", False)
+    owner, chi = {}, {}
     for nd in nodes:
-        owner[nd] = -1
+        owner[nd], chi[nd] = -1, 0.0
         for i, pt in enumerate(parts):
-            if inside(pt, disp(nd, pt["X"])):
-                owner[nd] = i
+            r = disp(nd, pt["X"])
+            if frac:
+                r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2]
+                if r2 < (pt["a"] + 0.5) * (pt["a"] + 0.5):
+                    owner[nd], chi[nd] = i, min(1.0, pt["a"] + 0.5 - math.sqrt(r2))
+                    break
+            elif inside(pt, r):
+                owner[nd], chi[nd] = i, 1.0
                 break
 
     # S2/S3: acceleration and macroscopic fields (eq. 15a-b)
-    def accel(i):
+    def accel(nd):
+        i = owner[nd]
         if i < 0:
             return [0.0, 0.0, 0.0]
         pt = parts[i]
         b = 1.0 - state["rho_f"] / pt["rho_s"]
-        return [b * state["g"][k] + pt["A"][k] if k < d else 0.0 for k in range(3)]
+        return [chi[nd] * (b * state["g"][k] + pt["A"][k]) if k < d else 0.0 for k in range(3)]
 
     f = state["f"]
     U, P = {}, {}
     for nd in nodes:
-        acc = accel(owner[nd])
+        acc = accel(nd)
         fv = f[nd]
         u = [sum(fv[a] * c[a][k] for a in range(Q)) + acc[k] / 2 for k in range(3)]
         p = (CS2 * sum(fv[1:]) - w[0] / 2 * dot(u, u)) / (1 - w[0])
@@ -123,13 +134,13 @@ def step(state):
     meas = []
     for i, pt in enumerate(parts):
         own = [nd for nd in nodes if owner[nd] == i]
-        N = len(own)
-        su = [sum(U[nd][k] for nd in own) for k in range(3)]
+        N = sum(chi[nd] for nd in own)  # the node count, or sum chi
+        su = [sum(chi[nd] * U[nd][k] for nd in own) for k in range(3)]
         Uv = [s / N for s in su]
         rs = [disp(nd, pt["X"]) for nd in own]
         if d == 2:
-            L = sum(r[0] * U[nd][1] - r[1] * U[nd][0] for r, nd in zip(rs, own))
-            I2 = sum(r[0] * r[0] + r[1] * r[1] for r in rs)
+            L = sum(chi[nd] * (r[0] * U[nd][1] - r[1] * U[nd][0]) for r, nd in zip(rs, own))
+            I2 = sum(chi[nd] * (r[0] * r[0] + r[1] * r[1]) for r, nd in zip(rs, own))
             W = [0.0, 0.0, L / I2]
         else:
             Lv = [0.0, 0.0, 0.0]
@@ -138,11 +149,11 @@ def step(state):
                 u = U[nd]
                 cr = [r[1] * u[2] - r[2] * u[1], r[2] * u[0] - r[0] * u[2], r[0] * u[1] - r[1] * u[0]]
                 for k in range(3):
-                    Lv[k] += cr[k]
+                    Lv[k] += chi[nd] * cr[k]
                 rr = dot(r, r)
                 for a in range(3):
                     for b in range(3):
-                        T[a][b] += (rr if a == b else 0.0) - r[a] * r[b]
+                        T[a][b] += chi[nd] * ((rr if a == b else 0.0) - r[a] * r[b])
             W = solve3(T, Lv)
         meas.append((N, Uv, W))
 
@@ -154,7 +165,7 @@ def step(state):
     post = {}
     for nd in nodes:
         i = owner[nd]
-        acc = accel(i)
+        acc = accel(nd)
         u, p, fv = U[nd], P[nd], f[nd]
         if i >= 0 and beta > 0:
             _, Ui, Wi = meas[i]
@@ -175,7 +186,7 @@ def step(state):
             S = 0.0
             if i >= 0 and stress:
                 PiCC = sum(Pi[r][s] * ca[r] * ca[s] for r in range(3) for s in range(3))
-                S = w[a] / (2 * CS2 ** 2) * alpha * (PiCC - CS2 * trPi)
+                S = w[a] / (2 * CS2 ** 2) * alpha * chi[nd] * (PiCC - CS2 * trPi)
             out.append(fv[a] - (fv[a] - fe[a]) / tau + F + S)
         post[nd] = out
 
@@ -289,7 +300,7 @@ def solve3(T, b):
 
 
 def initial_state(kind, n, periodic, tau, alpha, rho_f, g, u0, parts, eps_p=2.0, eps_w=1.0, delta=1.0, K=1,
-                  beta=0.0, no_stress_penalty=False):
+                  beta=0.0, no_stress_penalty=False, fractional=False):
     """f = f^eq(0, u0) everywhere; U^{-1} = U^0 from the initial indicator."""
     c, w = velocities(kind)
     u0 = list(u0) + [0.0] * (3 - len(u0))
@@ -298,7 +309,7 @@ def initial_state(kind, n, periodic, tau, alpha, rho_f, g, u0, parts, eps_p=2.0,
     nodes = [(x, y, z) for z in range(n[2]) for y in range(n[1]) for x in range(n[0])]
     st = dict(kind=kind, n=tuple(n), periodic=tuple(periodic), tau=tau, alpha=alpha if alpha > 0 else 1.0 / tau,
               rho_f=rho_f, g=g, eps_p=eps_p, eps_w=eps_w, delta=delta, K=K, beta=beta,
-              no_stress_penalty=no_stress_penalty,
+              no_stress_penalty=no_stress_penalty, fractional=fractional,
               f={nd: list(fe) for nd in nodes}, parts=[])
     for pt in parts:
         q = dict(pt)

@@ -41,6 +41,14 @@
  *    (form 0), or the printed form with the raw centre difference and
  *    C_i = (rho_s,i - rho_f)|g| (form 1).
  *  - theta^{n+1} = theta^n + (omega^n + omega^{n-1})/2 (2D).
+ *  - Fractional indicator (an extension for gradients in the positions,
+ *    disks and spheres only): chi_i(x) = min(1, R_i + 1/2 - |x - X_i|) on the
+ *    band |x - X_i| < R_i + 1/2 (decided on |r|^2 < (R + 1/2)^2 in FP64 from
+ *    real parts), the lowest id owning a node of two bands; every use of the
+ *    indicator is weighted by chi: a = chi ((1 - rho_f/rho_s) g + A), the
+ *    penalization strength chi alpha, and the sums N_i = sum chi,
+ *    U_i = sum chi u / N_i, omega from sum chi r x u and sum chi |r|^2 (the
+ *    tensor in 3D), M_i = rho_s N_i.  The binary indicator is its limit.
  *
  * Build:  gcc -O2 -std=gnu11 -ffp-contract=off -fopenmp -fPIC -shared
  *         [-DORACLE_COMPLEX] lbm_oracle.c -o liboracle[_cs].so -lm
@@ -212,6 +220,7 @@ typedef struct {
      * [0, 1], 0 = off; and a switch that leaves out the stress penalization */
     double rigid_beta;
     int no_stress_penalty;
+    int fractional; /* 1: the fractional indicator (disks and spheres) */
 } ora_cfg;
 
 typedef struct {
@@ -228,7 +237,8 @@ typedef struct {
     real U[3], W[3];         /* U^n, omega^n of the current step (valid after S4) */
     real Uprev[3], Wprev[3]; /* U^{n-1}, omega^{n-1} */
     real A[3];
-    int N;
+    int N;       /* owned nodes */
+    real Nw;     /* sum of the indicator over them: N, or sum chi (fractional) */
     real sum_r2; /* 2D: sum |r|^2 */
 } particle_t;
 
@@ -250,13 +260,15 @@ typedef struct {
     particle_t *p;
     real *f, *ft, *u, *pr;
     int *owner;
+    int fractional;
+    real *chi; /* fractional: the owner's chi at each node */
     long step;
     int perturbed;
     /* mask replay: rasterise from recorded centres/orientations */
     long rep_n0, rep_len;
     double *rep_X, *rep_theta;
-    /* pending complex-step seeds of the particle densities */
-    double *pend_drho;
+    /* pending complex-step seeds of the particle densities and centres */
+    double *pend_drho, *pend_dX;
     int pend_np;
 } ora_ctx;
 
@@ -305,7 +317,7 @@ static void rasterize(ora_ctx *c)
         particle_t *P = &c->p[i];
         double Xc[3] = {0, 0, 0}, th = RE(P->theta);
         long lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-        if (c->rep_X && c->step >= c->rep_n0 && c->step < c->rep_n0 + c->rep_len) {
+        if (!c->fractional && c->rep_X && c->step >= c->rep_n0 && c->step < c->rep_n0 + c->rep_len) {
             long s = c->step - c->rep_n0;
             for (int k = 0; k < 3; k++) Xc[k] = c->rep_X[(s * c->np + i) * 3 + k];
             th = c->rep_theta[s * c->np + i];
@@ -331,8 +343,23 @@ static void rasterize(ora_ctx *c)
                         if (k < d && c->periodic[k]) xw[k] = ((xu[k] % c->n[k]) + c->n[k]) % c->n[k];
                         if (k < d) dd[k] = (double)xu[k] - Xc[k];
                     }
-                    if (!inside_shape(P->shape, P->a, P->b, th, dd)) continue;
                     long id = node_index(c, (int)xw[0], (int)xw[1], (int)xw[2]);
+                    if (c->fractional) {
+                        /* the band |r| < R + 1/2, then chi = min(1, R + 1/2 - |r|) */
+                        const double Rh = P->a + 0.5;
+                        if (!(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2] < Rh * Rh)) continue;
+                        if (c->owner[id] >= 0) continue; /* ascending i: lowest id wins */
+                        real r2 = 0.0;
+                        for (int k = 0; k < d; k++) {
+                            real dk = (double)xu[k] - P->X[k];
+                            r2 += dk * dk;
+                        }
+                        real v = Rh - SQRT(r2);
+                        c->owner[id] = i;
+                        c->chi[id] = RE(v) >= 1.0 ? (real)1.0 : v;
+                        continue;
+                    }
+                    if (!inside_shape(P->shape, P->a, P->b, th, dd)) continue;
                     if (c->owner[id] < 0) c->owner[id] = i; /* ascending i: lowest id wins */
                 }
     }
@@ -341,8 +368,9 @@ static void rasterize(ora_ctx *c)
 /* S2: acceleration f/rho on a node (sec. 2.1 eq. 5-8 and sec. 2.4):
  * gravity minus the hydrostatic part, divided by rho = rho_s, plus the
  * collision acceleration A_i of Algorithm 1; zero on fluid nodes. */
-static void node_accel(const ora_ctx *c, int owner, real acc[3])
+static void node_accel(const ora_ctx *c, long id, real acc[3])
 {
+    const int owner = c->owner[id];
     acc[0] = acc[1] = acc[2] = 0.0;
     if (owner < 0) {
         for (int k = 0; k < c->L.d; k++) acc[k] = c->fluid_accel[k];
@@ -351,6 +379,8 @@ static void node_accel(const ora_ctx *c, int owner, real acc[3])
     const particle_t *P = &c->p[owner];
     real b = (c->gform == 0) ? (1.0 - c->rho_f / P->rho_s) : (P->rho_s / c->rho_f - 1.0);
     for (int k = 0; k < c->L.d; k++) acc[k] = b * c->g[k] + P->A[k];
+    if (c->fractional) /* the force density in proportion to the solid fraction */
+        for (int k = 0; k < c->L.d; k++) acc[k] = c->chi[id] * acc[k];
 }
 
 /* S3 over the whole lattice: u, p at every node from the current f. */
@@ -360,7 +390,7 @@ static void macros_all(ora_ctx *c)
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < c->N; i++) {
         real acc[3], u[3], p;
-        node_accel(c, c->owner[i], acc);
+        node_accel(c, i, acc);
         macro_node(&c->L, &c->f[i * Q], acc, u, &p);
         for (int k = 0; k < 3; k++) c->u[i * 3 + k] = u[k];
         c->pr[i] = p;
@@ -395,6 +425,7 @@ static void reduce_particles(ora_ctx *c)
     real *sl = calloc((size_t)np * 3, sizeof(real));
     real *si = calloc((size_t)np * 9, sizeof(real));
     real *sr2 = calloc((size_t)np, sizeof(real));
+    real *sw = calloc((size_t)np, sizeof(real));
     int *cnt = calloc((size_t)np, sizeof(int));
     for (int z = 0; z < c->n[2]; z++)
         for (int y = 0; y < c->n[1]; y++)
@@ -407,26 +438,30 @@ static void reduce_particles(ora_ctx *c)
                 real r[3] = {0, 0, 0};
                 for (int k = 0; k < d; k++) r[k] = (double)unwrap_coord(c, k, xs[k], RE(P->X[k])) - P->X[k];
                 const real *u = &c->u[id * 3];
+                const real wt = c->fractional ? c->chi[id] : (real)1.0; /* the node's weight */
                 cnt[o]++;
-                for (int k = 0; k < 3; k++) su[o * 3 + k] += u[k];
+                sw[o] += wt;
+                for (int k = 0; k < 3; k++) su[o * 3 + k] += wt * u[k];
                 if (d == 2) {
-                    sl[o * 3 + 2] += r[0] * u[1] - r[1] * u[0];
-                    sr2[o] += r[0] * r[0] + r[1] * r[1];
+                    sl[o * 3 + 2] += wt * (r[0] * u[1] - r[1] * u[0]);
+                    sr2[o] += wt * (r[0] * r[0] + r[1] * r[1]);
                 } else {
-                    sl[o * 3 + 0] += r[1] * u[2] - r[2] * u[1];
-                    sl[o * 3 + 1] += r[2] * u[0] - r[0] * u[2];
-                    sl[o * 3 + 2] += r[0] * u[1] - r[1] * u[0];
+                    sl[o * 3 + 0] += wt * (r[1] * u[2] - r[2] * u[1]);
+                    sl[o * 3 + 1] += wt * (r[2] * u[0] - r[0] * u[2]);
+                    sl[o * 3 + 2] += wt * (r[0] * u[1] - r[1] * u[0]);
                     real rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
                     for (int a = 0; a < 3; a++)
-                        for (int b = 0; b < 3; b++) si[o * 9 + a * 3 + b] += (a == b ? rr : 0.0) - r[a] * r[b];
+                        for (int b = 0; b < 3; b++)
+                            si[o * 9 + a * 3 + b] += wt * ((a == b ? rr : 0.0) - r[a] * r[b]);
                 }
             }
     for (int i = 0; i < np; i++) {
         particle_t *P = &c->p[i];
         P->N = cnt[i];
+        P->Nw = sw[i];
         for (int k = 0; k < 3; k++) P->U[k] = 0.0, P->W[k] = 0.0;
-        if (cnt[i] == 0) continue;
-        for (int k = 0; k < d; k++) P->U[k] = su[i * 3 + k] / (double)cnt[i];
+        if (cnt[i] == 0 || RE(sw[i]) == 0.0) continue;
+        for (int k = 0; k < d; k++) P->U[k] = su[i * 3 + k] / sw[i];
         if (d == 2) {
             P->sum_r2 = sr2[i];
             P->W[2] = sl[i * 3 + 2] / sr2[i];
@@ -441,6 +476,7 @@ static void reduce_particles(ora_ctx *c)
     free(sl);
     free(si);
     free(sr2);
+    free(sw);
     free(cnt);
 }
 
@@ -476,10 +512,12 @@ static void collide_stream(ora_ctx *c)
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < c->N; i++) {
         real acc[3], u[3], p;
-        node_accel(c, c->owner[i], acc);
+        node_accel(c, i, acc);
         if (c->owner[i] >= 0 && c->beta > 0.0) rigid_forcing(c, i, acc);
         int solid = (c->owner[i] >= 0 || c->penalize_all) && !c->no_stress_penalty;
-        collide_node(&c->L, c->tau, c->alpha, solid, &c->f[i * Q], acc, &c->ft[i * Q], u, &p);
+        /* fractional indicator: the penalization in proportion to the solid fraction */
+        real alpha = (c->fractional && c->owner[i] >= 0) ? c->chi[i] * c->alpha : c->alpha;
+        collide_node(&c->L, c->tau, alpha, solid, &c->f[i * Q], acc, &c->ft[i * Q], u, &p);
     }
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < c->N; i++) {
@@ -597,7 +635,7 @@ static void rigid_update(ora_ctx *c)
             coll_force(c, i, Ys, F1[i]);
         }
         for (int i = 0; i < np; i++) {
-            real M = c->p[i].rho_s * (double)c->p[i].N;
+            real M = c->p[i].rho_s * c->p[i].Nw; /* rho_s N_i (N_i = sum chi when fractional) */
             for (int k = 0; k < d; k++) { /* correction */
                 real corr = 1.0 / (2.0 * M) * (1.0 / ((double)K * K)) * (F0[i][k] + F1[i][k]) / 2.0;
                 Y[i][k] = Ys[i][k] + corr;
@@ -678,6 +716,7 @@ int ora_create(const ora_cfg *cfg, ora_ctx **out)
     }
     c->beta = cfg->rigid_beta;
     c->no_stress_penalty = cfg->no_stress_penalty != 0;
+    c->fractional = cfg->fractional != 0;
     /* moving walls: one axis (y or z), tangential velocities, others periodic */
     for (int k = 0; k < 3; k++)
         for (int sd = 0; sd < 2; sd++)
@@ -704,7 +743,8 @@ int ora_create(const ora_cfg *cfg, ora_ctx **out)
     c->u = calloc((size_t)c->N * 3, sizeof(real));
     c->pr = calloc((size_t)c->N, sizeof(real));
     c->owner = malloc((size_t)c->N * sizeof(int));
-    if (!c->f || !c->ft || !c->u || !c->pr || !c->owner) return -2;
+    c->chi = calloc((size_t)c->N, sizeof(real));
+    if (!c->f || !c->ft || !c->u || !c->pr || !c->owner || !c->chi) return -2;
     /* initial state: f = f^eq(p0, u0) everywhere */
     real u0[3] = {0, 0, 0}, fe[QMAX];
     for (int k = 0; k < c->L.d; k++) u0[k] = cfg->u0[k];
@@ -728,6 +768,8 @@ void ora_destroy(ora_ctx *c)
     free(c->rep_X);
     free(c->rep_theta);
     free(c->pend_drho);
+    free(c->pend_dX);
+    free(c->chi);
     free(c);
 }
 
@@ -735,7 +777,8 @@ void ora_destroy(ora_ctx *c)
  * fixed direction of g, and each rho_s,i).  Call between ora_create and
  * ora_set_particles, since U^0 already depends on the parameters.  In the
  * real build the imaginary part does not exist and the call is rejected. */
-int ora_perturb(ora_ctx *c, const double *d_rho_s, int np, double d_tau, double d_gmag, double h)
+int ora_perturb(ora_ctx *c, const double *d_rho_s, int np, double d_tau, double d_gmag, double h,
+                const double *d_X)
 {
     if (!c) return -1;
 #ifdef ORACLE_COMPLEX
@@ -749,13 +792,21 @@ int ora_perturb(ora_ctx *c, const double *d_rho_s, int np, double d_tau, double 
     free(c->pend_drho);
     c->pend_drho = NULL;
     c->pend_np = 0;
+    free(c->pend_dX);
+    c->pend_dX = NULL;
     if (d_rho_s && np > 0) {
         c->pend_drho = malloc(sizeof(double) * (size_t)np);
         for (int i = 0; i < np; i++) c->pend_drho[i] = h * d_rho_s[i];
         c->pend_np = np;
     }
+    if (d_X && np > 0) { /* seeds of the initial centres, [np][3] */
+        c->pend_dX = malloc(sizeof(double) * 3 * (size_t)np);
+        for (int i = 0; i < 3 * np; i++) c->pend_dX[i] = h * d_X[i];
+        c->pend_np = np;
+    }
     return 0;
 #else
+    (void)d_X;
     (void)d_rho_s;
     (void)np;
     (void)d_tau;
@@ -782,7 +833,12 @@ int ora_set_particles(ora_ctx *c, int np, const ora_pin *pin)
         P->a = pin[i].a;
         P->b = pin[i].b;
         for (int k = 0; k < 3; k++) P->X[k] = (k < c->L.d) ? pin[i].x[k] : 0.0;
+#ifdef ORACLE_COMPLEX
+        if (c->pend_dX && i < c->pend_np)
+            for (int k = 0; k < c->L.d; k++) P->X[k] += I * c->pend_dX[3 * i + k];
+#endif
         P->theta = pin[i].theta;
+        if (c->fractional && P->shape == 1) return -1; /* disks and spheres only */
     }
     rasterize(c);
     macros_all(c);
@@ -818,7 +874,8 @@ int ora_set_replay(ora_ctx *c, long n0, long len, const double *X, const double 
 #define REC_W 14
 
 /* Advance n steps.  If rec (real parts) / rec_im (imaginary parts) are given,
- * record X^n, theta^n, U^n, omega^n, A^n, N^n of every step. */
+ * record X^n, theta^n, U^n, omega^n, A^n, N^n (sum chi when fractional) of
+ * every step. */
 int ora_step(ora_ctx *c, long nsteps, double *rec, double *rec_im)
 {
     for (long s = 0; s < nsteps; s++) {
@@ -828,7 +885,7 @@ int ora_step(ora_ctx *c, long nsteps, double *rec, double *rec_im)
         for (int i = 0; i < c->np; i++) {
             particle_t *P = &c->p[i];
             real v[REC_W] = {P->X[0], P->X[1], P->X[2], P->theta, P->U[0], P->U[1], P->U[2],
-                             P->W[0], P->W[1], P->W[2], P->A[0], P->A[1], P->A[2], (double)P->N};
+                             P->W[0], P->W[1], P->W[2], P->A[0], P->A[1], P->A[2], P->Nw};
             for (int k = 0; k < REC_W; k++) {
                 if (rec) rec[(s * c->np + i) * REC_W + k] = RE(v[k]);
                 if (rec_im) rec_im[(s * c->np + i) * REC_W + k] = IM(v[k]);
@@ -876,7 +933,8 @@ int ora_get_fields(ora_ctx *c, double *u, double *p, int32_t *owner)
 }
 
 /* Particle state now (doubles per particle): X[3] theta U^n[3] W^n[3]
- * Uprev[3] Wprev[3] A[3] N  (22 values); U^n, omega^n, N are measured now. */
+ * Uprev[3] Wprev[3] A[3] N Nw pad (22 values); U^n, omega^n, N are measured
+ * now; Nw is sum chi over the owned nodes (= N for the binary indicator). */
 #define PART_W 22
 int ora_get_particles(ora_ctx *c, double *re, double *im)
 {
@@ -888,10 +946,10 @@ int ora_get_particles(ora_ctx *c, double *re, double *im)
         real v[PART_W] = {P->X[0],     P->X[1],     P->X[2],     P->theta,    P->U[0],     P->U[1],
                           P->U[2],     P->W[0],     P->W[1],     P->W[2],     P->Uprev[0], P->Uprev[1],
                           P->Uprev[2], P->Wprev[0], P->Wprev[1], P->Wprev[2], P->A[0],     P->A[1],
-                          P->A[2],     (double)P->N};
+                          P->A[2],     (double)P->N, P->Nw};
         for (int k = 0; k < PART_W; k++) {
-            if (re) re[i * PART_W + k] = (k < 20) ? RE(v[k]) : 0.0;
-            if (im) im[i * PART_W + k] = (k < 20) ? IM(v[k]) : 0.0;
+            if (re) re[i * PART_W + k] = (k < 21) ? RE(v[k]) : 0.0;
+            if (im) im[i * PART_W + k] = (k < 21) ? IM(v[k]) : 0.0;
         }
     }
     return 0;

@@ -10,7 +10,8 @@ Configurations and particles are plain dicts:
              p0=0, eps_p=2, eps_w=1, delta=1, K=1, collision_form=0,
              gravity_form=0, fluid_accel=(0, 0, 0), penalize_all=0,
              wall_velocity=None or [axis][low, high wall][component],
-             rigid_beta=0 (rigid-velocity forcing, an extension), no_stress_penalty=0)
+             rigid_beta=0 (rigid-velocity forcing, an extension), no_stress_penalty=0,
+             fractional=0 (1: the fractional indicator, an extension; disks and spheres))
   particle = dict(shape="disk"|"ellipse"|"sphere", rho_s=..., a=..., b=...,
                   x=(X, Y, Z), theta=...)
 Fields come back with shape (nz, ny, nx, ...) (x fastest).
@@ -25,7 +26,7 @@ from . import build as _build
 SHAPES = {"disk": 0, "ellipse": 1, "sphere": 2}
 LATTICES = {"D2Q9": 0, "D3Q19": 1}
 REC_W = 14  # X[3] theta U[3] W[3] A[3] N
-PART_W = 22  # X[3] theta U[3] W[3] Uprev[3] Wprev[3] A[3] N pad pad
+PART_W = 22  # X[3] theta U[3] W[3] Uprev[3] Wprev[3] A[3] N Nw pad
 
 
 class _Cfg(C.Structure):
@@ -37,6 +38,7 @@ class _Cfg(C.Structure):
         ("K", C.c_int), ("collision_form", C.c_int), ("gravity_form", C.c_int),
         ("fluid_accel", C.c_double * 3), ("penalize_all", C.c_int),
         ("wall_u", C.c_double * 18), ("rigid_beta", C.c_double), ("no_stress_penalty", C.c_int),
+        ("fractional", C.c_int),
     ]
 
 
@@ -61,7 +63,7 @@ def _lib(complex_step=False):
         lib.ora_create.argtypes = [C.POINTER(_Cfg), C.POINTER(P)]
         lib.ora_destroy.argtypes = [P]
         lib.ora_destroy.restype = None
-        lib.ora_perturb.argtypes = [P, dp, I, D, D, D]
+        lib.ora_perturb.argtypes = [P, dp, I, D, D, D, dp]
         lib.ora_set_particles.argtypes = [P, I, C.POINTER(_Pin)]
         lib.ora_set_replay.argtypes = [P, L, L, dp, dp]
         lib.ora_step.argtypes = [P, L, dp, dp]
@@ -123,6 +125,7 @@ def _make_cfg(cfg):
     c.wall_u = (C.c_double * 18)(*wv.ravel())
     c.rigid_beta = float(cfg.get("rigid_beta", 0.0))
     c.no_stress_penalty = int(bool(cfg.get("no_stress_penalty", 0)))
+    c.fractional = int(bool(cfg.get("fractional", 0)))
     return c
 
 
@@ -139,8 +142,9 @@ def _make_pins(parts):
 
 
 class Oracle:
-    """One oracle run.  complex_step=dict(d_rho_s=[...], d_tau=.., d_gmag=.., h=..)
-    selects the complex-step build and seeds the parameter perturbation."""
+    """One oracle run.  complex_step=dict(d_rho_s=[...], d_tau=.., d_gmag=.., d_X=[[..]]*np, h=..)
+    selects the complex-step build and seeds the perturbation of the
+    parameters and of the initial centres."""
 
     def __init__(self, cfg, particles=(), complex_step=None):
         self.cs = complex_step is not None
@@ -160,18 +164,24 @@ class Oracle:
         if self.cs:
             cs = complex_step
             drho = np.ascontiguousarray(np.asarray(cs.get("d_rho_s", np.zeros(self.np)), dtype=np.float64))
+            dX = np.zeros((max(self.np, 1), 3))
+            if cs.get("d_X") is not None:
+                dX[: self.np] = np.asarray(cs["d_X"], dtype=np.float64).reshape(self.np, 3)
+            dX = np.ascontiguousarray(dX)
             rc = self.lib.ora_perturb(self.ctx, _dp(drho), len(drho), float(cs.get("d_tau", 0.0)),
-                                      float(cs.get("d_gmag", 0.0)), float(cs["h"]))
+                                      float(cs.get("d_gmag", 0.0)), float(cs["h"]), _dp(dX))
             if rc != 0:
                 raise RuntimeError("complex-step seed rejected")
         pins = _make_pins(particles)
-        self.lib.ora_set_particles(self.ctx, self.np, pins)
+        if self.lib.ora_set_particles(self.ctx, self.np, pins) != 0:
+            raise ValueError("oracle rejected the particles (the fractional indicator takes disks and spheres)")
 
     def reset_particles(self, particles):
         """Copy particles in again: re-rasterise and re-measure U^0 (= U^{-1})
         from the current populations."""
         self.np = len(particles)
-        self.lib.ora_set_particles(self.ctx, self.np, _make_pins(particles))
+        if self.lib.ora_set_particles(self.ctx, self.np, _make_pins(particles)) != 0:
+            raise ValueError("oracle rejected the particles (the fractional indicator takes disks and spheres)")
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
@@ -229,7 +239,7 @@ class Oracle:
         return {
             "X": raw[:, 0:3], "theta": raw[:, 3], "U": raw[:, 4:7], "omega": raw[:, 7:10],
             "U_prev": raw[:, 10:13], "omega_prev": raw[:, 13:16], "A": raw[:, 16:19],
-            "N": raw[:, 19].astype(np.int64), "raw": raw,
+            "N": raw[:, 19].astype(np.int64), "Nw": raw[:, 20], "raw": raw,
         }
 
     def load_particles(self, raw, step):

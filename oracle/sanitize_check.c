@@ -4,7 +4,7 @@
  * infrastructure only; see tests/test_oracle_sanitize.py).  It exercises
  * every public entry point: D2Q9 with contacts, an ellipse, a periodic
  * axis, K = 2 sub-steps and the rigid-velocity forcing; D3Q19 spheres; moving
- * walls; mask replay; the single-node entry points (real build).  Built
+ * walls; the fractional indicator (2D and 3D); mask replay; the single-node entry points (real build).  Built
  * with -DORACLE_COMPLEX it runs the complex-step build on the same cases.  Prints "ok" and exits 0
  * when every call succeeded.
  */
@@ -23,6 +23,7 @@ typedef struct {
     double wall_u[3][2][3];
     double rigid_beta;
     int no_stress_penalty;
+    int fractional;
 } ora_cfg;
 
 typedef struct {
@@ -110,6 +111,21 @@ int main(void)
     cfg.wall_u[1][0][0] = -0.01, cfg.wall_u[1][1][0] = 0.01;
     ora_pin p1[1] = {{0, 1.0, 3.0, 3.0, {8.0, 6.0, 0}, 0}};
     rc |= run(&cfg, 1, p1, 6) << 8;
+    /* the fractional indicator: disks in contact across a periodic axis, then spheres */
+    memset(&cfg, 0, sizeof(cfg));
+    cfg.lattice = 0;
+    cfg.n[0] = 20, cfg.n[1] = 16, cfg.n[2] = 1;
+    cfg.periodic[0] = 1;
+    cfg.tau = 0.7, cfg.rho_f = 1.0, cfg.g[1] = -1e-3;
+    cfg.eps_p = 2.0, cfg.eps_w = 1.0, cfg.delta = 1.0, cfg.K = 1, cfg.fractional = 1;
+    ora_pin pf[2] = {{0, 1.5, 3.0, 3.0, {1.2, 8.0, 0}, 0.0}, {0, 1.3, 2.5, 2.5, {6.9, 8.3, 0}, 0.0}};
+    rc |= run(&cfg, 2, pf, 6) << 12;
+    memset(&cfg, 0, sizeof(cfg));
+    cfg.lattice = 1;
+    cfg.n[0] = 10, cfg.n[1] = 9, cfg.n[2] = 11;
+    cfg.tau = 0.65, cfg.rho_f = 1.0, cfg.g[2] = -1e-3;
+    cfg.eps_p = 2.0, cfg.eps_w = 1.0, cfg.delta = 1.0, cfg.K = 1, cfg.fractional = 1;
+    rc |= run(&cfg, 2, p3, 4) << 16;
 #ifndef ORACLE_COMPLEX
     /* single-node entry points */
     double u[3] = {0.01, -0.02, 0.0}, fe[19], acc[3] = {1e-4, 0, 0}, ft[19];

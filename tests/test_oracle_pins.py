@@ -307,9 +307,10 @@ def test_collision_force_wall():
 
 # ---------------------------------------------------------- whole step vs brute force
 
-def _compare_with_brute(kind, n, periodic, parts, g, steps, seed, K=1, beta=0.0, no_stress_penalty=False):
+def _compare_with_brute(kind, n, periodic, parts, g, steps, seed, K=1, beta=0.0, no_stress_penalty=False,
+                        fractional=False):
     cfg = dict(lattice=kind, n=n, periodic=periodic, tau=0.7, g=g, eps_p=2.0, eps_w=1.0, delta=1.0, K=K,
-               rigid_beta=beta, no_stress_penalty=int(no_stress_penalty))
+               rigid_beta=beta, no_stress_penalty=int(no_stress_penalty), fractional=int(fractional))
     o = O.Oracle(cfg, parts)
     Q = 9 if kind == "D2Q9" else 19
     shp = (n[2] if kind == "D3Q19" else 1, n[1], n[0])
@@ -317,7 +318,7 @@ def _compare_with_brute(kind, n, periodic, parts, g, steps, seed, K=1, beta=0.0,
     o.set_f(f0)
     o.reset_particles(parts)
     st = brute.initial_state(kind, n if len(n) == 3 else tuple(n) + (1,), periodic, 0.7, 0.0, 1.0, g, (0, 0, 0),
-                             parts, K=K, beta=beta, no_stress_penalty=no_stress_penalty)
+                             parts, K=K, beta=beta, no_stress_penalty=no_stress_penalty, fractional=fractional)
     for nd in st["f"]:
         x, y, z = nd
         st["f"][nd] = list(f0[z, y, x])
@@ -823,3 +824,144 @@ def test_stored_gradient_complex_step_vs_central_differences():
     assert len(have) >= 4
     for k in have:
         assert abs(cs[k] - fd[k]) <= 1e-6 * abs(fd[k]), (gold["params"][k], cs[k], fd[k])
+
+
+# ---------------------------------------------------------- fractional indicator (an extension)
+#
+# chi_i(x) = min(1, R_i + 1/2 - |x - X_i|) on the band |x - X_i| < R_i + 1/2
+# (disks and spheres), every use of the indicator weighted by chi.  The
+# integral of chi over the plane is pi (R^2 + 1/12) (a disk; the linear ramp of
+# width one across the circle of radius R adds pi/12 to pi R^2), over space
+# (4/3) pi (R^3 + R/4) (a sphere); averaged over the position of the centre
+# within a lattice cell, the lattice sum of chi equals that integral exactly.
+
+FRAC_RNG = np.random.default_rng(2511)
+
+
+@pytest.mark.parametrize("R", [3.3, 8.0])
+def test_fractional_area_disk(R):
+    vals = []
+    for _ in range(200):
+        X = (20.0 + FRAC_RNG.uniform(0, 1), 20.0 + FRAC_RNG.uniform(0, 1))
+        o = O.Oracle(dict(lattice="D2Q9", n=(40, 40), tau=0.8, fractional=1), [dict(shape="disk", rho_s=1.0, a=R, x=X)])
+        vals.append(o.particles()["Nw"][0])
+    vals = np.array(vals)
+    se = vals.std() / np.sqrt(len(vals))
+    exact = np.pi * (R * R + 1.0 / 12.0)
+    assert abs(vals.mean() - exact) < 5 * se
+    # a binary area (pi R^2) or a ramp ending at R (pi (R^2 - R + 1/3)) is far outside
+    assert abs(vals.mean() - np.pi * R * R) > 10 * se
+    assert abs(vals.mean() - np.pi * (R * R - R + 1.0 / 3.0)) > 100 * se
+
+
+def test_fractional_volume_sphere():
+    R = 4.0
+    vals = []
+    for _ in range(80):
+        X = tuple(8.0 + FRAC_RNG.uniform(0, 1, 3))
+        o = O.Oracle(dict(lattice="D3Q19", n=(16, 16, 16), tau=0.8, fractional=1),
+                     [dict(shape="sphere", rho_s=1.0, a=R, x=X)])
+        vals.append(o.particles()["Nw"][0])
+    vals = np.array(vals)
+    se = vals.std() / np.sqrt(len(vals))
+    assert abs(vals.mean() - 4.0 / 3.0 * np.pi * (R ** 3 + R / 4.0)) < 5 * se
+    assert abs(vals.mean() - 4.0 / 3.0 * np.pi * R ** 3) > 10 * se
+
+
+def test_fractional_rigid_field_2d():
+    """The chi-weighted sums of a rigid field u = U0 + omega0 z x r over a disk
+    centred on a node (the weights are symmetric, so sum chi r = 0) return U0
+    and omega0; the weight sum is that of the ramp over the disk's nodes."""
+    n = (40, 36, 1)
+    X = np.array([20.0, 17.0])
+    U0 = np.array([0.013, -0.007])
+    w0 = 2.3e-3
+    o = O.Oracle(dict(lattice="D2Q9", n=n, tau=0.8, fractional=1), [dict(shape="disk", rho_s=1.0, a=7.0, x=tuple(X))])
+    f = np.zeros((1, n[1], n[0], 9))
+    for y in range(n[1]):
+        for x in range(n[0]):
+            r = np.array([x, y]) - X
+            f[0, y, x] = O.feq("D2Q9", 0.0, U0 + w0 * np.array([-r[1], r[0]]))
+    o.set_f(f)
+    P = o.particles()
+    _, _, own = o.fields()
+    ys, xs = np.nonzero(own[0] == 0)
+    d = np.hypot(xs - X[0], ys - X[1])
+    assert d.max() < 7.5 and np.sum((np.hypot(*np.meshgrid(np.arange(40) - 20.0, np.arange(36) - 17.0)) < 7.5)) == len(d)
+    assert abs(P["Nw"][0] - np.minimum(1.0, 7.5 - d).sum()) < 1e-12
+    assert np.abs(P["U"][0, :2] - U0).max() < 1e-16
+    assert abs(P["omega"][0, 2] - w0) < 1e-16
+
+
+def test_fractional_rigid_field_3d():
+    n = (16, 15, 14)
+    X = np.array([8.0, 7.0, 6.0])
+    U0 = np.array([0.01, -0.02, 0.005])
+    W0 = np.array([1e-3, -2e-3, 3e-3])
+    o = O.Oracle(dict(lattice="D3Q19", n=n, tau=0.8, fractional=1), [dict(shape="sphere", rho_s=1.0, a=4.0, x=tuple(X))])
+    f = np.zeros((n[2], n[1], n[0], 19))
+    for z in range(n[2]):
+        for y in range(n[1]):
+            for x in range(n[0]):
+                r = np.array([x, y, z]) - X
+                f[z, y, x] = O.feq("D3Q19", 0.0, U0 + np.cross(W0, r))
+    o.set_f(f)
+    P = o.particles()
+    assert np.abs(P["U"][0] - U0).max() < 1e-16
+    assert np.abs(P["omega"][0] - W0).max() < 1e-15
+
+
+def test_fractional_vs_brute_d2q9():
+    """The whole step with the fractional indicator against the brute-force
+    transcription: two disks whose bands meet (the lower id owns the shared
+    nodes), one across the periodic x axis, contact forces active."""
+    parts = [dict(shape="disk", rho_s=1.6, a=2.2, x=(0.7, 3.2)),
+             dict(shape="disk", rho_s=1.3, a=2.0, x=(5.1, 4.4))]
+    st = _compare_with_brute("D2Q9", (9, 8, 1), (1, 0, 0), parts, (0.0, -1e-3, 0.0), 3, 3, fractional=True)
+    assert any(abs(a) > 1e-8 for q in st["parts"] for a in q["A"])
+    assert any(0.0 < abs(st["parts"][0]["N"] - k) for k in range(200))  # a weight sum, not a count
+
+
+def test_fractional_vs_brute_d3q19():
+    parts = [dict(shape="sphere", rho_s=1.6, a=1.6, x=(2.0, 2.1, 2.3)),
+             dict(shape="sphere", rho_s=1.4, a=1.4, x=(3.4, 3.0, 3.9))]
+    _compare_with_brute("D3Q19", (5, 5, 6), (0, 1, 0), parts, (0.0, 0.0, -1e-3), 2, 4, fractional=True)
+
+
+def test_fractional_rejects_ellipses():
+    with pytest.raises(ValueError):
+        O.Oracle(dict(lattice="D2Q9", n=(20, 20), tau=0.8, fractional=1),
+                 [dict(shape="ellipse", rho_s=1.2, a=4.0, b=2.0, x=(10.0, 10.0), theta=0.3)])
+
+
+def test_fractional_position_gradient():
+    """With the fractional indicator the loss is differentiable in the initial
+    centres: the complex-step derivative (the step map with nothing frozen)
+    equals central differences of plain runs, with no replay of the indicator.
+    With the binary indicator the same differences do not converge (the
+    indicator jumps between the +h and -h runs)."""
+    cfg, parts = _small_settling()
+    steps = 60
+    cfg_f = dict(cfg, fractional=1)
+
+    def loss(c, p):
+        o = O.Oracle(c, p)
+        o.step(steps)
+        return o.particles()["X"][:, 1].mean()
+
+    def moved(i, k, h):
+        p2 = [dict(q) for q in parts]
+        x = list(p2[i]["x"]) + [0.0]
+        x[k] += h
+        p2[i]["x"] = tuple(x[:2])
+        return p2
+
+    h = 1e-4
+    for i, k in ((0, 0), (0, 1), (1, 0)):
+        dX = np.zeros((2, 3))
+        dX[i, k] = 1.0
+        _, dcs = _loss(cfg_f, parts, steps, cs=dict(d_X=dX, h=1e-30))
+        fd = (loss(cfg_f, moved(i, k, h)) - loss(cfg_f, moved(i, k, -h))) / (2 * h)
+        assert abs(dcs - fd) <= 1e-6 * max(abs(fd), 1e-3), (i, k, dcs, fd)
+    fd_b = [(loss(cfg, moved(0, 0, hb)) - loss(cfg, moved(0, 0, -hb))) / (2 * hb) for hb in (1e-4, 1e-5)]
+    assert abs(fd_b[0] - fd_b[1]) > 10 * abs(fd_b[0]) * 1e-2
