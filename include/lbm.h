@@ -111,6 +111,18 @@ typedef struct {
                                momentum-sum slot tables of the K = 1 step (so a caller's
                                workspace owns them).  0, or a larger body later: the
                                library allocates those tables at lbm_set_particles.       */
+    int32_t fractional_indicator; /* 1: the fractional indicator, an extension beyond the paper
+                               (whose indicator is binary) for gradients in the positions:
+                               a node of the band |x - X_i| < R_i + 1/2 belongs to particle i
+                               (the lowest id where bands meet) with the weight
+                               chi = min(1, R_i + 1/2 - |x - X_i|), which multiplies its
+                               acceleration (eq. 5-8) and the penalization strength (eq. 17)
+                               and weights the momentum sums (eq. 22a-b:
+                               N_i = sum chi, U_i = sum chi u / N_i, omega_i from
+                               sum chi r x u and sum chi |r|^2, the tensor in 3D) and the
+                               mass M_i = rho_s N_i of Algorithm 1.  Disks and spheres only;
+                               not with rigid_beta > 0; not differentiated by
+                               lbm_backward.  0: the paper's binary indicator.            */
 } lbm_config;
 
 typedef struct {

@@ -26,7 +26,7 @@ constexpr size_t ALIGN = 256;
 
 // message of the last lbm_workspace_size / lbm_create failure on this thread
 thread_local std::string g_create_err = "no error";
-constexpr int PART_DOUBLES = 3 * 7 + 1 + 4 + 3 + 3 + 3 * 5 + 1; // X Xn U W Uprev Wprev A, theta, rho a b C, acc, Unext, Ub Y Ys Y2 Dc, dth
+constexpr int PART_DOUBLES = 3 * 7 + 1 + 4 + 3 + 3 + 3 * 5 + 1 + 1 + 4; // X Xn U W Uprev Wprev A, theta, rho a b C, acc, Unext, Ub Y Ys Y2 Dc, dth, Nw, geo
 constexpr double CS2 = 1.0 / 3.0;
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
@@ -102,7 +102,7 @@ Layout layout_for(const lbm_config *cfg, int Q, int d, int64_t N)
     // library allocates them at lbm_set_particles)
     L.slots = off;
     L.slots_bytes = 0;
-    if (cfg->max_radius > 0 && cfg->K == 1 && !(cfg->rigid_beta > 0)) {
+    if (cfg->max_radius > 0 && cfg->K == 1 && !(cfg->rigid_beta > 0) && !cfg->fractional_indicator) {
         const int n[3] = {cfg->n[0], cfg->n[1], d == 3 ? cfg->n[2] : 1};
         const int per[3] = {cfg->periodic[0] != 0, cfg->periodic[1] != 0, d == 3 && cfg->periodic[2] != 0};
         SlotSizes z;
@@ -152,6 +152,8 @@ int validate_cfg(const lbm_config *cfg, std::string &why, int &Q, int &d, int64_
     if (cfg->eps_p <= 0 || cfg->eps_w <= 0 || cfg->delta <= 0) return why = "eps_p, eps_w, delta must be positive", LBM_EINVAL;
     if (!(cfg->rigid_beta >= 0.0 && cfg->rigid_beta <= 1.0)) return why = "rigid_beta must lie in [0, 1]", LBM_EINVAL;
     if (!(cfg->max_radius >= 0.0 && cfg->max_radius < 1e6)) return why = "max_radius must be >= 0 and finite", LBM_EINVAL;
+    if (cfg->fractional_indicator && cfg->rigid_beta > 0)
+        return why = "the fractional indicator is not defined with the rigid-velocity forcing", LBM_EINVAL;
     // moving walls: one axis (y, or z in 3D), tangential, every other axis periodic
     int wall_axis = 0;
     for (int k = 0; k < 3; ++k)
@@ -264,6 +266,8 @@ void carve(lbm_ctx *c, const Layout &L)
     c->P.Ub = take(3);
     c->P.Dc = take(3);
     c->P.dth = take(1);
+    c->P.Nw = take(1);
+    c->P.geo = take(4);
     c->P.acc_f = (float *)(base + L.pf);
     int32_t *pi = (int32_t *)(base + L.pi);
     c->P.shape = pi;
@@ -409,6 +413,12 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
     }
     c->sp.penalize_all = cfg->penalize_all != 0;
     c->sp.beta = cfg->rigid_beta;
+    c->sp.frac = cfg->fractional_indicator != 0;
+    c->rp.frac = c->sp.frac;
+    for (int k = 0; k < 3; ++k) {
+        c->sp.n[k] = k == 0 ? cfg->n[0] : k == 1 ? cfg->n[1] : (d == 3 ? cfg->n[2] : 1);
+        c->sp.per[k] = k < d && cfg->periodic[k] != 0;
+    }
     c->sp.stress = cfg->no_stress_penalty == 0;
     if (!c->sp.stress) c->sp.alpha = 0.0; // S of eq. (17) is linear in alpha: off
     c->sp.alpha_tracks_tau = !(cfg->alpha > 0);
@@ -492,6 +502,7 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
         c->own_mem = true;
     }
     carve(c, L);
+    c->sp.geo = c->P.geo;
     double u0[3] = {cfg->u0[0], cfg->u0[1], d == 3 ? cfg->u0[2] : 0.0}, fe[19];
     feq_host(cfg->lattice, cfg->p0, u0, fe);
     if ((e = hipMemcpy(c->wall_tab, wall_tab, sizeof(wall_tab), hipMemcpyHostToDevice)) != hipSuccess ||
@@ -536,9 +547,13 @@ namespace {
 // The inclusion test of eq. (9) as the device evaluates it (raster_items in
 // particles.hip): the same operation order, every product and sum rounded on
 // its own (no contraction).
-bool host_inside(int shape, double a, double b, double cs, double sn, double dx, double dy, double dz)
+bool host_inside(int shape, double a, double b, double cs, double sn, double dx, double dy, double dz, bool band = false)
 {
 #pragma clang fp contract(off)
+    if (band) { // the fractional indicator's band |r| < R + 1/2 (disks and spheres)
+        const double Rh = a + 0.5;
+        return (dx * dx + dy * dy) + dz * dz < Rh * Rh;
+    }
     if (shape == LBM_DISK) return dx * dx + dy * dy <= a * a;
     if (shape == LBM_SPHERE) return (dx * dx + dy * dy) + dz * dz <= a * a;
     const double xi = cs * dx + sn * dy;
@@ -580,7 +595,9 @@ std::vector<int> host_claims(const lbm_ctx *c, const lbm_particle *p, int n)
             for (int y = lo[1]; y <= hi[1]; ++y)
                 for (int x = lo[0]; x <= hi[0]; ++x) {
                     const double dz = d == 3 ? (double)z - q.x[2] : 0.0;
-                    if (!host_inside(q.shape, q.a, b, cs, sn, (double)x - q.x[0], (double)y - q.x[1], dz)) continue;
+                    if (!host_inside(q.shape, q.a, b, cs, sn, (double)x - q.x[0], (double)y - q.x[1], dz,
+                                     c->sp.frac != 0))
+                        continue;
                     auto wrapn = [](int v, int m) { return v < 0 ? v + m : (v >= m ? v - m : v); };
                     const int64_t id = wrapn(x, nn[0]) + (int64_t)nn[0] * (wrapn(y, nn[1]) + (int64_t)nn[1] * wrapn(z, nn[2]));
                     if (!claimed.count(id)) ++count[i];
@@ -604,6 +621,8 @@ int check_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
         const lbm_particle &q = p[i];
         const bool ok_shape = (d == 2 && (q.shape == LBM_DISK || q.shape == LBM_ELLIPSE)) || (d == 3 && q.shape == LBM_SPHERE);
         if (!ok_shape) return fail(c, LBM_EINVAL, "shape not valid for this lattice");
+        if (c->sp.frac && q.shape == LBM_ELLIPSE)
+            return fail(c, LBM_EINVAL, "the fractional indicator takes disks and spheres only");
         if (!(q.rho_s > 0) || !isfinite(q.rho_s) || !(q.a >= 1.0) || !isfinite(q.a))
             return fail(c, LBM_EINVAL, "rho_s must be > 0 and a >= 1");
         if (q.shape == LBM_ELLIPSE && !(q.b >= 1.0 && q.b <= q.a)) return fail(c, LBM_EINVAL, "ellipse needs a >= b >= 1");
@@ -682,7 +701,9 @@ int install_particles(lbm_ctx *c, const lbm_particle *p, int32_t n)
     // fused-sums step (K = 1): the slot tables (slot_sizes), in the
     // workspace when it holds a large enough region, else allocated here
     c->fused = 0;
-    if (c->rp.K == 1 && n > 0 && !(c->sp.beta > 0)) { // the forcing pass needs the indicator after the sums
+    // (the forcing pass needs the indicator after the sums; the slots hold
+    // node counts, not the weight sums of the fractional indicator)
+    if (c->rp.K == 1 && n > 0 && !(c->sp.beta > 0) && !c->sp.frac) {
         const Geom &g = c->geo;
         int ext = 0;
         for (int i = 0; i < n; ++i) ext = std::max(ext, (int)ceil(2.0 * p[i].a) + 7);

@@ -28,6 +28,8 @@ struct PartDev {
     double *Unext;                                 // [cap*3] U^n written by the fused-sums step (swapped with U)
     double *Ub, *dth;                              // U_bar = (U^n + U^{n-1})/2 [cap*3], theta increment [cap]
     double *Y, *Ys, *Y2, *Dc;                      // [cap*3] sub-step scratch (Dc: summed corrections)
+    double *Nw;                                    // [cap] N_i as a weight sum (sum chi, or the node count)
+    double *geo;                                   // [cap*4] centre of the current indicator, bounding radius
     int32_t *shape, *N;                            // [cap]
     int32_t *lo, *hi;                              // [cap*3] scan box (unwrapped node coords)
 };
@@ -78,6 +80,14 @@ struct StepParams {
     // method; 0: alpha is held at 0, which switches the source off)
     double beta;
     int stress;
+    // fractional indicator (an extension, disks and spheres): a node of the
+    // band |x - X_i| < R_i + 1/2 carries chi = min(1, R_i + 1/2 - |x - X_i|),
+    // which weights its acceleration and penalization; geo holds, per
+    // particle, the centre the indicator was built from and R ([cap][4]), and
+    // n, per the lattice (for the node coordinates)
+    int frac;
+    const double *geo;
+    int n[3], per[3];
 };
 
 // Device pointers of one backward step of Algorithm 1 (see adjoint.hip).
@@ -97,6 +107,7 @@ struct RigidParams {
     double rho_f, gmag, g[3];
     double eps_p, eps_w, delta;
     int K, cform, gform, np, d;
+    int frac; // the fractional indicator (StepParams::frac)
 };
 
 } // namespace lbm

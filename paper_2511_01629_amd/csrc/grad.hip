@@ -269,8 +269,10 @@ int forward_impl(lbm_ctx *c, int64_t nsteps, int32_t every, void *ws, size_t ws_
     if (!c->fresh) return c->err = "a differentiated run must start right after lbm_set_particles", LBM_ESTATE;
     if (c->np == 0) return c->err = "no particles", LBM_ESTATE;
     if (c->rp.K != 1) return c->err = "the adjoint of Algorithm 1 is implemented for K = 1", LBM_EINVAL;
-    if (c->sp.beta > 0 || !c->sp.stress)
-        return c->err = "the adjoint covers the paper's method (no rigid-velocity forcing, stress penalty on)", LBM_EINVAL;
+    if (c->sp.beta > 0 || !c->sp.stress || c->sp.frac)
+        return c->err = "the adjoint covers the paper's method (binary indicator, no rigid-velocity forcing, stress "
+                        "penalty on)",
+               LBM_EINVAL;
     (void)hipSetDevice(c->device);
     free_grad(c);
     GradState *G = new GradState();

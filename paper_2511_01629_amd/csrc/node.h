@@ -305,6 +305,31 @@ __device__ __forceinline__ T feq_q(int q, T p3, T cu, T u15)
     return T(L::w[q]) * (p3 + T(3) * cu + T(4.5) * cu * cu - u15);
 }
 
+// Weight of node idx in the fractional indicator of particle own (an
+// extension; StepParams::frac): chi = min(1, R + 1/2 - |r|) with r = x - X,
+// X the centre the indicator was built from, x the node taken at its
+// nearest image on periodic axes; FP64, every product and sum rounded on its
+// own (the inclusion test's arithmetic).
+__device__ __forceinline__ double frac_chi(int idx, uint16_t own, const StepParams &sp)
+{
+    const int x = idx % sp.n[0], yz = idx / sp.n[0];
+    const int c[3] = {x, yz % sp.n[1], yz / sp.n[1]};
+    double r2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double X = sp.geo[4 * own + k];
+        int v = c[k];
+        if (sp.per[k]) {
+            const double half = 0.5 * sp.n[k], dd = (double)v - X;
+            v += dd > half ? -sp.n[k] : (dd < -half ? sp.n[k] : 0);
+        }
+        const double dk = (k < 2 || sp.n[2] > 1) ? __dsub_rn((double)v, X) : 0.0;
+        r2 = __dadd_rn(r2, __dmul_rn(dk, dk));
+    }
+    const double v = __dsub_rn(__dadd_rn(sp.geo[4 * own + 3], 0.5), sqrt(r2));
+    return v >= 1.0 ? 1.0 : v;
+}
+
 // Collision of one node, in place: f holds the pulled populations on entry
 // and f~ on return (right side of eq. 10 with F of eq. 14 and, on solid
 // nodes, S of eq. 17).  Writes the velocity of solid nodes for the sums
@@ -316,10 +341,17 @@ __device__ __forceinline__ void collide_node(T *f, uint16_t own, const T *__rest
 {
     const bool solid = own != FLUID;
     T ax = 0, ay = 0, az = 0;
+    T chi = 1;
     if (solid) {
         ax = acc_tab[3 * own + 0];
         ay = acc_tab[3 * own + 1];
         az = acc_tab[3 * own + 2];
+        if (sp.frac) { // the force density in proportion to the solid fraction
+            chi = (T)frac_chi(idx, own, sp);
+            ax = chi * ax;
+            ay = chi * ay;
+            az = chi * az;
+        }
     } else if (sp.has_fluid_acc) {
         ax = (T)sp.fluid_acc[0];
         ay = (T)sp.fluid_acc[1];
@@ -362,7 +394,9 @@ __device__ __forceinline__ void collide_node(T *f, uint16_t own, const T *__rest
         if (L::cy[q] * L::cz[q] > 0) Pyz += fneq[q];
         if (L::cy[q] * L::cz[q] < 0) Pyz -= fneq[q];
     }
-    const T al = pen ? (T)sp.alpha : T(0);
+    // the penalization strength, in proportion to the solid fraction with the
+    // fractional indicator
+    const T al = pen ? (solid && sp.frac ? (T)((double)chi * sp.alpha) : (T)sp.alpha) : T(0);
     const T trace3 = (Pxx + Pyy + Pzz) * T(1.0 / 3.0);
     const T gpre = T(1) - T(0.5) * om;
     const T ua = L::D == 3 ? ux * ax + uy * ay + uz * az : ux * ax + uy * ay;

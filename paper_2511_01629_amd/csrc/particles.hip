@@ -31,6 +31,7 @@
 // New centres go to a second buffer (P.Xn), swapped by the host, because every
 // workgroup reads all old centres.
 #include "lattice.h"
+#include "node.h"
 #include "reduce.h"
 
 namespace lbm {
@@ -38,10 +39,18 @@ namespace lbm {
 __device__ __forceinline__ double dmul(double a, double b) { return __dmul_rn(a, b); }
 __device__ __forceinline__ double dadd(double a, double b) { return __dadd_rn(a, b); }
 
+// The shape code of the fractional indicator's band |r| < R + 1/2 (disks and
+// spheres of radius a; StepParams::frac) for inside_shape.
+constexpr int SHAPE_BAND = 16;
+
 // inside test of eq. (9) on the displacement (dx, dy, dz) from the centre
 __device__ __forceinline__ bool inside_shape(int shape, double a, double b, double cs, double sn, double dx, double dy,
                                              double dz)
 {
+    if (shape == SHAPE_BAND) {
+        const double Rh = dadd(a, 0.5);
+        return dadd(dadd(dmul(dx, dx), dmul(dy, dy)), dmul(dz, dz)) < dmul(Rh, Rh);
+    }
     if (shape == LBM_DISK) return dadd(dmul(dx, dx), dmul(dy, dy)) <= dmul(a, a);
     if (shape == LBM_SPHERE) return dadd(dadd(dmul(dx, dx), dmul(dy, dy)), dmul(dz, dz)) <= dmul(a, a);
     const double xi = dadd(dmul(cs, dx), dmul(sn, dy));
@@ -152,7 +161,7 @@ template <int D> struct NSums {
 template <int D, int U>
 __device__ __forceinline__ void cell_sums(const uint16_t *owner_in, uint16_t *owner_clr, const double *__restrict__ usol,
                                           const Geom &g, int i, const double *Xc, const Box &b, int lane, int nl,
-                                          double *s)
+                                          double *s, const StepParams *frac, int &count)
 {
     const int N = (int)g.N;
     const double X0 = Xc[0], X1 = Xc[1], X2 = D == 3 ? Xc[2] : 0.0;
@@ -182,6 +191,31 @@ __device__ __forceinline__ void cell_sums(const uint16_t *owner_in, uint16_t *ow
             if (base + u * nl >= b.cells || o[u] != (uint16_t)i) continue;
             if (owner_clr) owner_clr[node] = FLUID;
             const double rx = (double)xu - X0, ry = (double)yu - X1;
+            ++count;
+            if (frac) { // the fractional indicator: each sum weighted by chi
+                const double w = frac_chi(node, (uint16_t)i, *frac);
+                s[0] += w;
+                s[1] += w * ux[u];
+                s[2] += w * uy[u];
+                if constexpr (D == 2) {
+                    s[3] += w * (rx * uy[u] - ry * ux[u]);
+                    s[4] += w * (rx * rx + ry * ry);
+                } else {
+                    const double rz = (double)zu - X2;
+                    s[3] += w * uz[u];
+                    s[4] += w * (ry * uz[u] - rz * uy[u]);
+                    s[5] += w * (rz * ux[u] - rx * uz[u]);
+                    s[6] += w * (rx * uy[u] - ry * ux[u]);
+                    const double rr = rx * rx + ry * ry + rz * rz;
+                    s[7] += w * (rr - rx * rx);
+                    s[8] += w * (rr - ry * ry);
+                    s[9] += w * (rr - rz * rz);
+                    s[10] -= w * (rx * ry);
+                    s[11] -= w * (rx * rz);
+                    s[12] -= w * (ry * rz);
+                }
+                continue;
+            }
             s[0] += 1.0;
             s[1] += ux[u];
             s[2] += uy[u];
@@ -229,13 +263,13 @@ __device__ __forceinline__ PrevState load_prev(const PartDev &P, int i)
 // (omega^n + omega^{n-1})/2 (z component), then U^{n-1} <- U^n, omega^{n-1} <-
 // omega^n.  Returns N; Ub (3) and dth receive U_bar and dtheta.
 template <int D, bool STEP>
-__device__ __forceinline__ int close_sums(PartDev &P, int i, const double *t, const PrevState &ps, double *rec,
-                                          double *Ub, double &dth)
+__device__ __forceinline__ int close_sums(PartDev &P, int i, const double *t, int cnt, const PrevState &ps,
+                                          double *rec, double *Ub, double &dth)
 {
-    const int cnt = (int)t[0];
     P.N[i] = cnt;
+    P.Nw[i] = t[0]; // the node count, or sum chi
     double U[3] = {0, 0, 0}, W[3] = {0, 0, 0};
-    if (cnt > 0) {
+    if (cnt > 0 && t[0] != 0.0) {
         if constexpr (D == 2) {
             U[0] = t[1] / t[0];
             U[1] = t[2] / t[0];
@@ -270,7 +304,7 @@ __device__ __forceinline__ int close_sums(PartDev &P, int i, const double *t, co
                 r[14 + k] = ps.Uprev[k];
             }
             r[3] = ps.theta;
-            r[13] = (double)cnt;
+            r[13] = t[0];
         }
         dth = 0.5 * (W[2] + ps.Wprev[2]);
         P.dth[i] = dth;
@@ -285,24 +319,29 @@ __device__ __forceinline__ int close_sums(PartDev &P, int i, const double *t, co
 }
 
 // One workgroup of BS threads per particle.
+// The sums carry the node count as one more entry (the weight sum s[0] is
+// not a count with the fractional indicator).
 template <int D, bool STEP, int BS>
 __global__ __launch_bounds__(BS) void k_sums(const uint16_t *owner_in, uint16_t *owner_clr,
                                              const double *__restrict__ usol, PartDev P, Geom g,
-                                             double *__restrict__ rec)
+                                             double *__restrict__ rec, StepParams sp)
 {
     constexpr int NS = NSums<D>::value;
-    __shared__ double part[BS / WAVE][NS];
+    __shared__ double part[BS / WAVE][NS + 1];
     const int i = blockIdx.x;
     const PrevState ps = load_prev(P, i);
     const Box b = make_box(P.lo + 3 * i, P.hi + 3 * i);
-    double s[NS];
+    double s[NS + 1];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) s[k] = 0.0;
-    cell_sums<D, UNR>(owner_in, STEP ? owner_clr : nullptr, usol, g, i, ps.X, b, threadIdx.x, BS, s);
-    block_sum<NS, BS>(s, part);
+    for (int k = 0; k <= NS; ++k) s[k] = 0.0;
+    int count = 0;
+    cell_sums<D, UNR>(owner_in, STEP ? owner_clr : nullptr, usol, g, i, ps.X, b, threadIdx.x, BS, s,
+                      sp.frac ? &sp : nullptr, count);
+    s[NS] = (double)count;
+    block_sum<NS + 1, BS>(s, part);
     if (threadIdx.x != 0) return;
     double Ub[3], dth;
-    close_sums<D, STEP>(P, i, s, ps, rec, Ub, dth);
+    close_sums<D, STEP>(P, i, s, (int)s[NS], ps, rec, Ub, dth);
 }
 
 // ------------------------------------------------------- collision forces
@@ -434,6 +473,7 @@ __global__ __launch_bounds__(BS) void k_rigid_raster(uint16_t *__restrict__ owne
     }
     if (update) {
         const int cnt = P.N[i];
+        const double Nw = P.Nw[i]; // the node count, or sum chi
         const double dth = P.dth[i];
         // orientation of the new indicator, ahead of the force sums (d == 2 only
         // turns; ellipses are 2D)
@@ -455,7 +495,7 @@ __global__ __launch_bounds__(BS) void k_rigid_raster(uint16_t *__restrict__ owne
         if (threadIdx.x == 0) {
             wall_force(Xi, Ri, Ci, rp, g, F);
             wall_force(Yi, Ri, Ci, rp, g, F + 3);
-            const double M = rho * (double)cnt;
+            const double M = rho * Nw;
             const double c = M > 0.0 ? 1.0 / (2.0 * M) : 0.0;
             double Y[3], Dc[3];
             for (int k = 0; k < 3; ++k) {
@@ -481,10 +521,13 @@ __global__ __launch_bounds__(BS) void k_rigid_raster(uint16_t *__restrict__ owne
         for (int k = 0; k < 3; ++k) { // unused axes get [0, 0]
             P.lo[3 * i + k] = s_lo[k];
             P.hi[3 * i + k] = s_hi[k];
+            P.geo[4 * i + k] = s_X[k]; // the centre this indicator is built from
         }
+        P.geo[4 * i + 3] = Ri;
     }
     __syncthreads();
-    raster_items<UNR>(owner, g, d, i, s_X, shape, Ri, bi, s_cs, s_sn, s_lo, s_hi, threadIdx.x, BS);
+    raster_items<UNR>(owner, g, d, i, s_X, rp.frac ? SHAPE_BAND : shape, Ri, bi, s_cs, s_sn, s_lo, s_hi, threadIdx.x,
+                      BS);
 }
 
 // Acceleration table a_i = b_i g + A_i of every particle from the current
@@ -689,6 +732,7 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
         for (int k = 0; k < 3; ++k) Ub[k] = 0.5 * (U[k] + ps.Uprev[k]);
         if (lane == 0) {
             P.N[i] = cnt;
+            P.Nw[i] = (double)cnt;
             if (rec) {
                 double *r = rec + REC_STRIDE * i;
                 for (int k = 0; k < 3; ++k) {
@@ -767,7 +811,9 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
             for (int k = 0; k < 3; ++k) {
                 P.lo[3 * i + k] = s_lo[k];
                 P.hi[3 * i + k] = s_hi[k];
+                P.geo[4 * i + k] = s_X[k];
             }
+            P.geo[4 * i + 3] = Ri;
         }
     }
     __syncthreads();
@@ -803,7 +849,7 @@ __global__ __launch_bounds__(1024) void k_rigid_substeps(PartDev P, RigidParams 
             }
             wall_force(P.Y + 3 * i, Ri, Ci, rp, g, F0);
             wall_force(P.Ys + 3 * i, Ri, Ci, rp, g, F1);
-            const double M = P.rho_s[i] * (double)P.N[i];
+            const double M = P.rho_s[i] * P.Nw[i]; // rho_s N_i (N_i = sum chi when fractional)
             const double c = M > 0.0 ? 1.0 / (2.0 * M) * (1.0 / ((double)K * K)) : 0.0;
             for (int k = 0; k < 3; ++k) {
                 const double corr = k < d ? c * (F0[k] + F1[k]) / 2.0 : 0.0;
@@ -918,10 +964,10 @@ hipError_t launch_reduce(lbm_ctx *c, int step, double *rec, int scratch)
         P.W = c->P.Ys;
     }
     if (c->d == 2)
-        return step ? launch(c, k_sums<2, true, SUMS_BS2>, grid, dim3(SUMS_BS2), oin, oclr, us, P, c->geo, rec)
-                    : launch(c, k_sums<2, false, SUMS_BS2>, grid, dim3(SUMS_BS2), oin, oclr, us, P, c->geo, rec);
-    return step ? launch(c, k_sums<3, true, SUMS_BS3>, grid, dim3(SUMS_BS3), oin, oclr, us, P, c->geo, rec)
-                : launch(c, k_sums<3, false, SUMS_BS3>, grid, dim3(SUMS_BS3), oin, oclr, us, P, c->geo, rec);
+        return step ? launch(c, k_sums<2, true, SUMS_BS2>, grid, dim3(SUMS_BS2), oin, oclr, us, P, c->geo, rec, c->sp)
+                    : launch(c, k_sums<2, false, SUMS_BS2>, grid, dim3(SUMS_BS2), oin, oclr, us, P, c->geo, rec, c->sp);
+    return step ? launch(c, k_sums<3, true, SUMS_BS3>, grid, dim3(SUMS_BS3), oin, oclr, us, P, c->geo, rec, c->sp)
+                : launch(c, k_sums<3, false, SUMS_BS3>, grid, dim3(SUMS_BS3), oin, oclr, us, P, c->geo, rec, c->sp);
 }
 
 hipError_t launch_rigid_raster(lbm_ctx *c, int update)

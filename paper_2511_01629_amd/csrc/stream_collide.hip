@@ -340,6 +340,12 @@ __global__ __launch_bounds__(256) void k_fields(const typename S::raw *__restric
         ax = acc_tab[3 * own + 0];
         ay = acc_tab[3 * own + 1];
         az = acc_tab[3 * own + 2];
+        if (sp.frac) { // as in collide_node
+            const T chi = (T)frac_chi(idx, own, sp);
+            ax = chi * ax;
+            ay = chi * ay;
+            az = chi * az;
+        }
     } else if (sp.has_fluid_acc) {
         ax = (T)sp.fluid_acc[0];
         ay = (T)sp.fluid_acc[1];

@@ -50,6 +50,7 @@ class Config(C.Structure):
         ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
         ("max_particles", C.c_int32), ("wall_velocity", C.c_double * 18), ("check_every", C.c_int32),
         ("rigid_beta", C.c_double), ("no_stress_penalty", C.c_int32), ("max_radius", C.c_double),
+        ("fractional_indicator", C.c_int32),
     ]
 
 
@@ -151,6 +152,7 @@ def make_config(cfg, storage=None, device=0, max_particles=0):
     c.rigid_beta = float(cfg.get("rigid_beta", 0.0))
     c.no_stress_penalty = int(bool(cfg.get("no_stress_penalty", 0)))
     c.max_radius = float(cfg.get("max_radius", 0.0))
+    c.fractional_indicator = int(bool(cfg.get("fractional", 0)))
     return c
 
 
