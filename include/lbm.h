@@ -121,8 +121,9 @@ typedef struct {
                                N_i = sum chi, U_i = sum chi u / N_i, omega_i from
                                sum chi r x u and sum chi |r|^2, the tensor in 3D) and the
                                mass M_i = rho_s N_i of Algorithm 1.  Disks and spheres only;
-                               not with rigid_beta > 0; not differentiated by
-                               lbm_backward.  0: the paper's binary indicator.            */
+                               not with rigid_beta > 0.  The weights vary smoothly with the
+                               centres, so lbm_backward also differentiates through them
+                               (lbm_grad_positions).  0: the paper's binary indicator.     */
 } lbm_config;
 
 typedef struct {
@@ -291,10 +292,15 @@ int lbm_load_state(lbm_ctx *ctx, const void *buf);
 
 /* ---- differentiated runs (extension beyond the paper) ----
  * Gradients of a loss of the final particle centres with respect to the
- * solid densities rho_s,i, tau (alpha follows it when alpha <= 0 was given)
- * and |g| (the direction of g fixed), by a hand-written adjoint of the step.
- * The derivative is that of the step map with the indicator sequence frozen
- * (a binary indicator makes the loss piecewise smooth).
+ * solid densities rho_s,i, tau (alpha follows it when alpha <= 0 was given),
+ * |g| (the direction of g fixed) and the initial centres X^0, by a
+ * hand-written adjoint of the step.  With the paper's binary indicator the
+ * derivative is that of the step map with the indicator sequence frozen (a
+ * binary indicator makes the loss piecewise smooth); with the fractional
+ * indicator (lbm_config.fractional_indicator) the node weights are smooth in
+ * the centres and the adjoint carries their derivative, so the gradient in
+ * X^0 is that of the loss itself (while no node changes owner where two
+ * bands meet).
  *
  * lbm_forward_checkpointed: run nsteps >= 1 steps starting right after
  * lbm_set_particles (else ESTATE; K must be 1, rigid_beta 0 and the stress
@@ -316,6 +322,14 @@ int lbm_forward_checkpointed(lbm_ctx *ctx, int64_t nsteps, int32_t every);
  * saved right after lbm_set_particles; lbm_set_params, lbm_set_particles and
  * lbm_load_state discard the run's checkpoints.) */
 int lbm_backward(lbm_ctx *ctx, const double *dL_dX, double *g_rho_s, double *g_tau, double *g_gmag);
+
+/* The gradient with respect to the initial centres X^0 from the last
+ * lbm_backward or lbm_backward_ws: host g_X0 (n x 3 doubles; the unused axis
+ * of a 2D lattice reads 0) out.  With the binary indicator it is the
+ * frozen-indicator derivative (the centres move the bodies but no node
+ * weight).  ESTATE before a backward sweep of the current particle set;
+ * EINVAL for NULL pointers. */
+int lbm_grad_positions(lbm_ctx *ctx, double *g_X0);
 
 /* The same two calls with every device buffer they need taken from
  * caller-owned device memory (e.g. torch tensors) instead of the library's

@@ -24,6 +24,13 @@
 //                   per-workgroup partial of dL/dtau.
 //   k_adj_particles per particle: A_bar^n = sum of a_bar over its nodes, and
 //                   the density and |g| partials through a = b g + A.
+// With the fractional indicator (disks and spheres) the weights chi depend
+// smoothly on the centres X^n, and the adjoint carries that dependence: per
+// node chi_bar gathers the weight's four uses (the acceleration chi (b g + A),
+// the penalization chi alpha, the sums chi u and N = sum chi, and, in step 0,
+// the initial U^{-1} measured on the same nodes), and X_bar^n receives
+// chi_bar dchi/dX summed over the particle's nodes.  The angular sums still
+// carry none: omega only turns a disk or sphere, which moves no node weight.
 // Where the forward step has momentum-sum slots, the lattice adjoint sums
 // a_bar per (particle, slot) record instead of writing it per node, and one
 // kernel per particle (k_adj_fused) closes A_bar^n from the records and then
@@ -72,7 +79,8 @@ __global__ __launch_bounds__(256) void k_adj_lattice(const typename S::raw *__re
                                                       const T *__restrict__ uext, const T *__restrict__ lam_in,
                                                       T *__restrict__ lam_out, double *__restrict__ asol,
                                                       double *__restrict__ tau_part, Geom g, StepParams sp, int gx,
-                                                      unsigned gxm, SlotParams sl)
+                                                      unsigned gxm, SlotParams sl, const double *__restrict__ fpart,
+                                                      int init)
 {
     const int row = div_magic((int)blockIdx.x, gx, gxm), bx = (int)blockIdx.x - row * gx;
     const int x = bx * 256 + (int)threadIdx.x;
@@ -98,9 +106,16 @@ __global__ __launch_bounds__(256) void k_adj_lattice(const typename S::raw *__re
         wall_motion<L, T>(f, y, z, g, sp); // the pre-collision populations, moving walls included
         const uint16_t own = owner[idx];
         const bool solid = own != FLUID;
-        T a[3] = {0, 0, 0};
+        const bool fr = solid && sp.frac;
+        T a[3] = {0, 0, 0}, acc[3] = {0, 0, 0};
+        T chi = 1;
+        double dchi[3] = {0, 0, 0};
         if (solid) {
-            for (int k = 0; k < 3; ++k) a[k] = acc_tab[3 * own + k];
+            for (int k = 0; k < 3; ++k) acc[k] = a[k] = acc_tab[3 * own + k];
+            if (fr) { // the forward's weight, and its derivative in the centre
+                chi = (T)frac_chi(idx, own, sp, dchi);
+                for (int k = 0; k < 3; ++k) a[k] = chi * acc[k];
+            }
         } else if (sp.has_fluid_acc) {
             for (int k = 0; k < 3; ++k) a[k] = (T)sp.fluid_acc[k];
         }
@@ -144,7 +159,7 @@ __global__ __launch_bounds__(256) void k_adj_lattice(const typename S::raw *__re
         T sigb = 0;
         if (pen) {
             // S_q = sigma 4.5 w_q (Pi : c c - tr Pi / 3): Pi_bar and sigma_bar
-            const T sigma = (T)sp.alpha;
+            const T sigma = fr ? (T)((double)chi * sp.alpha) : (T)sp.alpha;
             const T tr3 = (Pxx.v + Pyy.v + Pzz.v) * T(1.0 / 3.0);
             CSum<T> sxx, syy, szz, sxy, sxz, syz;
             T str = 0;
@@ -244,11 +259,30 @@ __global__ __launch_bounds__(256) void k_adj_lattice(const typename S::raw *__re
 #pragma unroll
         for (int k = 0; k < L::D; ++k) ub[k] += pb * T(-L::w[0] / (1.0 - L::w[0])) * u[k];
         if (solid)
-            for (int k = 0; k < L::D; ++k) ub[k] += uext[3 * own + k];
+            for (int k = 0; k < L::D; ++k) ub[k] += chi * uext[3 * own + k];
         if (L::D == 2) ub[2] = 0;
         // u = j + a/2
 #pragma unroll
         for (int k = 0; k < L::D; ++k) ab[k] += T(0.5) * ub[k];
+        // fractional indicator: chi_bar from a = chi acc, sigma = chi alpha,
+        // the sums chi u (U_bar / N . u) and N (N_bar), and in step 0 the
+        // initial U^{-1} = sum chi (j + chi acc / 2) / N (w = its adjoint / N);
+        // then the weight's adjoint share of acc: chi a_bar (+ chi^2 w / 2)
+        double xs[3] = {0, 0, 0}, as[3];
+        for (int k = 0; k < 3; ++k) as[k] = (double)ab[k];
+        if (fr) {
+            const double *fp = fpart + FRAC_STRIDE * own;
+            double cb = fp[0] + (double)sigb * sp.alpha;
+            for (int k = 0; k < L::D; ++k) {
+                cb += (double)ab[k] * (double)acc[k] + (double)uext[3 * own + k] * (double)u[k];
+                as[k] = (double)chi * (double)ab[k];
+                if (init) {
+                    cb += fp[1 + k] * ((double)u[k] + 0.5 * (double)chi * (double)acc[k] - fp[4 + k]);
+                    as[k] += 0.5 * (double)chi * (double)chi * fp[1 + k];
+                }
+            }
+            for (int k = 0; k < L::D; ++k) xs[k] = cb * dchi[k];
+        }
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) {
             if (q > 0) fbar[q] += cdot<L, T>(q, ub[0], ub[1], ub[2]) + sb;
@@ -256,9 +290,11 @@ __global__ __launch_bounds__(256) void k_adj_lattice(const typename S::raw *__re
             lam_out[rp.at(q)] = fbar[q];
         }
         if (solid && asol) {
-            asol[idx] = (double)ab[0];
-            asol[N + idx] = (double)ab[1];
-            if (L::D == 3) asol[2 * N + idx] = (double)ab[2];
+            asol[idx] = as[0];
+            asol[N + idx] = as[1];
+            if (L::D == 3) asol[2 * N + idx] = as[2];
+            if (sp.frac) // uniform
+                for (int k = 0; k < L::D; ++k) asol[(size_t)(L::D + k) * N + idx] = xs[k];
         }
         solid_node = solid;
         own_node = own;
@@ -266,7 +302,7 @@ __global__ __launch_bounds__(256) void k_adj_lattice(const typename S::raw *__re
         // dL/dtau through om = 1/tau, gamma = 1 - 1/(2 tau), and alpha = 1/tau
         const double om2 = sp.omega * sp.omega;
         tb = (double)omb * (-om2) + (double)gamb * (0.5 * om2);
-        if (pen && sp.alpha_tracks_tau) tb += (double)sigb * (-om2);
+        if (pen && sp.alpha_tracks_tau) tb += (double)sigb * (double)chi * (-om2);
     }
     __shared__ double part[256 / WAVE][1];
     double s[1] = {tb};
@@ -291,6 +327,7 @@ struct AdjArrays {
     double *acc_d; // a_i of step n
     float *acc_f;
     double *rho_g, *g_g; // accumulated partials per particle
+    double *fpart, *geo; // fractional indicator only: see AdjArraysHost
 };
 
 __device__ __forceinline__ double particle_volume(int shape, double a, double b)
@@ -382,10 +419,13 @@ __device__ __forceinline__ void adj_pair(const AdjBody &bj, const AdjBody &bi, c
 // X_bar^n, the adjoint of U^{n-1}, the broadcast U_bar^n / N, the acceleration
 // of the step's nodes; drho and dg receive the density and |g| partials of
 // the collision constant and of 1/(2M).  Xbj, Abj, Upbj: X_bar^{n+1}, A_bar^{n+1}
-// and the adjoint of U^n of particle j; Nj, Aj: N and A^n of its record.
+// and the adjoint of U^n of particle j; Nj, Aj: N and A^n of its record rj.
+// With the fractional indicator it also leaves the lattice adjoint of step n
+// the terms of j's chi_bar (A.fpart) and the indicator's centre (A.geo).
 __device__ void adj_rigid_close(int j, const AdjArrays &A, const RigidParams &rp, const Geom &g, const AdjBody &bj,
-                                double Nj, const double *Aj, double rho, double V, const double *Xbj, const double *Abj,
-                                const double *Upbj, double acc[2][3], double unit[2][3], double &drho, double &dg)
+                                const double *rj, double Nj, const double *Aj, double rho, double V, const double *Xbj,
+                                const double *Abj, const double *Upbj, double acc[2][3], double unit[2][3],
+                                double &drho, double &dg)
 {
     const int d = rp.d;
     const int n[3] = {g.nx, g.ny, g.nz};
@@ -418,7 +458,7 @@ __device__ void adj_rigid_close(int j, const AdjArrays &A, const RigidParams &rp
         }
     }
     const double cj = Nj > 0 ? 1.0 / (2.0 * rho * Nj) : 0.0;
-    double corrb_dot_F = 0.0, Cbar = 0.0;
+    double corrb_dot_F = 0.0, Cbar = 0.0, UbU = 0.0;
     for (int k = 0; k < 3; ++k) {
         const double corrb = k < d ? Xbj[k] + 2.0 * Abj[k] : 0.0;
         corrb_dot_F += corrb * 0.5 * Cj * (unit[0][k] + unit[1][k]);
@@ -430,6 +470,17 @@ __device__ void adj_rigid_close(int j, const AdjArrays &A, const RigidParams &rp
         const double ue = Nj > 0 ? Unb / Nj : 0.0;
         A.uext_d[3 * j + k] = ue;
         A.uext_f[3 * j + k] = (float)ue;
+        UbU += Unb * rj[4 + k];
+        if (A.fpart) {
+            A.fpart[FRAC_STRIDE * j + 1 + k] = Nj > 0 ? 0.5 * Xsb / Nj : 0.0;
+            A.fpart[FRAC_STRIDE * j + 4 + k] = rj[14 + k];
+            A.geo[4 * j + k] = rj[k];
+        }
+    }
+    if (A.fpart) {
+        // N enters U^n = sum chi u / N and c = 1/(2 rho N), dc/dN = -c/N
+        A.fpart[FRAC_STRIDE * j] = Nj > 0 ? (-UbU - corrb_dot_F * cj) / Nj : 0.0;
+        A.geo[4 * j + 3] = Rj;
     }
     // c = 1/(2 rho N): dc/drho = -c/rho;  C = (rho - rho_f)|g| V (form 0) or (rho - rho_f)|g| (form 1)
     const double Vc = rp.cform == 1 ? 1.0 : V;
@@ -491,7 +542,7 @@ __global__ __launch_bounds__(256) void k_adj_rigid(AdjArrays A, PartDev P, Rigid
             unit[w][k] = s[6 + w * 3 + k];
         }
     double drho, dg;
-    adj_rigid_close(j, A, rp, g, bj, Nj, Aj, rho, V, Xbj, Abj, Upbj, acc, unit, drho, dg);
+    adj_rigid_close(j, A, rp, g, bj, rj, Nj, Aj, rho, V, Xbj, Abj, Upbj, acc, unit, drho, dg);
     A.rho_g[j] = rg0 + drho;
     A.g_g[j] = gg0 + dg;
 }
@@ -500,9 +551,11 @@ __global__ __launch_bounds__(256) void k_adj_rigid(AdjArrays A, PartDev P, Rigid
 // A_bar^n_i = sum of a_bar over the nodes of particle i (step n indicator);
 // a = b_i g + A_i gives the density and |g| partials.
 
-// This lane's partial sums of a_bar over the owned cells lane, lane + nl, ...
-// of box b, the loads of U cells in flight together.
-template <int D, int U>
+// This lane's partial sums of the C per-node fields of asol (a_bar, then,
+// with the fractional indicator, chi_bar dchi/dX) over the owned cells lane,
+// lane + nl, ... of box b, the loads of U cells in flight together; field m
+// goes to s[m] for m < D and to s[3 + m - D] after.
+template <int D, int C, int U>
 __device__ __forceinline__ void cell_abar(const uint16_t *__restrict__ owner, const double *__restrict__ asol,
                                           const Geom &g, int i, const Box &b, int lane, int nl, double *s)
 {
@@ -510,7 +563,7 @@ __device__ __forceinline__ void cell_abar(const uint16_t *__restrict__ owner, co
     CellWalk w(b.ext[0] > 0 ? b.ext[0] : 1, b.ext[1] > 0 ? b.ext[1] : 1, lane, nl);
     for (int base = lane; base < b.cells; base += U * nl) {
         uint16_t o[U];
-        double v[U][D];
+        double v[U][C];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             int xu, yu, zu;
@@ -518,13 +571,13 @@ __device__ __forceinline__ void cell_abar(const uint16_t *__restrict__ owner, co
             w.next();
             o[u] = owner[node];
 #pragma unroll
-            for (int k = 0; k < D; ++k) v[u][k] = asol[(size_t)k * N + node];
+            for (int k = 0; k < C; ++k) v[u][k] = asol[(size_t)k * N + node];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (base + u * nl >= b.cells || o[u] != (uint16_t)i) continue;
 #pragma unroll
-            for (int k = 0; k < D; ++k) s[k] += v[u][k];
+            for (int k = 0; k < C; ++k) s[k < D ? k : 3 + k - D] += v[u][k];
         }
     }
 }
@@ -554,24 +607,30 @@ __device__ __forceinline__ Box adj_box(const double *r, double R, const Geom &g,
     return make_box(lo, hi);
 }
 
-template <int D>
+// C = D: A_bar^n; C = 2 D (fractional indicator): also X_bar^n += the sum of
+// chi_bar dchi/dX over the particle's nodes.
+template <int D, int C>
 __global__ __launch_bounds__(256) void k_adj_particles(const uint16_t *__restrict__ owner,
                                                         const double *__restrict__ asol, const double *__restrict__ rec,
                                                         PartDev P, RigidParams rp, Geom g, double *__restrict__ Abar_out,
-                                                        double *__restrict__ rho_g, double *__restrict__ g_g)
+                                                        double *__restrict__ rho_g, double *__restrict__ g_g,
+                                                        double *__restrict__ Xbar_n)
 {
-    __shared__ double part[256 / WAVE][3];
+    constexpr int NS = C > D ? 6 : 3;
+    __shared__ double part[256 / WAVE][NS];
     const int i = blockIdx.x;
     const Box b = adj_box(rec + REC_STRIDE * i, P.a[i], g, D);
     const double rho = P.rho_s[i], rg0 = rho_g[i], gg0 = g_g[i];
-    double s[3] = {0, 0, 0};
-    cell_abar<D, UNR>(owner, asol, g, i, b, threadIdx.x, 256, s);
-    block_sum<3, 256>(s, part);
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    cell_abar<D, C, UNR>(owner, asol, g, i, b, threadIdx.x, 256, s);
+    block_sum<NS, 256>(s, part);
     if (threadIdx.x != 0) return;
     double drho, dg;
     adj_particle_close(s, rho, rp, Abar_out + 3 * i, drho, dg);
     rho_g[i] = rg0 + drho;
     g_g[i] = gg0 + dg;
+    if (C > D)
+        for (int k = 0; k < D; ++k) Xbar_n[3 * i + k] += s[3 + k];
 }
 
 // Steps with slots: one workgroup per particle j closes the particle adjoint
@@ -699,7 +758,7 @@ __global__ __launch_bounds__(BS) void k_adj_fused(AdjArrays A, PartDev P, RigidP
     }
     if (lane != 0) return;
     double drho2, dg2;
-    adj_rigid_close(j, A, rp, g, bj, Nj, Aj, rho, V, Xbj, t, Upbj, acc, unit, drho2, dg2);
+    adj_rigid_close(j, A, rp, g, bj, rj, Nj, Aj, rho, V, Xbj, t, Upbj, acc, unit, drho2, dg2);
     A.rho_g[j] = (rg0 + drho) + drho2;
     A.g_g[j] = (gg0 + dg) + dg2;
 }
@@ -735,8 +794,10 @@ __global__ void k_adj_initial(PartDev P, RigidParams rp, const double *__restric
 // ----------------------------------------------------------------- launchers
 hipError_t launch_adj_lattice(lbm_ctx *c, const void *fprev, const uint16_t *owner, const double *uext_d,
                               const float *uext_f, const double *acc_d, const float *acc_f, const void *lam_in,
-                              void *lam_out, double *asol, double *tau_part, const SlotParams &sl)
+                              void *lam_out, double *asol, double *tau_part, const SlotParams &sl,
+                              const double *fpart, const double *geo, int init)
 {
+    if (c->sp.frac && (!fpart || !geo || !asol)) return hipErrorInvalidValue;
     const int gx = (c->geo.nx + 255) / 256;
     const unsigned blocks = (unsigned)gx * (unsigned)(c->geo.ny * c->geo.nz);
     return dispatch(c, [&](auto L, auto S, auto T) {
@@ -746,17 +807,19 @@ hipError_t launch_adj_lattice(lbm_ctx *c, const void *fprev, const uint16_t *own
         const bool dbl = std::is_same<Tt, double>::value;
         const Tt *acc = dbl ? (const Tt *)acc_d : (const Tt *)acc_f;
         const Tt *uext = dbl ? (const Tt *)uext_d : (const Tt *)uext_f;
+        StepParams sp = c->sp;
+        sp.geo = geo; // step n's indicator centres (fractional indicator)
         hipLaunchKernelGGL((k_adj_lattice<Lt, St, Tt>), dim3(blocks), dim3(256), 0, c->stream,
                            (const typename St::raw *)fprev, owner, acc, uext, (const Tt *)lam_in, (Tt *)lam_out, asol,
-                           tau_part, c->geo, c->sp, gx, magic_for(gx), sl);
+                           tau_part, c->geo, sp, gx, magic_for(gx), sl, fpart, init);
         return hipGetLastError();
     });
 }
 
 static AdjArrays adj_arrays(const AdjArraysHost &h)
 {
-    return AdjArrays{h.rec,    h.Xbar,   h.Abar,  h.Upbar,  h.Xbar_out, h.Upbar_out,
-                     h.uext_d, h.uext_f, h.acc_d, h.acc_f, h.rho_g,    h.g_g};
+    return AdjArrays{h.rec,    h.Xbar,   h.Abar,  h.Upbar, h.Xbar_out, h.Upbar_out, h.uext_d,
+                     h.uext_f, h.acc_d,  h.acc_f, h.rho_g, h.g_g,      h.fpart,     h.geo};
 }
 
 hipError_t launch_adj_rigid(lbm_ctx *c, const PartDev &P, const AdjArraysHost &h)
@@ -769,17 +832,26 @@ hipError_t launch_adj_rigid(lbm_ctx *c, const PartDev &P, const AdjArraysHost &h
 }
 
 hipError_t launch_adj_particles(lbm_ctx *c, const PartDev &P, const uint16_t *owner, const double *asol,
-                                const double *rec, double *Abar_out, double *rho_g, double *g_g)
+                                const double *rec, double *Abar_out, double *rho_g, double *g_g, double *Xbar_n)
 {
     if (c->np == 0) return hipSuccess;
     RigidParams rp = c->rp;
     rp.np = c->np;
-    if (c->d == 2)
-        hipLaunchKernelGGL(k_adj_particles<2>, dim3(c->np), dim3(256), 0, c->stream, owner, asol, rec, P, rp, c->geo,
-                           Abar_out, rho_g, g_g);
+    const bool fr = c->sp.frac != 0;
+    if (fr && !Xbar_n) return hipErrorInvalidValue;
+    const dim3 grid(c->np), block(256);
+    if (c->d == 2 && !fr)
+        hipLaunchKernelGGL((k_adj_particles<2, 2>), grid, block, 0, c->stream, owner, asol, rec, P, rp, c->geo, Abar_out,
+                           rho_g, g_g, Xbar_n);
+    else if (c->d == 2)
+        hipLaunchKernelGGL((k_adj_particles<2, 4>), grid, block, 0, c->stream, owner, asol, rec, P, rp, c->geo, Abar_out,
+                           rho_g, g_g, Xbar_n);
+    else if (!fr)
+        hipLaunchKernelGGL((k_adj_particles<3, 3>), grid, block, 0, c->stream, owner, asol, rec, P, rp, c->geo, Abar_out,
+                           rho_g, g_g, Xbar_n);
     else
-        hipLaunchKernelGGL(k_adj_particles<3>, dim3(c->np), dim3(256), 0, c->stream, owner, asol, rec, P, rp, c->geo,
-                           Abar_out, rho_g, g_g);
+        hipLaunchKernelGGL((k_adj_particles<3, 6>), grid, block, 0, c->stream, owner, asol, rec, P, rp, c->geo, Abar_out,
+                           rho_g, g_g, Xbar_n);
     return hipGetLastError();
 }
 

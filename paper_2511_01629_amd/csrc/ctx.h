@@ -19,6 +19,12 @@ namespace lbm {
 // X[3] theta U^n[3] omega^n[3] A^n[3] N U^{n-1}[3] (pad to 20 doubles).
 constexpr int REC_STRIDE = 20;
 
+// Per-particle terms of the adjoint with the fractional indicator, written by
+// the rigid adjoint of step n for the lattice adjoint of the same step:
+// N_bar (the adjoint of N = sum chi through U^n = sum chi u / N and the mass
+// rho_s N), w = (adjoint of U^{n-1}) / N [3], U^{n-1} [3], pad.
+constexpr int FRAC_STRIDE = 8;
+
 // Device arrays of the particle state, structure-of-arrays, FP64.
 struct PartDev {
     double *X, *Xn, *theta, *U, *W, *Uprev, *Wprev, *A; // [cap*3] (theta [cap]); Xn: next centres
@@ -98,6 +104,10 @@ struct AdjArraysHost {
     double *acc_d;
     float *acc_f;
     double *rho_g, *g_g;
+    // fractional indicator only (else NULL): per particle, the adjoint terms
+    // the lattice adjoint adds to chi_bar ([np][FRAC_STRIDE]) and
+    // the centre and radius of step n's indicator ([np][4], StepParams::geo)
+    double *fpart = nullptr, *geo = nullptr;
 };
 
 // Periodic index wrap for an index at most one period out of range.
@@ -216,14 +226,16 @@ hipError_t launch_copy_arrays(void *dst, const void *src, int na, size_t bytes_p
 // adjoint.hip
 hipError_t launch_adj_lattice(lbm_ctx *c, const void *fprev, const uint16_t *owner, const double *uext_d,
                               const float *uext_f, const double *acc_d, const float *acc_f, const void *lam_in,
-                              void *lam_out, double *asol, double *tau_part, const SlotParams &sl);
+                              void *lam_out, double *asol, double *tau_part, const SlotParams &sl,
+                              const double *fpart = nullptr, const double *geo = nullptr, int init = 0);
 // The particle adjoints read only the constants rho_s, a, b, Cc and shape of P.
 hipError_t launch_adj_rigid(lbm_ctx *c, const PartDev &P, const AdjArraysHost &h);
 // particle adjoint of step n from the slots (A_bar^n), then, if rigid, the rigid adjoint of step n - 1
 hipError_t launch_adj_fused(lbm_ctx *c, const PartDev &P, const AdjArraysHost &h, const SlotParams &sl,
                             double *Abar_n, int rigid);
 hipError_t launch_adj_particles(lbm_ctx *c, const PartDev &P, const uint16_t *owner, const double *asol,
-                                const double *rec, double *Abar_out, double *rho_g, double *g_g);
+                                const double *rec, double *Abar_out, double *rho_g, double *g_g,
+                                double *Xbar_n = nullptr);
 hipError_t launch_adj_initial(lbm_ctx *c, const PartDev &P, const double *Upbar, double *rho_g, double *g_g);
 
 

@@ -36,6 +36,7 @@ struct GradState {
     std::vector<int> snapCur;
     std::vector<int64_t> snapStep;
     double *rec = nullptr; // T x np x REC_STRIDE
+    std::vector<double> gX0; // dL/dX^0 of the last backward sweep, [np][3] (empty before one)
     std::vector<void *> owned; // library allocations (none when the caller supplied the memory)
 };
 
@@ -170,6 +171,7 @@ struct BackBufs {
     double *asol = nullptr, *taup = nullptr, *Xbar = nullptr, *Abar = nullptr, *Upbar = nullptr, *rho_g = nullptr,
            *g_g = nullptr, *uext_d = nullptr, *acc_d = nullptr;
     float *uext_f = nullptr, *acc_f = nullptr;
+    double *fpart = nullptr, *geo = nullptr; // fractional indicator only
 };
 
 int carve_backward(Carver &m, int64_t T, int every, size_t fbytes, size_t obytes, BackBufs &b)
@@ -191,7 +193,8 @@ int carve_backward(Carver &m, int64_t T, int every, size_t fbytes, size_t obytes
     if (!rc) rc = m.take(&b.cst, 4 * (size_t)np, true);
     if (!rc) rc = m.take(&b.cshape, (size_t)np, true);
     if (!rc) rc = m.take(&b.lam, 2 * Q * N * lam_elt, true);
-    if (!rc) rc = m.take(&b.asol, slots ? 1 : (size_t)c->d * N, true);
+    // a_bar per node, and with the fractional indicator chi_bar dchi/dX
+    if (!rc) rc = m.take(&b.asol, slots ? 1 : (size_t)c->d * N * (c->sp.frac ? 2 : 1), true);
     if (!rc) rc = m.take(&b.taup, nblocks, true);
     if (!rc) rc = m.take(&b.Xbar, 6 * (size_t)np, true);
     if (!rc) rc = m.take(&b.Abar, 3 * (size_t)np, true);
@@ -202,6 +205,8 @@ int carve_backward(Carver &m, int64_t T, int every, size_t fbytes, size_t obytes
     if (!rc) rc = m.take(&b.acc_d, 3 * (size_t)np, true);
     if (!rc) rc = m.take(&b.uext_f, 3 * (size_t)np, true);
     if (!rc) rc = m.take(&b.acc_f, 3 * (size_t)np, true);
+    if (!rc && c->sp.frac) rc = m.take(&b.fpart, FRAC_STRIDE * (size_t)np, true);
+    if (!rc && c->sp.frac) rc = m.take(&b.geo, 4 * (size_t)np, true);
     return rc;
 }
 
@@ -269,9 +274,8 @@ int forward_impl(lbm_ctx *c, int64_t nsteps, int32_t every, void *ws, size_t ws_
     if (!c->fresh) return c->err = "a differentiated run must start right after lbm_set_particles", LBM_ESTATE;
     if (c->np == 0) return c->err = "no particles", LBM_ESTATE;
     if (c->rp.K != 1) return c->err = "the adjoint of Algorithm 1 is implemented for K = 1", LBM_EINVAL;
-    if (c->sp.beta > 0 || !c->sp.stress || c->sp.frac)
-        return c->err = "the adjoint covers the paper's method (binary indicator, no rigid-velocity forcing, stress "
-                        "penalty on)",
+    if (c->sp.beta > 0 || !c->sp.stress)
+        return c->err = "the adjoint covers the paper's method (no rigid-velocity forcing, stress penalty on)",
                LBM_EINVAL;
     (void)hipSetDevice(c->device);
     free_grad(c);
@@ -443,9 +447,20 @@ int backward_impl(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_ta
     int cx = 0, cu = 0, cl = 0; // which half of the ping-pong adjoint buffers is current
     // arrays of the rigid adjoint of step n (X_bar and the adjoint of U ping-pong)
     auto rigid_arrays = [&](int64_t n) {
-        return AdjArraysHost{G->rec + (size_t)n * np * REC_STRIDE, Xbar + 3 * np * cx, Abar, Upbar + 3 * np * cu,
-                             Xbar + 3 * np * (cx ^ 1), Upbar + 3 * np * (cu ^ 1), uext_d, uext_f, acc_d, acc_f,
-                             rho_g, g_g};
+        return AdjArraysHost{G->rec + (size_t)n * np * REC_STRIDE,
+                             Xbar + 3 * np * cx,
+                             Abar,
+                             Upbar + 3 * np * cu,
+                             Xbar + 3 * np * (cx ^ 1),
+                             Upbar + 3 * np * (cu ^ 1),
+                             uext_d,
+                             uext_f,
+                             acc_d,
+                             acc_f,
+                             rho_g,
+                             g_g,
+                             bb.fpart,
+                             bb.geo};
     };
     if (overlap) rc = recompute(nseg - 1);
     for (int sg = nseg - 1; sg >= 0 && rc == LBM_OK; --sg) {
@@ -488,7 +503,8 @@ int backward_impl(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_ta
                 asl.clear = nullptr;
             }
             if (rc == LBM_OK && launch_adj_lattice(c, fprev, own_n, uext_d, uext_f, acc_d, acc_f, lin, lout,
-                                                   aslots ? nullptr : asol, taup, asl) != hipSuccess)
+                                                   aslots ? nullptr : asol, taup, asl, bb.fpart, bb.geo,
+                                                   n == 0) != hipSuccess)
                 rc = LBM_EDEVICE;
             cl ^= 1;
             if (aslots) {
@@ -501,8 +517,9 @@ int backward_impl(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_ta
                     cx ^= 1;
                     cu ^= 1;
                 }
-            } else if (rc == LBM_OK && launch_adj_particles(c, Pc, own_n, asol, rec_n, Abar, rho_g, g_g) != hipSuccess) {
-                rc = LBM_EDEVICE;
+            } else if (rc == LBM_OK && launch_adj_particles(c, Pc, own_n, asol, rec_n, Abar, rho_g, g_g,
+                                                            Xbar + 3 * np * cx) != hipSuccess) {
+                rc = LBM_EDEVICE; // X_bar^n (the rigid adjoint of step n wrote it) gains the indicator's terms
             }
         }
         if (overlap && rc == LBM_OK) {
@@ -511,10 +528,16 @@ int backward_impl(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_ta
             freed_set[sg & 1] = true;
         }
     }
-    if (rc == LBM_OK && launch_adj_initial(c, Pc, Upbar + 3 * np * cu, rho_g, g_g) != hipSuccess) rc = LBM_EDEVICE;
-    std::vector<double> hr(np), hg(np), ht(nblocks);
+    // the initial U^{-1} (binary indicator; with the fractional one its terms
+    // were taken by the lattice adjoint of step 0)
+    if (rc == LBM_OK && !c->sp.frac && launch_adj_initial(c, Pc, Upbar + 3 * np * cu, rho_g, g_g) != hipSuccess)
+        rc = LBM_EDEVICE;
+    std::vector<double> hr(np), hg(np), ht(nblocks), hx(3 * (size_t)np);
+    G->gX0.clear();
     if (rc == LBM_OK) {
         if (hipMemcpyAsync(hr.data(), rho_g, np * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipMemcpyAsync(hx.data(), Xbar + 3 * np * cx, hx.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream) != hipSuccess ||
             hipMemcpyAsync(hg.data(), g_g, np * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
             hipMemcpyAsync(ht.data(), taup, nblocks * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
             hipStreamSynchronize(c->stream) != hipSuccess)
@@ -528,6 +551,7 @@ int backward_impl(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_ta
             for (int i = 0; i < np; ++i) g_rho_s[i] = hr[i];
         if (g_tau) *g_tau = gt;
         if (g_gmag) *g_gmag = gg;
+        G->gX0 = hx;
     }
     c->f[0] = c->fws[0];
     c->f[1] = c->fws[1];
@@ -546,5 +570,14 @@ extern "C" int lbm_backward(lbm_ctx *c, const double *dL_dX, double *g_rho_s, do
 {
     if (!c || !dL_dX) return LBM_EINVAL;
     return backward_impl(c, dL_dX, g_rho_s, g_tau, g_gmag, nullptr, 0);
+}
+
+extern "C" int lbm_grad_positions(lbm_ctx *c, double *g_X0)
+{
+    if (!c || !g_X0) return LBM_EINVAL;
+    if (!c->grad || c->grad->gX0.empty() || c->grad->np != c->np)
+        return c->err = "no backward sweep to read the position gradient of", LBM_ESTATE;
+    for (size_t i = 0; i < c->grad->gX0.size(); ++i) g_X0[i] = c->grad->gX0[i];
+    return LBM_OK;
 }
 

@@ -309,12 +309,13 @@ __device__ __forceinline__ T feq_q(int q, T p3, T cu, T u15)
 // extension; StepParams::frac): chi = min(1, R + 1/2 - |r|) with r = x - X,
 // X the centre the indicator was built from, x the node taken at its
 // nearest image on periodic axes; FP64, every product and sum rounded on its
-// own (the inclusion test's arithmetic).
-__device__ __forceinline__ double frac_chi(int idx, uint16_t own, const StepParams &sp)
+// own (the inclusion test's arithmetic).  dX (optional) receives the
+// derivative of chi in the centre: r/|r| where chi < 1, else zero.
+__device__ __forceinline__ double frac_chi(int idx, uint16_t own, const StepParams &sp, double *dX = nullptr)
 {
     const int x = idx % sp.n[0], yz = idx / sp.n[0];
     const int c[3] = {x, yz % sp.n[1], yz / sp.n[1]};
-    double r2 = 0.0;
+    double r2 = 0.0, r[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double X = sp.geo[4 * own + k];
@@ -323,10 +324,16 @@ __device__ __forceinline__ double frac_chi(int idx, uint16_t own, const StepPara
             const double half = 0.5 * sp.n[k], dd = (double)v - X;
             v += dd > half ? -sp.n[k] : (dd < -half ? sp.n[k] : 0);
         }
-        const double dk = (k < 2 || sp.n[2] > 1) ? __dsub_rn((double)v, X) : 0.0;
-        r2 = __dadd_rn(r2, __dmul_rn(dk, dk));
+        r[k] = (k < 2 || sp.n[2] > 1) ? __dsub_rn((double)v, X) : 0.0;
+        r2 = __dadd_rn(r2, __dmul_rn(r[k], r[k]));
     }
-    const double v = __dsub_rn(__dadd_rn(sp.geo[4 * own + 3], 0.5), sqrt(r2));
+    const double len = sqrt(r2);
+    const double v = __dsub_rn(__dadd_rn(sp.geo[4 * own + 3], 0.5), len);
+    if (dX) {
+        const bool edge = v < 1.0 && len > 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dX[k] = edge ? r[k] / len : 0.0;
+    }
     return v >= 1.0 ? 1.0 : v;
 }
 

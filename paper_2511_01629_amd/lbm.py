@@ -27,7 +27,8 @@ EXPORTS = ["lbm_workspace_size", "lbm_create", "lbm_destroy", "lbm_set_particles
            "lbm_get_step", "lbm_last_error", "lbm_profile", "lbm_profile_read", "lbm_copy", "lbm_copy_arrays",
            "lbm_forward_checkpointed", "lbm_backward", "lbm_get_fields_device", "lbm_set_params",
            "lbm_state_size", "lbm_save_state", "lbm_load_state", "lbm_step_record_noalloc",
-           "lbm_step_slabs", "lbm_grad_workspace_size", "lbm_forward_checkpointed_ws", "lbm_backward_ws"]
+           "lbm_step_slabs", "lbm_grad_workspace_size", "lbm_forward_checkpointed_ws", "lbm_backward_ws",
+           "lbm_grad_positions"]
 
 
 class LbmUnavailable(RuntimeError):
@@ -109,6 +110,7 @@ def load():
     lib.lbm_grad_workspace_size.argtypes = [P, I64, I32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
     lib.lbm_forward_checkpointed_ws.argtypes = [P, I64, I32, P, C.c_size_t]
     lib.lbm_backward_ws.argtypes = [P, dp, dp, dp, dp, P, C.c_size_t]
+    lib.lbm_grad_positions.argtypes = [P, dp]
     _LIB = lib
     return lib
 
@@ -311,6 +313,12 @@ class Simulation:
             self._check(self.lib.lbm_backward(self.ctx, seed.ctypes.data_as(dp), g_rho.ctypes.data_as(dp),
                                               C.byref(g_tau), C.byref(g_g)))
         return g_rho[: self.np], g_tau.value, g_g.value
+
+    def grad_positions(self):
+        """dL/dX^0 (n x 3) of the last backward sweep."""
+        out = np.zeros((max(self.np, 1), 3))
+        self._check(self.lib.lbm_grad_positions(self.ctx, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out[: self.np]
 
     KERNELS = ("stream_collide", "reduce_clear", "rigid_raster", "raster_after_substeps", "rigid_forcing")
 

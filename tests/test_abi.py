@@ -111,7 +111,7 @@ def test_null_arguments():
                lib.lbm_state_size(None, C.byref(size)), lib.lbm_save_state(None, None),
                lib.lbm_load_state(None, None), lib.lbm_step_slabs(None, 1, 2),
                lib.lbm_grad_workspace_size(None, 1, 1, None, None), lib.lbm_forward_checkpointed_ws(None, 1, 1, None, 0),
-               lib.lbm_backward_ws(None, None, None, None, None, None, 0)):
+               lib.lbm_backward_ws(None, None, None, None, None, None, 0), lib.lbm_grad_positions(None, None)):
         assert rc == lbm.LBM_EINVAL
     assert lib.lbm_workspace_size(C.byref(lbm.make_config(_base())), None) == lbm.LBM_EINVAL
     # lbm_copy: NULL with bytes > 0, misaligned pointers, sizes that are not whole 16-byte words

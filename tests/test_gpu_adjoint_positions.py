@@ -1,0 +1,146 @@
+"""The gradient with respect to the initial centres X^0 (lbm_grad_positions)
+against the oracle's complex-step derivative in each centre coordinate.
+
+* Fractional indicator: the node weights chi = min(1, R + 1/2 - |x - X|) are
+  smooth in the centres, the adjoint differentiates through them (the
+  acceleration, the penalization, the momentum sums and N = sum chi, the
+  mass, and the initial U^{-1}), and the complex step through the oracle
+  carries the same derivative: FP64 storage within 1e-8 relative in 2D (with
+  contacts, x periodic, segments and every frame kept) and 3D; the parameter
+  gradients (rho_s, tau, |g|) of the same runs too.  The oracle's own
+  position derivative is pinned to plain central differences in the CPU
+  suite.
+* Binary indicator: the frozen-indicator derivative (the complex step
+  rasterises from the real parts, so it freezes the indicator too).
+* FP32 storage within a relative bound; the call's errors.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import banner
+from oracle import oracle as O
+from paper_2511_01629_amd import lbm
+from paper_2511_01629_amd.workloads import place
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_gradient(cfg, parts, steps, w, d):
+    """Complex-step derivative of L = sum(w * X_final): each rho_s, tau, |g|,
+    then each coordinate k < d of each initial centre."""
+    npart = len(parts)
+    seeds = []
+    for k in range(npart + 2):
+        s = dict(d_rho_s=[0.0] * npart, d_tau=0.0, d_gmag=0.0)
+        if k < npart:
+            s["d_rho_s"][k] = 1.0
+        elif k == npart:
+            s["d_tau"] = 1.0
+        else:
+            s["d_gmag"] = 1.0
+        seeds.append(s)
+    for i in range(npart):
+        for k in range(d):
+            dX = np.zeros((npart, 3))
+            dX[i, k] = 1.0
+            seeds.append(dict(d_X=dX))
+    out = []
+    for s in seeds:
+        s["h"] = 1e-30
+        o = O.Oracle(cfg, parts, complex_step=s)
+        o.step(steps)
+        out.append(float((w * o.particles(imag=True)["X"]).sum() / s["h"]))
+    return np.array(out)
+
+
+def gpu_gradient(cfg, parts, steps, every, w, d, storage="f64"):
+    sim = lbm.Simulation(cfg, parts, storage=storage)
+    sim.forward_checkpointed(steps, every)
+    g_rho, g_tau, g_g = sim.backward(w)
+    gX = sim.grad_positions()
+    assert gX.shape == (len(parts), 3) and np.all(gX[:, d:] == 0.0)
+    sim.backward(w)
+    assert np.array_equal(sim.grad_positions(), gX)  # deterministic
+    return np.concatenate([g_rho, [g_tau, g_g], gX[:, :d].ravel()])
+
+
+def _check(ga, go, tol, label):
+    scale = np.abs(go).max()
+    err = np.abs(ga - go) / np.maximum(np.abs(go), 1e-3 * scale)
+    print(f"[measured] {label}: max rel err {err.max():.3e}", flush=True)
+    for a, o in zip(ga, go):
+        print(f"   adjoint {a: .10e}  oracle {o: .10e}", flush=True)
+    assert err.max() < tol, err
+
+
+def _disks(fractional):
+    parts = [dict(shape="disk", rho_s=1.5, a=4.0, x=(10.2, 14.7, 0.0)),
+             dict(shape="disk", rho_s=1.2, a=5.0, x=(19.6, 17.1, 0.0)),
+             dict(shape="disk", rho_s=1.4, a=4.5, x=(43.2, 6.3, 0.0))]  # across the periodic x axis
+    cfg = dict(lattice="D2Q9", n=(45, 37, 1), periodic=(1, 0, 0), tau=0.7, g=(0.0, -5e-4, 0.0), eps_p=2.0,
+               eps_w=1.0, delta=1.0, fractional=fractional)
+    return cfg, parts
+
+
+@pytest.mark.parametrize("every", [16, 1])
+def test_position_gradient_fractional_2d_f64(every):
+    banner(f"position gradient fractional 2d f64 every={every}")
+    cfg, parts = _disks(1)
+    w = np.random.default_rng(11).normal(size=(len(parts), 3))
+    w[:, 2] = 0.0
+    go = oracle_gradient(cfg, parts, 40, w, 2)
+    ga = gpu_gradient(cfg, parts, 40, every, w, 2)
+    _check(ga, go, 1e-8, f"fractional 2d every={every}")
+
+
+def test_position_gradient_fractional_3d_f64():
+    banner("position gradient fractional 3d f64")
+    cfg = dict(lattice="D3Q19", n=(17, 15, 19), periodic=(0, 1, 0), tau=0.65, g=(0.0, 0.0, -5e-4), fractional=1)
+    parts = [dict(shape="sphere", rho_s=1.6, a=3.0, x=(7.0, 7.5, 9.0)),
+             dict(shape="sphere", rho_s=1.3, a=3.5, x=(12.2, 8.0, 12.4))]
+    w = np.random.default_rng(12).normal(size=(len(parts), 3))
+    go = oracle_gradient(cfg, parts, 20, w, 3)
+    ga = gpu_gradient(cfg, parts, 20, 7, w, 3)
+    _check(ga, go, 1e-8, "fractional 3d")
+
+
+def test_position_gradient_binary_f64():
+    banner("position gradient binary 2d f64")
+    kinds = [("disk", 5.0, 5.0)] * 3 + [("ellipse", 6.0, 3.0)]
+    parts = place((48, 64), kinds, seed=31, rho_range=(1.3, 1.8), upper_axis=1, gap=0.3, margin=0.3)
+    cfg = dict(lattice="D2Q9", n=(48, 64, 1), periodic=(0, 0, 0), tau=0.65, g=(0.0, -3e-4, 0.0))
+    w = np.random.default_rng(5).normal(size=(len(parts), 3))
+    w[:, 2] = 0.0
+    go = oracle_gradient(cfg, parts, 40, w, 2)
+    ga = gpu_gradient(cfg, parts, 40, 16, w, 2)
+    _check(ga, go, 1e-8, "binary 2d")
+
+
+def test_position_gradient_fractional_f32():
+    """FP32 storage and arithmetic in the lattice (FP64 particle adjoint)."""
+    banner("position gradient fractional 2d f32")
+    cfg, parts = _disks(1)
+    w = np.zeros((len(parts), 3))
+    w[:, 1] = 1.0 / len(parts)
+    go = oracle_gradient(cfg, parts, 40, w, 2)
+    ga = gpu_gradient(cfg, parts, 40, 10, w, 2, storage="f32")
+    _check(ga, go, 1e-3, "fractional 2d f32")
+
+
+def test_grad_positions_errors():
+    banner("position gradient errors")
+    cfg, parts = _disks(1)
+    sim = lbm.Simulation(cfg, parts, storage="f64")
+    with pytest.raises(lbm.LbmError) as e:
+        sim.grad_positions()  # no backward sweep yet
+    assert e.value.code == lbm.LBM_ESTATE
+    sim.forward_checkpointed(3, 2)
+    with pytest.raises(lbm.LbmError) as e:
+        sim.grad_positions()  # a forward run alone
+    assert e.value.code == lbm.LBM_ESTATE
+    sim.backward(np.ones((len(parts), 3)))
+    assert np.all(np.isfinite(sim.grad_positions()))
+    sim.set_particles(parts)  # discards the differentiated run
+    with pytest.raises(lbm.LbmError) as e:
+        sim.grad_positions()
+    assert e.value.code == lbm.LBM_ESTATE

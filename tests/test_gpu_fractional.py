@@ -9,8 +9,8 @@ momentum sums and the mass of Algorithm 1.
   band identical node for node, the weight sums N_i = sum chi to round-off;
   FP32 and FP16 storage within the bounds of the other reduced-storage tests.
 * The weights matter: the same run with the binary indicator ends elsewhere.
-* What the library rejects: ellipses, the rigid-velocity forcing, the
-  differentiated run.
+* What the library rejects: ellipses and the rigid-velocity forcing (the
+  differentiated run is covered by test_gpu_adjoint_positions.py).
 """
 import numpy as np
 import pytest
@@ -103,8 +103,4 @@ def test_fractional_rejections():
     assert e.value.code == lbm.LBM_EINVAL
     with pytest.raises(lbm.LbmError) as e:
         lbm.Simulation(dict(cfg, rigid_beta=0.5), parts, storage="f64")
-    assert e.value.code == lbm.LBM_EINVAL
-    sim = lbm.Simulation(cfg, parts, storage="f32")
-    with pytest.raises(lbm.LbmError) as e:
-        sim.forward_checkpointed(10, 5)
     assert e.value.code == lbm.LBM_EINVAL
