@@ -1,11 +1,13 @@
 """torch.autograd wrapper of a differentiated run.
 
-LbmTrajectory.apply(rho_s, tau, gmag, run) runs `run.steps` steps of the
-penalized LBM on the GPU with checkpoints every `run.every` steps and returns
-the final particle centres (n x 3, float64, on the device of rho_s).  Its
-backward calls the library's
-hand-written adjoint (lbm_backward), so gradients of any loss of the final
-centres flow to the solid densities, tau and |g|, each on its input's device
+LbmTrajectory.apply(rho_s, tau, gmag, run[, X0]) runs `run.steps` steps of
+the penalized LBM on the GPU with checkpoints every `run.every` steps and
+returns the final particle centres (n x 3, float64, on the device of rho_s).
+Its backward calls the library's hand-written adjoint (lbm_backward, and
+lbm_grad_positions for X0), so gradients of any loss of the final centres
+flow to the solid densities, tau, |g| and, if given, the initial centres X0
+(n x 3; with the fractional indicator the gradient of the loss itself, with
+the binary one the frozen-indicator derivative), each on its input's device
 and dtype (a plain number for tau or |g| gets no gradient).  Every step runs in the HIP
 library; this module only marshals tensors.
 
@@ -53,7 +55,7 @@ def _number(x):
 
 class LbmTrajectory(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, rho_s, tau, gmag, run):
+    def forward(ctx, rho_s, tau, gmag, run, X0=None):
         rho = rho_s.detach().cpu().double().numpy()
         g = np.asarray(run.cfg.get("g", (0.0, 0.0, 0.0)), dtype=np.float64)
         g0 = np.linalg.norm(g)
@@ -61,6 +63,9 @@ class LbmTrajectory(torch.autograd.Function):
             raise ValueError("the gravity direction is taken from cfg['g'], which is zero")
         sim = _context(run)
         sim.load_state(run.start)
+        if X0 is not None:  # the run starts from these centres instead of run.particles' ones
+            x0 = X0.detach().cpu().double().numpy().reshape(len(run.particles), 3)
+            sim.set_particles([dict(p, x=tuple(float(v) for v in x0[i])) for i, p in enumerate(run.particles)])
         sim.set_params(rho_s=rho, tau=_number(tau), g=g / g0 * _number(gmag))
         sim.forward_checkpointed(run.steps, run.every, torch_memory=True)
         X = sim.particles()["X"]
@@ -70,7 +75,7 @@ class LbmTrajectory(torch.autograd.Function):
         ctx.generation = run.generation
         # each gradient goes back on its input's device and dtype (inputs may
         # be CUDA tensors or plain numbers)
-        ctx.like = [(t.device, t.dtype) if torch.is_tensor(t) else None for t in (rho_s, tau, gmag)]
+        ctx.like = [(t.device, t.dtype) if torch.is_tensor(t) else None for t in (rho_s, tau, gmag, X0)]
         run.last["sim"] = sim
         out = torch.from_numpy(np.ascontiguousarray(X)).to(torch.float64)
         return out.to(rho_s.device) if torch.is_tensor(rho_s) else out
@@ -80,21 +85,22 @@ class LbmTrajectory(torch.autograd.Function):
         if ctx.generation != ctx.run.generation:
             raise RuntimeError("a later forward of the same Run replaced this run's checkpoints")
         g_rho, g_tau, g_g = ctx.sim.backward(gX.detach().cpu().double().numpy())
+        g_X0 = ctx.sim.grad_positions() if ctx.like[3] is not None and ctx.needs_input_grad[4] else None
         out = []
-        for k, g in enumerate((np.ascontiguousarray(g_rho), g_tau, g_g)):
-            like = ctx.like[k]
+        for k, g in zip((0, 1, 2, 4), (np.ascontiguousarray(g_rho), g_tau, g_g, g_X0)):
+            like = ctx.like[min(k, 3)]
             if not ctx.needs_input_grad[k] or like is None:
                 out.append(None)
             else:
                 out.append(torch.as_tensor(g, dtype=torch.float64).to(device=like[0], dtype=like[1]))
-        return (*out, None)
+        return out[0], out[1], out[2], None, out[3]
 
 
-def final_centres(rho_s, tau, gmag, run):
+def final_centres(rho_s, tau, gmag, run, X0=None):
     """Differentiable final particle centres of `run` (see LbmTrajectory)."""
-    return LbmTrajectory.apply(rho_s, tau, gmag, run)
+    return LbmTrajectory.apply(rho_s, tau, gmag, run, X0)
 
 
-def mean_height_loss(rho_s, tau, gmag, run, axis=1):
+def mean_height_loss(rho_s, tau, gmag, run, axis=1, X0=None):
     """L = mean over particles of the final centre coordinate `axis`."""
-    return final_centres(rho_s, tau, gmag, run)[:, axis].mean()
+    return final_centres(rho_s, tau, gmag, run, X0)[:, axis].mean()
