@@ -63,7 +63,8 @@ def measured_traffic(key):
 
 def _counter_kib(csv_path, kernel_prefix):
     """Mean value (KiB per dispatch) of the counter in a rocprofv3 counter CSV
-    over the dispatches of kernels whose name contains kernel_prefix."""
+    over the dispatches of kernels whose name contains kernel_prefix (a
+    substring: "k_copy(" to tell the one-array copy from k_copy_arrays)."""
     import csv
 
     vals = []
@@ -90,7 +91,7 @@ def record_traffic(root, storages, workload_name, copy_bytes):
         for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
             path = os.path.join(root, f"pmc_{ctr}_{st}", "run_counter_collection.csv")
             k_kib, k_n = _counter_kib(path, "k_stream_collide")
-            c_kib, c_n = _counter_kib(path, "k_copy")
+            c_kib, c_n = _counter_kib(path, "k_copy(")  # the one-array copy, not k_copy_arrays
             scale = copy_bytes / 1024.0 / c_kib
             entry[ctr] = {"kernel_kib": k_kib, "kernel_dispatches": k_n, "copy_kib": c_kib, "copy_dispatches": c_n,
                           "scale": scale, "bytes": k_kib * 1024.0 * scale}
@@ -103,13 +104,15 @@ def record_traffic(root, storages, workload_name, copy_bytes):
     log(f"wrote {TRAFFIC_FILE}")
 
 
-def run_mode(name, storage, steps, warmup, profile=True):
+def run_mode(name, storage, steps, warmup, profile=True, fractional=False):
     import torch
 
     from paper_2511_01629_amd import lbm
     from paper_2511_01629_amd.workloads import workload
 
     cfg, parts, _, info = workload(name)
+    if fractional:  # the same workload with the fractional indicator (disks and spheres only)
+        cfg = dict(cfg, fractional=1)
     sim = lbm.Simulation(cfg, parts, storage=storage, device=0)
     N, Q = sim.N, sim.Q
     sim.step(warmup)
@@ -172,7 +175,7 @@ def pattern_ceiling(narrays, bytes_per_array, reps=20):
     return 2 * narrays * per / (ms * 1e-3) / 1e9
 
 
-def run_adjoint(name, storage, every, max_steps=None):
+def run_adjoint(name, storage, every, max_steps=None, fractional=False):
     """Forward with checkpoints + hand-written adjoint on the differentiated
     workload; fwd+adj MLUPS counts each node-step once.  max_steps shortens the
     run (profiling)."""
@@ -184,6 +187,8 @@ def run_adjoint(name, storage, every, max_steps=None):
     from paper_2511_01629_amd.workloads import workload
 
     cfg, parts, steps, _ = workload(name)
+    if fractional:
+        cfg = dict(cfg, fractional=1)
     if max_steps:
         steps = min(steps, max_steps)
     sim = lbm.Simulation(cfg, parts, storage=storage, device=0)
@@ -332,23 +337,27 @@ def main():
 
     modes = {}
     if not args.no_modes:
-        for name, storage, steps in ((args.workload, "f64", args.steps // 2), (args.workload, "f16", args.steps),
-                                     (args.workload, "bf16", args.steps), ("spheres_256x256x512", "f32", 100)):
-            log(f"mode {name} {storage}")
-            r = run_mode(name, storage, steps, max(10, args.warmup // 4))
-            modes[f"{name}/{storage}"] = {k: r[k] for k in ("mlups", "ms_per_step", "kernel_gbs", "kernel_frac",
-                                                             "kernel_avg_us", "breakdown_us", "pattern_ceiling_gbs",
-                                                             "kernel_frac_of_pattern")}
-            modes[f"{name}/{storage}"]["step_frac"] = r["step_gbs_alg"] / HBM_PEAK_GBS
+        for name, storage, steps, frac in ((args.workload, "f64", args.steps // 2, False),
+                                           (args.workload, "f16", args.steps, False),
+                                           (args.workload, "bf16", args.steps, False),
+                                           ("spheres_256x256x512", "f32", 100, False),
+                                           ("spheres_256x256x512", "f32", 100, True)):
+            key = f"{name}/{storage}" + ("/fractional" if frac else "")
+            log(f"mode {key}")
+            r = run_mode(name, storage, steps, max(10, args.warmup // 4), fractional=frac)
+            modes[key] = {k: r[k] for k in ("mlups", "ms_per_step", "kernel_gbs", "kernel_frac", "kernel_avg_us",
+                                            "breakdown_us", "pattern_ceiling_gbs", "kernel_frac_of_pattern")}
+            modes[key]["step_frac"] = r["step_gbs_alg"] / HBM_PEAK_GBS
             log(f"  {r['mlups']:.0f} MLUPS, fused kernel {r['kernel_gbs']:.0f} GB/s, "
                 f"{r['Q']}-array copy of the same bytes {r['pattern_ceiling_gbs']:.0f} GB/s")
     if not args.no_modes:
         log("forward + adjoint adjoint_512x1024 f32 (5000 steps; checkpoint every 100, and every step kept)")
-        for every in (100, 1):
-            adj = run_adjoint("adjoint_512x1024", "f32", every, args.adj_steps)
-            modes[f"adjoint_512x1024/f32/fwd+adj/every{every}"] = adj
-            log(f"  every {every}: {adj['mlups']:.0f} MLUPS fwd+adj ({adj['ms_forward']:.0f} ms forward, "
-                f"{adj['ms_backward']:.0f} ms backward), {adj['frac']:.3f} of roofline")
+        for every, frac in ((100, False), (1, False), (100, True)):
+            adj = run_adjoint("adjoint_512x1024", "f32", every, args.adj_steps, fractional=frac)
+            modes[f"adjoint_512x1024/f32/fwd+adj/every{every}" + ("/fractional" if frac else "")] = adj
+            log(f"  every {every}{' fractional' if frac else ''}: {adj['mlups']:.0f} MLUPS fwd+adj "
+                f"({adj['ms_forward']:.0f} ms forward, {adj['ms_backward']:.0f} ms backward), "
+                f"{adj['frac']:.3f} of roofline")
     log("copy ceiling")
     ceiling = copy_ceiling()
     log(f"  {ceiling:.0f} GB/s")
