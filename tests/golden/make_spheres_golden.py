@@ -10,7 +10,7 @@ on a fixed seeded sample of nodes after the last step.  The run resumes from
 --partial if interrupted (trajectory.py).
 
 Calls only oracle/; writes tests/golden/spheres_256x256x512.json.
-    python tests/golden/make_spheres_golden.py --partial DIR [--steps 2000]
+    python tests/golden/make_spheres_golden.py --partial DIR [--steps 5000]
 """
 import argparse
 import json
@@ -33,7 +33,7 @@ N_SAMPLE = 4096  # fluid-velocity sample nodes (seeded, fixed)
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--every", type=int, default=100)
     ap.add_argument("--save-every", type=int, default=500)
     ap.add_argument("--partial", required=True, help="directory for the resumable record")

@@ -178,3 +178,35 @@ def test_autograd_initial_centres():
     o = O.Oracle(cfg, [dict(p, x=tuple(moved[i].tolist())) for i, p in enumerate(parts)])
     o.step(40)
     assert abs(loss2.item() - o.particles()["X"][:, 1].mean()) < 1e-10
+
+
+@pytest.mark.parametrize("fractional,steps", [(1, 1), (1, 7), (0, 1), (0, 7)])
+def test_dot_product_random_direction(fractional, steps):
+    """The transpose identity <J v, w> = <v, J^T w> for a seeded direction v
+    over every input at once (rho_s, tau, |g|, the initial centres) and a
+    seeded weighting w of the final centres: J v from one complex-step oracle
+    run in the direction v, J^T w from the GPU adjoint; one step (the three
+    kernels of one backward step) and seven steps, FP64 storage, both
+    indicators."""
+    banner(f"dot product fractional={fractional} steps={steps}")
+    cfg, parts = _disks(fractional)
+    n = len(parts)
+    rng = np.random.default_rng(40 + steps + 10 * fractional)
+    w = rng.normal(size=(n, 3))
+    w[:, 2] = 0.0
+    v_rho, v_tau, v_g = rng.normal(size=n), 0.1 * rng.normal(), 5e-4 * rng.normal()
+    v_X = rng.normal(size=(n, 3))
+    v_X[:, 2] = 0.0
+    h = 1e-30
+    o = O.Oracle(cfg, parts, complex_step=dict(d_rho_s=list(v_rho), d_tau=v_tau, d_gmag=v_g, d_X=v_X, h=h))
+    o.step(steps)
+    jv_w = float((w * o.particles(imag=True)["X"]).sum() / h)
+    sim = lbm.Simulation(cfg, parts, storage="f64")
+    sim.forward_checkpointed(steps, 3)
+    g_rho, g_tau, g_g = sim.backward(w)
+    terms = np.concatenate([v_rho * g_rho, [v_tau * g_tau, v_g * g_g], (v_X * sim.grad_positions()).ravel()])
+    v_jtw = float(terms.sum())
+    err = abs(jv_w - v_jtw) / np.abs(terms).sum()
+    print(f"[measured] dot product fractional={fractional} steps={steps}: <Jv,w> {jv_w:.15e} "
+          f"<v,J^T w> {v_jtw:.15e} rel {err:.2e}", flush=True)
+    assert err < 1e-13

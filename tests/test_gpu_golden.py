@@ -10,7 +10,7 @@ written by the script beside it, which calls only the oracle).
   FP32, FP16 and BF16 storage, the velocity error U, and the ensemble
   statistics (mean and spread of the heights); the horizon where the curve
   reaches 0.1 R is reported (bounds: twice the measured maxima).
-* 3D sphere settling, 256x256x512 D3Q19, 64 spheres, 2000 steps: the same
+* 3D sphere settling, 256x256x512 D3Q19, 64 spheres, the stored steps: the same
   curve and the fluid velocity on sampled nodes at the end, FP32 and FP16.
 * Adjoint workload, 512x1024, 16 disks, 5000 steps, checkpoints every 100:
   the gradient of the mean final height with respect to every rho_s, tau and

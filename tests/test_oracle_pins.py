@@ -751,6 +751,27 @@ def test_floating_disk_walls():
     assert rec[0, 0, 13] == 317  # N of the disk at the integer centre
 
 
+def test_centred_disk_falls_straight_to_a_terminal_velocity():
+    """Settling sanity (sec. 3): a disk centred between two walls falls along
+    the mid-line -- the step commutes with the mirror x -> n_x - 1 - x (halfway
+    walls at -1/2 and n_x - 1/2, a symmetric indicator), so X_x stays on the
+    centre line and omega at zero to round-off -- and, started from rest,
+    accelerates (|U_y| at step 50 below half its final value) to a terminal
+    velocity: over the last two thirds of 3000 steps U_y stays within 5 % of
+    its mean (the wobble left is the binary indicator crossing nodes)."""
+    cfg = dict(lattice="D2Q9", n=(41, 200), tau=0.8, g=(0.0, -2e-5), eps_p=2.0, eps_w=1.0, delta=1.0)
+    o = O.Oracle(cfg, [dict(shape="disk", rho_s=1.5, a=5.0, x=(20.0, 170.0))])
+    rec = o.step(3000, record=True)
+    X, U, W = rec[:, 0, 0:2], rec[:, 0, 4:6], rec[:, 0, 9]
+    Umax = np.abs(U[:, 1]).max()
+    assert np.abs(X[:, 0] - 20.0).max() < 1e-12
+    assert np.abs(U[:, 0]).max() < 1e-12 * Umax and np.abs(W).max() * 5.0 < 1e-12 * Umax
+    late = U[1000:, 1]
+    assert late.mean() < 0 and np.abs(late - late.mean()).max() < 0.05 * abs(late.mean())
+    assert abs(U[50, 1]) < 0.5 * abs(late.mean())
+    assert X[0, 1] - X[-1, 1] > 0.5  # it fell
+
+
 # ---------------------------------------------------------- complex step vs finite differences
 
 def _small_settling():
