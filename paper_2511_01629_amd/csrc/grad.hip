@@ -20,6 +20,8 @@
 #include <algorithm>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "ctx.h"
 
 using namespace lbm;
@@ -41,6 +43,17 @@ struct GradState {
 };
 
 namespace {
+
+// A roctx range over a scope: the phases of a differentiated run (forward,
+// each segment's recomputation and adjoint sweep) as host-side ranges in a
+// rocprofv3 --marker-trace timeline.  The ranges mark when the host queues
+// the work; the kernels they enclose run on the device afterwards.
+struct Range {
+    explicit Range(const char *m) { roctxRangePush(m); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 #define HIPCHK(c, expr)                                                                                                \
     do {                                                                                                               \
@@ -270,6 +283,7 @@ namespace {
 
 int forward_impl(lbm_ctx *c, int64_t nsteps, int32_t every, void *ws, size_t ws_bytes)
 {
+    Range range("lbm forward (checkpointed)");
     if (nsteps < 1 || every < 1) return c->err = "nsteps and every must be >= 1", LBM_EINVAL;
     if (!c->fresh) return c->err = "a differentiated run must start right after lbm_set_particles", LBM_ESTATE;
     if (c->np == 0) return c->err = "no particles", LBM_ESTATE;
@@ -333,6 +347,7 @@ int forward_impl(lbm_ctx *c, int64_t nsteps, int32_t every, void *ws, size_t ws_
 int backward_impl(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_tau, double *g_gmag, void *ws,
                   size_t ws_bytes)
 {
+    Range range("lbm backward");
     GradState *G = c->grad;
     if (!G) return c->err = "no differentiated forward run to go back through", LBM_ESTATE;
     if (G->np != c->np || G->fused != c->fused || G->slot_stride != c->slot_stride)
@@ -424,6 +439,7 @@ int backward_impl(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_ta
     const int64_t span = all ? G->T : G->every;
     // recompute segment sg into its buffer on the side stream
     auto recompute = [&](int sg) -> int {
+        Range rr("lbm backward: recompute segment");
         const int b = sg & 1;
         char *fr = segbuf[b], *ow = segbuf[b] + (size_t)(G->every + 1) * G->fbytes;
         const int64_t s0 = (int64_t)sg * span, s1 = std::min<int64_t>(s0 + span, G->T);
@@ -481,9 +497,11 @@ int backward_impl(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_ta
         } else {
             fr = seg;
             ow = seg + (size_t)(G->every + 1) * G->fbytes;
+            Range rr("lbm backward: recompute segment");
             if ((rc = restore(c, G, sg, fr, ow))) break;
             if ((rc = run_frames(c, G, fr, ow, s1 - s0, nullptr))) break;
         }
+        Range rs("lbm backward: adjoint sweep of a segment");
         for (int64_t n = s1 - 1; n >= s0 && rc == LBM_OK; --n) {
             const char *fprev = fr + (size_t)(n - s0) * G->fbytes;
             const uint16_t *own_n = (const uint16_t *)(ow + (size_t)(n - s0) * G->obytes);
