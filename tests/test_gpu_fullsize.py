@@ -17,14 +17,19 @@ from paper_2511_01629_amd.workloads import workload
 pytestmark = pytest.mark.gpu
 
 
-def _compare(name, storage, steps, tol, nsample=200_000, u_atol=0.0, f_atol=0.0):
+def _compare(name, storage, steps, tol, nsample=200_000, u_atol=0.0, f_atol=0.0, fractional=False):
     cfg, parts, _, _ = workload(name)
-    banner(f"full size {name} {storage} {steps} steps")
+    if fractional:  # the same workload with the fractional indicator
+        cfg = dict(cfg, fractional=1)
+    banner(f"full size {name} {storage} {steps} steps" + (" fractional" if fractional else ""))
     sim, ora = pair(cfg, parts, storage=storage)
     rg = sim.step_record(steps)
     ro = ora.step(steps, record=True)
     # particle records of every step
-    assert np.array_equal(rg[:, :, 13], ro[:, :, 13])  # node counts
+    if fractional:  # sums of the FP64 weights, in another order
+        assert np.abs(rg[:, :, 13] - ro[:, :, 13]).max() <= 1e-13 * ro[:, :, 13].max()
+    else:
+        assert np.array_equal(rg[:, :, 13], ro[:, :, 13])  # node counts
     assert np.abs(rg[:, :, 0:3] - ro[:, :, 0:3]).max() <= tol * np.abs(ro[:, :, 0:3]).max()
     Usc = np.abs(ro[:, :, 4:7]).max()
     if Usc > 0:
@@ -33,7 +38,10 @@ def _compare(name, storage, steps, tol, nsample=200_000, u_atol=0.0, f_atol=0.0)
     _, _, og = sim.fields()
     uo, po, oo = ora.fields()
     Po = ora.particles()
-    check_owner(og, oo, parts, Po, cfg.get("periodic", (0, 0, 0)))
+    if fractional:
+        assert np.array_equal(og, oo)  # the band, node for node
+    else:
+        check_owner(og, oo, parts, Po, cfg.get("periodic", (0, 0, 0)))
     # populations on a sample of nodes and on all solid nodes
     fg, fo = sim.populations(), ora.f()
     flat_g = fg.reshape(-1, fg.shape[-1])
@@ -70,6 +78,16 @@ def test_fullsize_spheres_f32():
 
 def test_fullsize_adjoint_workload_f64():
     _compare("adjoint_512x1024", "f64", 100, 1e-12)
+
+
+def test_fullsize_fractional_spheres_f32():
+    """The fractional indicator at full size: the 64 spheres of 256x256x512
+    (the bench's fractional mode), FP32 storage."""
+    _compare("spheres_256x256x512", "f32", 2, 2e-6, nsample=100_000, fractional=True)
+
+
+def test_fullsize_fractional_adjoint_workload_f64():
+    _compare("adjoint_512x1024", "f64", 100, 1e-12, fractional=True)
 
 
 def test_fullsize_disk_settling_f64():
