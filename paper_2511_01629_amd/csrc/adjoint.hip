@@ -1,8 +1,9 @@
 // adjoint.hip -- hand-written adjoint of one time step (gfx950).
 //
-// The step map is differentiated with the indicator sequence frozen (a
-// binary indicator makes the loss piecewise smooth in the parameters; the
-// derivative is that of the smooth pieces).  With the indicator frozen,
+// With the paper's binary indicator the step map is differentiated with the
+// indicator sequence frozen (a binary indicator makes the loss piecewise
+// smooth in the parameters; the derivative is that of the smooth pieces).
+// With the indicator frozen,
 // omega^n only advances theta, and theta only moves the indicator, so the
 // angular sums carry no derivative: the adjoint of the momentum sums is the
 // broadcast u_bar(x) = U_bar_i / N_i onto the nodes of particle i.
