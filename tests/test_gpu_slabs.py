@@ -2,8 +2,8 @@
 halo rows exchanged by explicit copies, per-slab momentum-sum tables merged
 before Algorithm 1) against the unsplit step: bit for bit, in D2Q9 and D3Q19,
 every storage type, walls or a periodic split axis, moving walls, the fused
-sums and the separate sums kernel, 2 to 5 slabs (the one-GPU part of a
-multi-GPU slab decomposition)."""
+sums and the separate sums kernel, the fractional indicator, 2 to 5 slabs (the
+one-GPU part of a multi-GPU slab decomposition)."""
 import numpy as np
 import pytest
 
@@ -108,6 +108,25 @@ def test_slabs_3d(storage):
              dict(shape="sphere", rho_s=1.3, a=4.5, x=(20.2, 10.0, 13.4))]
     f0 = random_state((24, 20, 32), 19, 1e-3, seed=4).astype(np.float32).astype(np.float64)
     _run_pair(cfg, parts, storage, 20, 2, f0=f0)
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+def test_slabs_fractional_indicator(lattice):
+    """The fractional indicator (weights from the global node coordinates in
+    every slab kernel, sums in the separate kernel): bit for bit."""
+    banner(f"slabs fractional {lattice}")
+    if lattice == "D2Q9":
+        cfg = dict(lattice="D2Q9", n=(45, 37, 1), periodic=(1, 0, 0), tau=0.7, g=(0.0, -5e-4, 0.0), fractional=1)
+        parts = [dict(shape="disk", rho_s=1.5, a=4.0, x=(10.2, 14.7, 0.0)),
+                 dict(shape="disk", rho_s=1.2, a=5.0, x=(19.6, 17.1, 0.0)),
+                 dict(shape="disk", rho_s=1.4, a=4.5, x=(43.2, 6.3, 0.0))]
+        f0 = random_state((1, 37, 45), 9, 1e-3, seed=3)
+        _run_pair(cfg, parts, "f64", 30, 3, f0=f0, fused=False)
+    else:
+        cfg = dict(lattice="D3Q19", n=(17, 15, 19), periodic=(0, 1, 0), tau=0.65, g=(0.0, 0.0, -5e-4), fractional=1)
+        parts = [dict(shape="sphere", rho_s=1.6, a=3.0, x=(7.0, 7.5, 9.0)),
+                 dict(shape="sphere", rho_s=1.3, a=3.5, x=(12.2, 8.0, 12.4))]
+        _run_pair(cfg, parts, "f32", 20, 2, fused=False)
 
 
 def test_slabs_fluid_only_and_rejections():
