@@ -155,8 +155,14 @@ struct Carver {
     }
 };
 
-size_t frame_bytes(const lbm_ctx *c) { return (size_t)c->Q * c->geo.N * storage_bytes(c->cfg.storage); }
-size_t owner_bytes(const lbm_ctx *c) { return (size_t)((c->geo.N + 1) / 2 * 2) * sizeof(uint16_t); }
+// Frame strides, rounded up to the 256 bytes the context's own buffers are
+// aligned to (and sized to): frames sit back to back in the segment and
+// history buffers, and the rasterisation claims indicator entries with 32-bit
+// compare-and-swap, so every indicator frame must start on a 4-byte boundary
+// -- which Q N s bytes of 2-byte populations with Q N odd would break.
+size_t round_frame(size_t v) { return (v + 255) / 256 * 256; }
+size_t frame_bytes(const lbm_ctx *c) { return round_frame((size_t)c->Q * c->geo.N * storage_bytes(c->cfg.storage)); }
+size_t owner_bytes(const lbm_ctx *c) { return round_frame((size_t)((c->geo.N + 1) / 2 * 2) * sizeof(uint16_t)); }
 
 // The forward run's pieces: the particle records, then the frames (every = 1)
 // or the snapshots.

@@ -131,6 +131,27 @@ def test_adjoint_2d_two_byte_storage(storage):
     _check(ga, go, TWO_BYTE_BOUNDS[storage])
 
 
+@pytest.mark.parametrize("every", [10, 1])
+def test_adjoint_two_byte_odd_lattice(every):
+    """FP16 storage on a lattice with Q N odd (45 x 37): Q N 2 bytes per
+    population frame is not a multiple of 4, and the indicator frames that
+    follow the population frames in the checkpoint buffers must still start
+    on the 4-byte boundary the rasterisation's 32-bit compare-and-swap needs
+    (frames are laid out on 256-byte strides).  Segments of 10 and every
+    frame kept; the gradient against the complex-step oracle."""
+    banner(f"adjoint 2d f16 odd lattice every={every}")
+    parts = [dict(shape="disk", rho_s=1.5, a=4.0, x=(10.2, 14.7, 0.0)),
+             dict(shape="disk", rho_s=1.2, a=5.0, x=(19.6, 17.1, 0.0)),
+             dict(shape="disk", rho_s=1.4, a=4.5, x=(43.2, 6.3, 0.0))]
+    cfg = dict(lattice="D2Q9", n=(45, 37, 1), periodic=(1, 0, 0), tau=0.7, g=(0.0, -5e-4, 0.0), eps_p=2.0,
+               eps_w=1.0, delta=1.0)
+    w = np.zeros((len(parts), 3))
+    w[:, 1] = 1.0 / len(parts)
+    go = oracle_gradient(cfg, parts, 40, w)
+    ga = gpu_gradient(cfg, parts, 40, every, w, storage="f16")
+    _check(ga, go, TWO_BYTE_BOUNDS["f16"])  # measured 3.1e-6
+
+
 def test_adjoint_rejects_bad_use():
     banner("adjoint errors")
     parts = [dict(shape="disk", rho_s=1.5, a=5.0, x=(20.0, 30.0, 0.0))]
