@@ -340,8 +340,10 @@ int lbm_grad_positions(lbm_ctx *ctx, double *g_X0);
  * untouched until the run's last lbm_backward_ws, or until the next
  * differentiated run, lbm_set_particles, lbm_set_params or lbm_load_state)
  * and of the backward workspace (segment frames, adjoint populations and
- * partial sums; needed only during the call).  ENOMEM if a workspace is
- * smaller than that; EINVAL for a NULL workspace.  The library frees neither. */
+ * partial sums; needed only during the call).  Each workspace must start on
+ * a 256-byte boundary (torch's allocations do; the indicator frames inside are
+ * updated with 32-bit atomics).  ENOMEM if a workspace is smaller than that;
+ * EINVAL for a NULL or misaligned workspace.  The library frees neither. */
 int lbm_grad_workspace_size(lbm_ctx *ctx, int64_t nsteps, int32_t every, size_t *fwd_bytes, size_t *bwd_bytes);
 int lbm_forward_checkpointed_ws(lbm_ctx *ctx, int64_t nsteps, int32_t every, void *dev_ws, size_t ws_bytes);
 int lbm_backward_ws(lbm_ctx *ctx, const double *dL_dX, double *g_rho_s, double *g_tau, double *g_gmag, void *dev_ws,

@@ -255,6 +255,7 @@ int lbm_forward_checkpointed_ws(lbm_ctx *c, int64_t nsteps, int32_t every, void 
 {
     if (!c) return LBM_EINVAL;
     if (!ws) return c->err = "workspace is NULL", LBM_EINVAL;
+    if ((uintptr_t)ws % 256) return c->err = "workspace is not 256-byte aligned", LBM_EINVAL;
     return forward_impl(c, nsteps, every, ws, ws_bytes);
 }
 
@@ -263,6 +264,7 @@ int lbm_backward_ws(lbm_ctx *c, const double *dL_dX, double *g_rho_s, double *g_
 {
     if (!c || !dL_dX) return LBM_EINVAL;
     if (!ws) return c->err = "workspace is NULL", LBM_EINVAL;
+    if ((uintptr_t)ws % 256) return c->err = "workspace is not 256-byte aligned", LBM_EINVAL;
     return backward_impl(c, dL_dX, g_rho_s, g_tau, g_gmag, ws, ws_bytes);
 }
 

@@ -243,7 +243,7 @@ def test_adjoint_in_caller_memory(every):
     """lbm_forward_checkpointed_ws / lbm_backward_ws with every buffer in torch
     tensors (sized by lbm_grad_workspace_size) give the library-allocated
     run's gradients bit for bit; a workspace one byte short is rejected with
-    ENOMEM."""
+    ENOMEM, one off a 256-byte boundary with EINVAL."""
     banner(f"adjoint in caller memory every={every}")
     kinds = [("disk", 5.0, 5.0)] * 4 + [("ellipse", 6.0, 3.0)] * 2
     parts = place((64, 96), kinds, seed=7, rho_range=(1.2, 1.8), upper_axis=1, gap=0.3, margin=0.3)
@@ -268,3 +268,12 @@ def test_adjoint_in_caller_memory(every):
     small = torch.empty(fb - 1, dtype=torch.uint8, device="cuda")
     rc = sim.lib.lbm_forward_checkpointed_ws(sim.ctx, 40, every, C.c_void_p(small.data_ptr()), fb - 1)
     assert rc == lbm.LBM_ENOMEM
+    # a workspace that does not start on a 256-byte boundary is rejected on
+    # the host, before anything is carved from it
+    big = torch.empty(fb + 512, dtype=torch.uint8, device="cuda")
+    rc = sim.lib.lbm_forward_checkpointed_ws(sim.ctx, 40, every, C.c_void_p(big.data_ptr() + 2), fb)
+    assert rc == lbm.LBM_EINVAL
+    seed = np.ascontiguousarray(w, dtype=np.float64)
+    rc = sim.lib.lbm_backward_ws(sim.ctx, seed.ctypes.data_as(C.POINTER(C.c_double)), None, None, None,
+                                 C.c_void_p(big.data_ptr() + 2), fb)
+    assert rc == lbm.LBM_EINVAL
