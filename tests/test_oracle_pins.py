@@ -953,6 +953,25 @@ def test_fractional_vs_brute_d3q19():
     _compare_with_brute("D3Q19", (5, 5, 6), (0, 1, 0), parts, (0.0, 0.0, -1e-3), 2, 4, fractional=True)
 
 
+def test_fractional_velocity_has_no_node_crossing_jumps():
+    """What the weights are for (reading 24): a disk settling across about
+    six nodes.  With the binary indicator U = sum u / N jumps whenever a node
+    enters or leaves (N changes by one): the largest step-to-step change of
+    U_y over steps 1000-2500 exceeds 2e-3 of its mean.  With the fractional
+    indicator the weights, and so U, move continuously: that change stays
+    below 1e-3, and below a fifth of the binary run's."""
+    jumps = []
+    for frac in (0, 1):
+        cfg = dict(lattice="D2Q9", n=(41, 240), tau=0.8, g=(0.0, -2e-4), eps_p=2.0, eps_w=1.0, delta=1.0,
+                   fractional=frac)
+        o = O.Oracle(cfg, [dict(shape="disk", rho_s=1.5, a=5.0, x=(20.0, 200.0))])
+        rec = o.step(2500, record=True)
+        late = rec[1000:, 0, 5]
+        assert rec[0, 0, 1] - rec[-1, 0, 1] > 5.0  # it crossed several nodes
+        jumps.append(np.abs(np.diff(late)).max() / abs(late.mean()))
+    assert jumps[0] > 2e-3 and jumps[1] < 1e-3 and jumps[1] < 0.2 * jumps[0], jumps
+
+
 def test_fractional_rejects_ellipses():
     with pytest.raises(ValueError):
         O.Oracle(dict(lattice="D2Q9", n=(20, 20), tau=0.8, fractional=1),
