@@ -731,8 +731,8 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
         dth = 0.5 * (W[2] + ps.Wprev[2]);
         for (int k = 0; k < 3; ++k) Ub[k] = 0.5 * (U[k] + ps.Uprev[k]);
         if (lane == 0) {
-            P.N[i] = cnt;
-            P.Nw[i] = (double)cnt;
+            P.N[i] = cnt; // (P.Nw and P.geo serve the unfused steps only: the
+                          // fused step never runs with the fractional indicator)
             if (rec) {
                 double *r = rec + REC_STRIDE * i;
                 for (int k = 0; k < 3; ++k) {
@@ -811,9 +811,7 @@ __global__ __launch_bounds__(BS) void k_rigid_fused(uint16_t *__restrict__ owner
             for (int k = 0; k < 3; ++k) {
                 P.lo[3 * i + k] = s_lo[k];
                 P.hi[3 * i + k] = s_hi[k];
-                P.geo[4 * i + k] = s_X[k];
             }
-            P.geo[4 * i + 3] = Ri;
         }
     }
     __syncthreads();
