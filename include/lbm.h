@@ -144,8 +144,13 @@ typedef struct {
 int lbm_workspace_size(const lbm_config *cfg, size_t *bytes);
 
 /* Validate cfg, allocate (or carve the workspace), and initialise every node
- * to f^eq(p0, u0) (eq. 13), also next to moving walls.  EINVAL: tau <= 1/2,
- * alpha > 1/tau, n <= 0, Q*N >= 2^31, unknown lattice/storage, max_particles
+ * to f^eq(p0, u0) (eq. 13), also next to moving walls.  Size limit: d*N <
+ * 2^31 (node offsets and the [d][N] solid-velocity field are 32-bit); from
+ * Q*N >= 2^31 on, the lattice update addresses populations with 64-bit
+ * offsets (the same arithmetic, so the same bits; setting LBM_WIDE_OFFSETS=1
+ * in the environment before this call selects that kernel on any lattice, a
+ * testing aid).  EINVAL: tau <= 1/2,
+ * alpha > 1/tau, n <= 0, d*N >= 2^31, unknown lattice/storage, max_particles
  * outside [0, 65534], K < 1, non-positive rho_f, eps_p, eps_w or delta, and
  * moving walls outside their limits (on x, on a periodic axis, on two axes,
  * with a normal component or a non-finite value, or with another axis not
@@ -199,7 +204,9 @@ int lbm_step(lbm_ctx *ctx, int64_t nsteps);
  * cross-slab particle sums).  The state afterwards equals lbm_step's bit for
  * bit.  The slab buffers are allocated by the library (about 2 Q s N bytes
  * plus a slot table per extra slab) and kept for later calls.  EINVAL:
- * nslabs outside [1, min(64, rows of the split axis)], K > 1, rigid_beta > 0.
+ * nslabs outside [1, min(64, rows of the split axis)], K > 1, rigid_beta > 0,
+ * or a slab buffer of Q*(rows + 2)*plane >= 2^31 elements (the slab kernel's
+ * offsets are 32-bit: a larger lattice needs more slabs).
  * Waits for the stream and reports the sentinel like lbm_sync. */
 int lbm_step_slabs(lbm_ctx *ctx, int64_t nsteps, int32_t nslabs);
 
@@ -303,8 +310,9 @@ int lbm_load_state(lbm_ctx *ctx, const void *buf);
  * bands meet).
  *
  * lbm_forward_checkpointed: run nsteps >= 1 steps starting right after
- * lbm_set_particles (else ESTATE; K must be 1, rigid_beta 0 and the stress
- * penalty on, else EINVAL), snapshotting the state every `every`
+ * lbm_set_particles (else ESTATE; K must be 1, rigid_beta 0, the stress
+ * penalty on and Q*N < 2^31 -- the lattice adjoint's offsets are 32-bit --
+ * else EINVAL, also from lbm_grad_workspace_size), snapshotting the state every `every`
  * steps and keeping every step's particle record (device memory allocated
  * by the library: about (nsteps/every + 1) population buffers plus small
  * records).  Waits for the stream.

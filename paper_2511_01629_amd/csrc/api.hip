@@ -143,7 +143,9 @@ int validate_cfg(const lbm_config *cfg, std::string &why, int &Q, int &d, int64_
     for (int k = 0; k < 3; ++k)
         if (n[k] <= 0) return why = "lattice sizes must be positive", LBM_EINVAL;
     N = (int64_t)n[0] * n[1] * n[2];
-    if ((int64_t)Q * N >= ((int64_t)1 << 31)) return why = "Q*N must stay below 2^31", LBM_EINVAL;
+    // node indices and the [d][N] solid-velocity field use 32-bit offsets;
+    // population offsets q N + node switch to 64 bits when Q N >= 2^31
+    if ((int64_t)d * N >= ((int64_t)1 << 31)) return why = "d*N must stay below 2^31", LBM_EINVAL;
     if (!(cfg->tau > 0.5)) return why = "tau must exceed 1/2", LBM_EINVAL;
     if (cfg->alpha > 1.0 / cfg->tau * (1.0 + 1e-12)) return why = "alpha must not exceed 1/tau", LBM_EINVAL;
     if (cfg->max_particles < 0 || cfg->max_particles > 65534) return why = "max_particles out of range", LBM_EINVAL;
@@ -400,6 +402,13 @@ int lbm_create(const lbm_config *cfg, lbm_ctx **out)
     c->geo.nz = d == 3 ? cfg->n[2] : 1;
     c->cfg.n[2] = c->geo.nz;
     c->geo.N = N;
+    // 64-bit population offsets in the lattice kernel when Q N >= 2^31;
+    // LBM_WIDE_OFFSETS=1 in the environment selects them on any lattice (a
+    // testing aid: the two kernels give the same bits)
+    {
+        const char *w = getenv("LBM_WIDE_OFFSETS");
+        c->wide = (int64_t)Q * N >= ((int64_t)1 << 31) || (w && w[0] == '1');
+    }
     c->geo.per_x = cfg->periodic[0] != 0;
     c->geo.per_y = cfg->periodic[1] != 0;
     c->geo.per_z = d == 3 && cfg->periodic[2] != 0;

@@ -125,6 +125,7 @@ struct RigidParams {
 struct lbm_ctx {
     lbm_config cfg;
     int Q, d;
+    int wide; // 64-bit population offsets in the lattice kernel (Q N >= 2^31)
     lbm::Geom geo;
     lbm::StepParams sp;
     lbm::RigidParams rp;

@@ -161,6 +161,10 @@ struct Carver {
 // compare-and-swap, so every indicator frame must start on a 4-byte boundary
 // -- which Q N s bytes of 2-byte populations with Q N odd would break.
 size_t round_frame(size_t v) { return (v + 255) / 256 * 256; }
+// The lattice adjoint keeps 32-bit population offsets.
+bool narrow_offsets(const lbm_ctx *c) { return (int64_t)c->Q * c->geo.N < ((int64_t)1 << 31); }
+const char *const WIDE_MSG = "the differentiated run keeps 32-bit population offsets: Q*N must stay below 2^31";
+
 size_t frame_bytes(const lbm_ctx *c) { return round_frame((size_t)c->Q * c->geo.N * storage_bytes(c->cfg.storage)); }
 size_t owner_bytes(const lbm_ctx *c) { return round_frame((size_t)((c->geo.N + 1) / 2 * 2) * sizeof(uint16_t)); }
 
@@ -272,6 +276,7 @@ int lbm_grad_workspace_size(lbm_ctx *c, int64_t nsteps, int32_t every, size_t *f
 {
     if (!c) return LBM_EINVAL;
     if (nsteps < 1 || every < 1) return c->err = "nsteps and every must be >= 1", LBM_EINVAL;
+    if (!narrow_offsets(c)) return c->err = WIDE_MSG, LBM_EINVAL;
     const size_t fb = frame_bytes(c), ob = owner_bytes(c);
     Carver f{c, nullptr, 0, true, nullptr};
     double *rec;
@@ -293,6 +298,7 @@ int forward_impl(lbm_ctx *c, int64_t nsteps, int32_t every, void *ws, size_t ws_
 {
     Range range("lbm forward (checkpointed)");
     if (nsteps < 1 || every < 1) return c->err = "nsteps and every must be >= 1", LBM_EINVAL;
+    if (!narrow_offsets(c)) return c->err = WIDE_MSG, LBM_EINVAL;
     if (!c->fresh) return c->err = "a differentiated run must start right after lbm_set_particles", LBM_ESTATE;
     if (c->np == 0) return c->err = "no particles", LBM_ESTATE;
     if (c->rp.K != 1) return c->err = "the adjoint of Algorithm 1 is implemented for K = 1", LBM_EINVAL;

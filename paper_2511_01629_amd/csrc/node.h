@@ -27,8 +27,11 @@ __device__ __forceinline__ void coords(int idx, const Geom &g, int &x, int &y, i
 // Source offset of population q pulled into node (x,y,z): the neighbour
 // x - c_q (wrapped on periodic axes) or, behind a wall, the opposite
 // population of the node itself.
-template <class L>
-__device__ __forceinline__ int pull_offset(int q, int idx, int x, int y, int z, const Geom &g, int N)
+//
+// I is the type of population offsets q N + node: int while Q N < 2^31 (every
+// lattice the differentiated run and the slab step take), int64_t above.
+template <class L, class I = int>
+__device__ __forceinline__ I pull_offset(int q, int idx, int x, int y, int z, const Geom &g, I N)
 {
     int sx = x - L::cx[q], sy = y - L::cy[q], sz = z - L::cz[q];
     bool wall = false;
@@ -53,7 +56,7 @@ __device__ __forceinline__ int pull_offset(int q, int idx, int x, int y, int z, 
             if (g.per_z) sz -= g.nz; else wall = true;
         }
     }
-    return wall ? L::opp[q] * N + idx : q * N + (sx + g.nx * (sy + g.ny * sz));
+    return wall ? (I)L::opp[q] * N + idx : (I)q * N + (sx + g.nx * (sy + g.ny * sz));
 }
 
 // The same offsets for a node of a row-segment kernel (one workgroup per
@@ -63,10 +66,11 @@ __device__ __forceinline__ int pull_offset(int q, int idx, int x, int y, int z, 
 // rows all exist (`interior`) needs no test per lane: population q of node x
 // comes from (source row base + q N - c_x) + x, a uniform pointer plus the
 // lane's column.  Other segments test x - 1 and x + 1 per lane and select.
-template <class L>
+template <class L, class I = int>
 struct RowPull {
     int rb[3][3]; // [c_y + 1][c_z + 1]: (sy + ny sz) nx of the source row; -1 behind a wall
-    int x, idx, N;
+    int x, idx;
+    I N;
     bool interior;
     const Geom &g;
 
@@ -83,7 +87,7 @@ struct RowPull {
     }
 
     __device__ __forceinline__ RowPull(int x_, int y, int z, int idx_, bool inner_segment, const Geom &g_)
-        : x(x_), idx(idx_), N((int)g_.N), g(g_)
+        : x(x_), idx(idx_), N((I)g_.N), g(g_)
     {
         bool walls = false;
 #pragma unroll
@@ -100,18 +104,18 @@ struct RowPull {
         interior = inner_segment && !walls;
     }
     // offset on any segment
-    __device__ __forceinline__ int at(int q) const
+    __device__ __forceinline__ I at(int q) const
     {
-        return interior ? q * N + rb[L::cy[q] + 1][L::cz[q] + 1] - L::cx[q] + x : offset(q);
+        return interior ? (I)q * N + rb[L::cy[q] + 1][L::cz[q] + 1] - L::cx[q] + x : offset(q);
     }
     // general offset (any segment): the column x - c_x tested per lane
-    __device__ __forceinline__ int offset(int q) const
+    __device__ __forceinline__ I offset(int q) const
     {
         bool wx = false;
         const int s = L::cx[q] != 0 ? src(x, L::cx[q], g.nx, g.per_x, wx) : x;
         const int r = rb[L::cy[q] + 1][L::cz[q] + 1];
-        const int a = q * N + r + s, b = L::opp[q] * N + idx;
-        const int m = -(int)(r >= 0 && !wx); // branch-free select
+        const I a = (I)q * N + r + s, b = (I)L::opp[q] * N + idx;
+        const I m = -(I)(r >= 0 && !wx); // branch-free select
         return (a & m) | (b & ~m);
     }
 };
@@ -210,14 +214,14 @@ __device__ __forceinline__ P *uniform_at(P *base, int i)
 
 // Loads in both branches and the conversion after them, so that no wait for
 // the loads is placed at the branch join.
-template <class L, class S, class T>
-__device__ __forceinline__ void pull_row(const typename S::raw *__restrict__ fin, const RowPull<L> &rp, T *f)
+template <class L, class S, class T, class I = int>
+__device__ __forceinline__ void pull_row(const typename S::raw *__restrict__ fin, const RowPull<L, I> &rp, T *f)
 {
     decltype(ld_reg<S>(fin)) r[L::Q];
     if (rp.interior) { // uniform
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) {
-            const typename S::raw *src = fin + (q * rp.N + rp.rb[L::cy[q] + 1][L::cz[q] + 1] - L::cx[q]);
+            const typename S::raw *src = fin + ((I)q * rp.N + rp.rb[L::cy[q] + 1][L::cz[q] + 1] - L::cx[q]);
             r[q] = ld_reg<S>(uniform_at(src, rp.x));
         }
     } else {
@@ -228,12 +232,12 @@ __device__ __forceinline__ void pull_row(const typename S::raw *__restrict__ fin
     for (int q = 0; q < L::Q; ++q) f[q] = from_reg<S, T>(r[q]);
 }
 
-template <class L, class S, class T>
+template <class L, class S, class T, class I = int>
 __device__ __forceinline__ void pull(const typename S::raw *__restrict__ fin, int idx, int x, int y, int z,
-                                     const Geom &g, int N, T *f)
+                                     const Geom &g, I N, T *f)
 {
 #pragma unroll
-    for (int q = 0; q < L::Q; ++q) f[q] = ld<S, T>(fin + pull_offset<L>(q, idx, x, y, z, g, N));
+    for (int q = 0; q < L::Q; ++q) f[q] = ld<S, T>(fin + pull_offset<L, I>(q, idx, x, y, z, g, N));
 }
 
 // A sum whose terms are known at compile time to be present or not (after

@@ -158,6 +158,10 @@ extern "C" int lbm_step_slabs(lbm_ctx *c, int64_t nsteps, int32_t nslabs)
         return c->err = "nsteps >= 0 and 1 <= nslabs <= min(64, rows of the split axis) required", LBM_EINVAL;
     if (c->sp.beta > 0) return c->err = "the rigid-velocity forcing runs on the unsplit lattice only", LBM_EINVAL;
     if (c->rp.K != 1) return c->err = "slabs are implemented for K = 1", LBM_EINVAL;
+    // the slab kernel keeps 32-bit population offsets within a slab buffer
+    const int64_t max_rows = len / nslabs + (len % nslabs ? 1 : 0);
+    if ((int64_t)c->Q * (max_rows + 2) * plane >= ((int64_t)1 << 31))
+        return c->err = "a slab's Q*(rows+2)*plane must stay below 2^31 (32-bit offsets): use more slabs", LBM_EINVAL;
     (void)hipSetDevice(c->device);
     const size_t e = elt_bytes(c->cfg.storage);
     // slabs: rows split as evenly as possible

@@ -34,7 +34,11 @@ namespace lbm {
 // With slots (the fused-sums step), the solid nodes also add their momentum
 // sums to their particle's slots (keyed wavefront sums, no table lookups) and,
 // on in-place steps, reset their owner entry, which no other lane reads.
-template <class L, class S, class T, int BS>
+//
+// I: the type of the population offsets q N + node -- int, or int64_t on a
+// lattice with Q N >= 2^31 (node indices and the d N velocity field stay
+// 32-bit; the same arithmetic, so the same bits, either way).
+template <class L, class S, class T, int BS, class I = int>
 __global__ __launch_bounds__(BS) void k_stream_collide(const typename S::raw *__restrict__ fin,
                                                          typename S::raw *__restrict__ fout, const uint16_t *owner,
                                                          const T *__restrict__ acc_tab, double *__restrict__ usol,
@@ -56,7 +60,7 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename S::raw *__
         z = row / g.ny;
         y = row - z * g.ny;
     }
-    const int N = (int)g.N;
+    const I N = (I)g.N;
     const int idx = row * g.nx + x;
     uint16_t own = FLUID;
     T ux = 0, uy = 0, uz = 0;
@@ -72,18 +76,18 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename S::raw *__
             // 2-byte storage: the row-uniform offsets (the instruction count
             // limits these kernels; measured 4 % faster in FP16, 8 % in BF16)
             own = owner[idx];
-            const RowPull<L> rp(x, y, z, idx, bx > 0 && bx * BS + BS < g.nx, g);
-            pull_row<L, S, T>(fin, rp, f);
+            const RowPull<L, I> rp(x, y, z, idx, bx > 0 && bx * BS + BS < g.nx, g);
+            pull_row<L, S, T, I>(fin, rp, f);
         } else {
             // 4- and 8-byte storage, bound by HBM: the per-lane offsets measured
             // 3 % (FP32) and 2 % (FP64) faster than the row-uniform ones
-            pull<L, S, T>(fin, idx, x, y, z, g, N, f);
+            pull<L, S, T, I>(fin, idx, x, y, z, g, N, f);
             own = owner[idx];
         }
         if constexpr (decltype(at_wall)::value || !split) wall_motion<L, T>(f, y, z, g, sp);
-        collide_node<L, T>(f, own, acc_tab, sp, flags, usol, idx, N, ux, uy, uz);
+        collide_node<L, T>(f, own, acc_tab, sp, flags, usol, idx, (int)N, ux, uy, uz);
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) st<S, T>(uniform_at(fout + q * N, idx), f[q]);
+        for (int q = 0; q < L::Q; ++q) st<S, T>(uniform_at(fout + (I)q * N, idx), f[q]);
     };
     if (valid) {
         if (split && wall_row(y, z, g, sp)) update(std::true_type{}); // uniform
@@ -333,7 +337,7 @@ __global__ __launch_bounds__(256) void k_fields(const typename S::raw *__restric
     int x, y, z;
     coords<L>(idx, g, x, y, z);
     T f[L::Q];
-    pull<L, S, T>(fin, idx, x, y, z, g, N, f);
+    pull<L, S, T, int64_t>(fin, idx, x, y, z, g, g.N, f); // 64-bit offsets: any lattice size
     wall_motion<L, T>(f, y, z, g, sp);
     T ax = 0, ay = 0, az = 0;
     if (solid) {
@@ -376,7 +380,7 @@ __global__ __launch_bounds__(256) void k_populations(const typename S::raw *__re
     int x, y, z;
     coords<L>(idx, g, x, y, z);
     T f[L::Q];
-    pull<L, S, T>(fin, idx, x, y, z, g, N, f);
+    pull<L, S, T, int64_t>(fin, idx, x, y, z, g, g.N, f); // 64-bit offsets: any lattice size
     wall_motion<L, T>(f, y, z, g, sp);
 #pragma unroll
     for (int q = 0; q < L::Q; ++q)
@@ -484,7 +488,7 @@ __global__ __launch_bounds__(BS) void k_force(const typename S::raw *__restrict_
         if (owner[idx] != (uint16_t)i) continue;
         const int x = wrap(xu, g.nx), y = wrap(yu, g.ny), z = wrap(zu, g.nz);
         T f[L::Q];
-        pull<L, S, T>(fin, idx, x, y, z, g, N, f);
+        pull<L, S, T, int64_t>(fin, idx, x, y, z, g, g.N, f); // 64-bit offsets: any lattice size
         wall_motion<L, T>(f, y, z, g, sp);
         T ux, uy, uz, p;
         moments<L, T>(f, ag[0], ag[1], ag[2], ux, uy, uz, p);
@@ -494,7 +498,7 @@ __global__ __launch_bounds__(BS) void k_force(const typename S::raw *__restrict_
                           L::D == 3 ? ag[2] + beta2 * ((T)vz - uz) : T(0)};
         collide_node<L, T>(f, 0, acc, sp, flags, nullptr, idx, N, ux, uy, uz);
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) st<S, T>(fout + q * N + idx, f[q]);
+        for (int q = 0; q < L::Q; ++q) st<S, T>(fout + (size_t)q * N + idx, f[q]);
         owner[idx] = FLUID;
     }
 }
@@ -535,7 +539,7 @@ hipError_t launch_stream_collide(lbm_ctx *c, const void *fin, void *fout)
                               (const uint16_t *)c->owner, acc, usol, c->flags, c->geo, c->sp, gxw, magic_for(gxw), sl);
             };
             const int64_t blocks1 = (int64_t)((c->geo.nx + 255) / 256) * c->geo.ny;
-            if (blocks1 <= 4096) return multi(std::integral_constant<int, 2>{});
+            if (blocks1 <= 4096 && !c->wide) return multi(std::integral_constant<int, 2>{});
         }
         constexpr bool d2f64 = Lt::D == 2 && sizeof(Tt) == 8;
         constexpr int BS = d2f64 ? 512 : 256;
@@ -545,6 +549,10 @@ hipError_t launch_stream_collide(lbm_ctx *c, const void *fin, void *fout)
         constexpr size_t shm = d2f64 ? (size_t)56 << 10 : 0;
         const int gx = (c->geo.nx + BS - 1) / BS;
         const unsigned blocks = (unsigned)gx * (unsigned)(c->geo.ny * c->geo.nz);
+        if (c->wide) // Q N >= 2^31: 64-bit population offsets
+            return launch_shm(c, k_stream_collide<Lt, St, Tt, BS, int64_t>, dim3(blocks), dim3(BS), shm,
+                              (const typename St::raw *)fin, (typename St::raw *)fout, (const uint16_t *)c->owner,
+                              acc, usol, c->flags, c->geo, c->sp, gx, magic_for(gx), sl);
         return launch_shm(c, k_stream_collide<Lt, St, Tt, BS>, dim3(blocks), dim3(BS), shm,
                           (const typename St::raw *)fin, (typename St::raw *)fout, (const uint16_t *)c->owner, acc,
                           usol, c->flags, c->geo, c->sp, gx, magic_for(gx), sl);

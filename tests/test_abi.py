@@ -45,6 +45,28 @@ def test_invalid_configs_rejected_on_host(bad):
     assert not ctx.value
 
 
+@pytest.mark.parametrize("lattice,n,ok", [
+    ("D2Q9", (16384, 16384, 1), True),    # Q N = 2.42e9: 64-bit population offsets
+    ("D3Q19", (512, 512, 512), True),     # Q N = 2.55e9
+    ("D3Q19", (1024, 1024, 682), True),   # d N = 2.1457e9, just below 2^31
+    ("D3Q19", (1024, 1024, 683), False),  # d N = 2.1489e9: 32-bit node offsets no longer hold
+    ("D2Q9", (32768, 32768, 1), False),   # d N = 2^31
+])
+def test_lattice_size_limit_is_on_node_offsets(lattice, n, ok):
+    """Population offsets q N + node switch to 64 bits when Q N >= 2^31; node
+    offsets (and the d N solid-velocity field) stay 32-bit, so d N < 2^31 is
+    the limit, checked on the host before any device work."""
+    lib = lbm.load()
+    c = lbm.make_config(dict(lattice=lattice, n=n, periodic=(1, 0, 0), tau=0.8, storage="f16"), max_particles=4)
+    size = C.c_size_t()
+    rc = lib.lbm_workspace_size(C.byref(c), C.byref(size))
+    if ok:
+        Q = 9 if lattice == "D2Q9" else 19
+        assert rc == 0 and size.value >= 2 * Q * n[0] * n[1] * n[2] * 2
+    else:
+        assert rc == lbm.LBM_EINVAL
+
+
 def _walls(axis, lo, hi):
     w = [[(0.0, 0.0, 0.0), (0.0, 0.0, 0.0)] for _ in range(3)]
     w[axis] = [lo, hi]
