@@ -88,6 +88,15 @@ def workload(name):
         kinds = [("sphere", 8.0, 8.0)] * 64
         parts = place((256, 256, 512), kinds, 1630, (1.2, 1.8), upper_axis=2)
         return cfg, parts, 5000, dict(desc="64 spheres R=8 settling in a closed 256x256x512 box (D3Q19)")
+    if name == "spheres_64x64x128":
+        # the sphere workload's spheres, fluid and gravity in a box 1/64 of its
+        # volume with 8 spheres (8 times its solid fraction, so that they meet):
+        # the full 5000-step horizon within reach of the FP64 oracle
+        cfg = _cfg(lattice="D3Q19", n=(64, 64, 128), periodic=(0, 0, 0), tau=0.6, g=(0.0, 0.0, -1e-5),
+                   storage="f32")
+        kinds = [("sphere", 8.0, 8.0)] * 8
+        parts = place((64, 64, 128), kinds, 1632, (1.2, 1.8), upper_axis=2)
+        return cfg, parts, 5000, dict(desc="8 spheres R=8 settling in a closed 64x64x128 box (D3Q19)")
     if name == "adjoint_512x1024":
         cfg = _cfg(lattice="D2Q9", n=(512, 1024, 1), periodic=(0, 0, 0), tau=0.7, g=(0.0, -1e-5, 0.0),
                    storage="f32")
@@ -109,7 +118,7 @@ def workload(name):
 
 
 NAMES = ["floating_disk_200x400", "disk_settling_400x1600", "sedimentation_2048x4096", "spheres_256x256x512",
-         "couette_migration_5000x200",
+         "spheres_64x64x128", "couette_migration_5000x200",
          "adjoint_512x1024"]
 
 

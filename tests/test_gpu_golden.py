@@ -10,8 +10,11 @@ written by the script beside it, which calls only the oracle).
   FP32, FP16 and BF16 storage, the velocity error U, and the ensemble
   statistics (mean and spread of the heights); the horizon where the curve
   reaches 0.1 R is reported (bounds: twice the measured maxima).
-* 3D sphere settling, 256x256x512 D3Q19, 64 spheres, the stored steps: the same
-  curve and the fluid velocity on sampled nodes at the end, FP32 and FP16.
+* 3D sphere settling, 256x256x512 D3Q19, 64 spheres, the stored steps (the
+  first 1000 of the workload's 5000: the FP64 oracle takes about 4 s per step
+  of this lattice on 8 cores), and the same spheres, fluid and gravity in a
+  64x64x128 box with 8 spheres over the full 5000 steps: the same curve and
+  the fluid velocity on sampled nodes at the end, FP32 and FP16.
 * Adjoint workload, 512x1024, 16 disks, 5000 steps, checkpoints every 100:
   the gradient of the mean final height with respect to every rho_s, tau and
   |g| against the oracle's complex-step derivative (indicator sequence
@@ -113,21 +116,23 @@ def test_sedimentation_error_growth(storage):
 
 
 # max |X err| (l.u.), max |U err| / max |U|, final max |u err| / max |u|: twice the measured values
-SPHERE_BOUNDS = {"f32": (1.0, 1.0, 1.0), "f16": (1.0, 1.0, 1.0)}
+SPHERE_BOUNDS = {("spheres_256x256x512", "f32"): (1.0, 1.0, 1.0), ("spheres_256x256x512", "f16"): (1.0, 1.0, 1.0),
+                 ("spheres_64x64x128", "f32"): (1.0, 1.0, 1.0), ("spheres_64x64x128", "f16"): (1.0, 1.0, 1.0)}
 
 
+@pytest.mark.parametrize("name", ["spheres_256x256x512", "spheres_64x64x128"])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_spheres_error_growth(storage):
-    path = os.path.join(GOLDEN, "spheres_256x256x512.json")
+def test_spheres_error_growth(name, storage):
+    path = os.path.join(GOLDEN, f"{name}.json")
     if not os.path.exists(path):
-        pytest.skip("the stored FP64 trajectory of the sphere workload is not written yet")
-    gold = _load("spheres_256x256x512")
-    sim, curve, ucurve = _error_growth("spheres_256x256x512", storage, gold, 3)
+        pytest.skip("the stored FP64 trajectory of this sphere workload is not written yet")
+    gold = _load(name)
+    sim, curve, ucurve = _error_growth(name, storage, gold, 3)
     u, _, _ = sim.fields()
     ug = u.reshape(-1, 3)[np.asarray(gold["nodes"])]
     eu = float(np.abs(ug - np.asarray(gold["u_nodes"])).max() / gold["u_max"])
-    print(f"[measured] spheres {storage}: final u err {eu:.3e} rel on {len(gold['nodes'])} nodes", flush=True)
-    bX, bU, bu = SPHERE_BOUNDS[storage]
+    print(f"[measured] {name} {storage}: final u err {eu:.3e} rel on {len(gold['nodes'])} nodes", flush=True)
+    bX, bU, bu = SPHERE_BOUNDS[(name, storage)]
     assert curve.max() <= bX and ucurve.max() <= bU and eu <= bu
 
 
