@@ -115,9 +115,11 @@ def test_sedimentation_error_growth(storage):
     assert curve.max() <= bX and ucurve.max() <= bU
 
 
-# max |X err| (l.u.), max |U err| / max |U|, final max |u err| / max |u|: twice the measured values
+# max |X err| (l.u.), max |U err| / max |U|, final max |u err| / max |u|: twice the values measured on
+# MI355X (64x64x128 over 5000 steps: FP32 5.76e-4 l.u., 1.53e-3, 1.77e-5; FP16 1.22e-3, 2.67e-3, 2.37e-3)
 SPHERE_BOUNDS = {("spheres_256x256x512", "f32"): (1.0, 1.0, 1.0), ("spheres_256x256x512", "f16"): (1.0, 1.0, 1.0),
-                 ("spheres_64x64x128", "f32"): (1.0, 1.0, 1.0), ("spheres_64x64x128", "f16"): (1.0, 1.0, 1.0)}
+                 ("spheres_64x64x128", "f32"): (1.2e-3, 3.1e-3, 3.6e-5),
+                 ("spheres_64x64x128", "f16"): (2.5e-3, 5.4e-3, 4.8e-3)}
 
 
 @pytest.mark.parametrize("name", ["spheres_256x256x512", "spheres_64x64x128"])
