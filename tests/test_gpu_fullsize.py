@@ -104,7 +104,7 @@ LARGEST = {
 @pytest.mark.parametrize("kind,storage", [("D2Q9", "f64"), ("D2Q9", "f16"), ("D3Q19", "f64"), ("D3Q19", "f32"),
                                           ("D3Q19", "f16")])
 def test_largest_lattice_index_range(kind, storage):
-    """The largest lattices the library accepts (Q N just below 2^31: D2Q9
+    """The largest lattices with 32-bit population offsets (Q N just below 2^31: D2Q9
     16384 x 14563, D3Q19 512 x 512 x 431): every population offset q N + node
     sits at the top of the 32-bit index range.  Uniform flow along a periodic
     x between walls (in y, or in z with y periodic) stays independent of the
