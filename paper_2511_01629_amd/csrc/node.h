@@ -198,7 +198,8 @@ __device__ __forceinline__ T from_reg(R r)
 // value and the element offset taken as a 32-bit byte offset (i * sizeof(P)
 // < 2^32 for every lattice the library accepts): the access then takes the
 // scalar-base form of the global instructions, base in scalar registers plus
-// one 32-bit lane offset, instead of a 64-bit address add per access.
+// one 32-bit lane offset, instead of a 64-bit address add per access.  The
+// byte offset i * sizeof(P) must stay below 2^32.
 template <class P>
 __device__ __forceinline__ P *uniform_at(P *base, int i)
 {

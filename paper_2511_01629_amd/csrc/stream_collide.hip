@@ -86,8 +86,15 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const typename S::raw *__
         }
         if constexpr (decltype(at_wall)::value || !split) wall_motion<L, T>(f, y, z, g, sp);
         collide_node<L, T>(f, own, acc_tab, sp, flags, usol, idx, (int)N, ux, uy, uz);
+        // uniform_at forms a 32-bit byte offset (idx * element size), which
+        // the 64-bit-offset lattices (up to 2^30 nodes) can exceed
+        if constexpr (std::is_same<I, int>::value) {
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) st<S, T>(uniform_at(fout + (I)q * N, idx), f[q]);
+            for (int q = 0; q < L::Q; ++q) st<S, T>(uniform_at(fout + q * N, idx), f[q]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < L::Q; ++q) st<S, T>(fout + ((I)q * N + idx), f[q]);
+        }
     };
     if (valid) {
         if (split && wall_row(y, z, g, sp)) update(std::true_type{}); // uniform

@@ -8,7 +8,9 @@ the pull and of the stores are 64-bit once Q N reaches 2^31.  Two checks:
   kernels over runs with bodies in contact, walls and periodic axes, in every
   storage type, D2Q9 and D3Q19, and in FP64 within 1e-12 of the oracle;
 * lattices past the 32-bit range (D2Q9 16384 x 16384, Q N = 2.42e9; D3Q19
-  512^3, Q N = 2.55e9): uniform flow along a periodic x between walls stays
+  512^3, Q N = 2.55e9; at the top of the range D2Q9 24576 x 24576 in FP64,
+  whose store byte offsets pass 2^32, and D3Q19 1022 x 1024 x 682 with d N
+  just below 2^31): uniform flow along a periodic x between walls stays
   independent of the periodic coordinates, so after three steps every sampled
   column equals that of a lattice four nodes wide (one deep) with the same
   wall-normal rows -- against the oracle within 1e-12 in FP64, bit for bit
@@ -72,19 +74,25 @@ def test_wide_offsets_same_bits_on_small_lattices(kind, storage):
 
 
 WIDE = {
-    # lattice: (n, periodic, the small lattice with the same rows, sampled (x, y))
-    "D2Q9": ((16384, 16384, 1), (1, 0, 0), (4, 16384, 1),
+    # name: (lattice, n, periodic, the small lattice with the same rows, sampled (x, y))
+    "D2Q9": ("D2Q9", (16384, 16384, 1), (1, 0, 0), (4, 16384, 1),
              [(0, 0), (1, 0), (3, 16383), (4097, 8191), (16383, 16383), (9000, 12000)]),
-    "D3Q19": ((512, 512, 512), (1, 1, 0), (4, 1, 512), [(0, 0), (3, 511), (257, 130), (511, 0), (511, 511)]),
+    "D3Q19": ("D3Q19", (512, 512, 512), (1, 1, 0), (4, 1, 512), [(0, 0), (3, 511), (257, 130), (511, 0), (511, 511)]),
+    # the top of the range: byte offsets of the FP64 stores past 2^32 (604 M nodes), and
+    # d N just below 2^31 in D3Q19 (714 M nodes, Q N = 1.36e10)
+    "D2Q9-top": ("D2Q9", (24576, 24576, 1), (1, 0, 0), (4, 24576, 1),
+                 [(0, 0), (5, 24575), (12288, 12288), (24575, 24575), (20000, 23000)]),
+    "D3Q19-top": ("D3Q19", (1022, 1024, 682), (1, 1, 0), (4, 1, 682),
+                  [(0, 0), (3, 1023), (511, 700), (1021, 0), (1021, 1023)]),
 }
 
 
-@pytest.mark.parametrize("kind,storage", [("D2Q9", "f32"), ("D2Q9", "f16"), ("D3Q19", "f64"), ("D3Q19", "f32"),
-                                          ("D3Q19", "f16")])
-def test_lattice_past_32bit_population_offsets(kind, storage):
+@pytest.mark.parametrize("case,storage", [("D2Q9", "f32"), ("D2Q9", "f16"), ("D3Q19", "f64"), ("D3Q19", "f32"),
+                                          ("D3Q19", "f16"), ("D2Q9-top", "f64"), ("D3Q19-top", "f16")])
+def test_lattice_past_32bit_population_offsets(case, storage):
     import torch
 
-    n, per, n_small, pts = WIDE[kind]
+    kind, n, per, n_small, pts = WIDE[case]
     Q = 9 if kind == "D2Q9" else 19
     d = 2 if kind == "D2Q9" else 3
     N = n[0] * n[1] * n[2]
