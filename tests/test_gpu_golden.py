@@ -116,8 +116,10 @@ def test_sedimentation_error_growth(storage):
 
 
 # max |X err| (l.u.), max |U err| / max |U|, final max |u err| / max |u|: twice the values measured on
-# MI355X (64x64x128 over 5000 steps: FP32 5.76e-4 l.u., 1.53e-3, 1.77e-5; FP16 1.22e-3, 2.67e-3, 2.37e-3)
-SPHERE_BOUNDS = {("spheres_256x256x512", "f32"): (1.0, 1.0, 1.0), ("spheres_256x256x512", "f16"): (1.0, 1.0, 1.0),
+# MI355X (64x64x128 over 5000 steps: FP32 5.76e-4 l.u., 1.53e-3, 1.77e-5; FP16 1.22e-3, 2.67e-3, 2.37e-3;
+# 256x256x512 over the stored 1000 steps: FP32 6.91e-4, 1.95e-3, 3.12e-5; FP16 4.36e-4, 1.74e-3, 2.63e-3)
+SPHERE_BOUNDS = {("spheres_256x256x512", "f32"): (1.4e-3, 3.9e-3, 6.2e-5),
+                 ("spheres_256x256x512", "f16"): (8.7e-4, 3.5e-3, 5.3e-3),
                  ("spheres_64x64x128", "f32"): (1.2e-3, 3.1e-3, 3.6e-5),
                  ("spheres_64x64x128", "f16"): (2.5e-3, 5.4e-3, 4.8e-3)}
 
